@@ -1,0 +1,196 @@
+"""Benchmark: field updates (Nz x range steps) per second of the batched spectral
+split-step Pade march on one MI355X.
+
+Workload (deep-ocean Munk waveguide): H = 5000 m, c0 = 1500 m/s, f = 50 Hz, Nz = 4096,
+[6/6] Pade, dr = 25 m, Neumann tol 1e-10 (series capped at 48 terms), TL written every
+4 steps, a batch of B such solves with seeded source depths zs ~ U[50, 2000] m.  A bench
+"step" is one range step of the whole batch (every Pade factor and every Neumann term of
+every solve); inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line (contract of the driver) and, with --plain, also times the plain
+one-kernel-per-stage form for comparison.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+PEAK_FP32 = 157.3e12   # MI355X published FP32 vector peak (FLOP/s)
+PEAK_HBM = 8.0e12      # MI355X HBM3E (B/s)
+
+
+def algorithmic_flops(nz, pade_order, terms, steps, outputs):
+    """Algorithmic FP32 work of the range step: every Neumann term costs two DSTs
+    (5 Nz log2 Nz each) plus 8 Nz pointwise; every Pade factor 16 Nz; every output one
+    DST."""
+    tr = 5.0 * nz * math.log2(nz)
+    return terms * 2 * (tr + 8 * nz) + steps * pade_order * 16 * nz + outputs * tr
+
+
+def _oracle_worker(args):
+    nz, nsteps, zs = args
+    import scipy.fft  # noqa: F401
+    from oracle import Plan
+    s = W.munk_deep(nsteps=nsteps, nz=nz, zs=zs)
+    pl = Plan(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol)
+    t = time.perf_counter()
+    pl.march(s.starter(), nsteps, s.profile(), out_every=s.out_every)
+    return s.nz * nsteps, time.perf_counter() - t
+
+
+def cpu_baseline(nz, seconds_target=20.0):
+    """The FP64 oracle on the host cores: one solve per process, a bounded number of steps."""
+    cores = max(1, min(16, os.cpu_count() or 1))
+    # calibrate: one step of one solve
+    upd, dt = _oracle_worker((nz, 1, 1000.0))
+    steps = max(1, int(seconds_target / max(dt, 1e-3)))
+    zs = W.source_depths(cores, 50.0, 2000.0)
+    t = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(nz, steps, float(z)) for z in zs])
+    wall = time.perf_counter() - t
+    total = sum(r[0] for r in res)
+    return {"value": total / wall, "unit": "field updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} solves x {steps} range steps of the Nz={nz} Munk workload "
+                      f"(FP64, one solve per process, {wall:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed range steps")
+    ap.add_argument("--warmup", type=int, default=8, help="untimed range steps")
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--nz", type=int, default=4096)
+    ap.add_argument("--chunk", type=int, default=100, help="range steps per kernel launch")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); every solve of the batch is "
+              "independent, so several GPUs would each run their own batch", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2511_03343_amd import ssp
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+
+    s = W.munk_deep(nz=args.nz)
+    B = args.batch
+    pl = ssp.ssp_plan_create(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol)
+    ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
+    ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_OUT_EVERY, s.out_every)
+    ssp.ssp_set_profile(pl, 0, -1, s.profile()[0])
+
+    zs = W.source_depths(B, 50.0, 2000.0)
+    psi = np.stack([W.gaussian_starter(s.nz, s.depth, s.freq, s.c0, z) for z in zs])
+    d_psi = torch.from_numpy(psi.astype(np.complex64)).to(dev)
+    d_step = torch.zeros(B, dtype=torch.int64, device=dev)
+    d_stats = torch.zeros((B, 48), dtype=torch.uint8, device=dev)
+    nout_chunk = args.chunk // s.out_every + 1
+    d_tl = torch.empty((B, nout_chunk, s.nz), dtype=torch.float32, device=dev)
+    ssp.ssp_to_sine(pl, B, d_psi.data_ptr(), d_psi.data_ptr())
+
+    def run(nsteps, events=None):
+        done = 0
+        while done < nsteps:
+            k = min(args.chunk, nsteps - done)
+            if events is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            ssp.ssp_march_device(pl, B, d_psi.data_ptr(), d_step.data_ptr(), k, d_tl.data_ptr(),
+                                 d_stats.data_ptr())
+            if events is not None:
+                e1.record(stream)
+                events.append((e0, e1, k))
+            done += k
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    terms0 = _terms(d_stats)
+    events = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(args.steps, events)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [a.elapsed_time(b) for a, b, _ in events]
+    stats = _stats(d_stats)
+    terms_per_step = stats["terms"] / max(1, args.chunk if len(events) else 1)
+    st_codes = set(stats["status"])
+    kernel_s = sum(launch_ms) / 1e3
+    updates = B * s.nz * args.steps
+    value = updates / wall
+
+    # algorithmic work of the timed launches, from the per-solve series counts of the last
+    # launch scaled to all launches (every launch here covers the same number of steps)
+    last_k = events[-1][2]
+    flops_last = sum(algorithmic_flops(s.nz, s.pade_order, t, last_k, last_k // s.out_every)
+                     for t in stats["terms_list"])
+    avg_launch_s = launch_ms[-1] / 1e3
+    achieved = flops_last / avg_launch_s
+    del terms0, terms_per_step
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(s.nz, args.cpu_seconds)
+
+    out = {
+        "metric": "field updates (Nz x range steps)/s at TL err<=0.1 dB",
+        "value": value,
+        "unit": "field updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 (FP32; double-float multipliers, FP64 residual and carrier)",
+        "data": "synthetic (seeded Munk profile and Gaussian starters)",
+        "config": {"workload": "deep Munk waveguide, Nz=4096, [6/6] Pade, dr=25 m, 50 Hz, "
+                               "Neumann tol 1e-10 (cap 48), TL every 4 steps",
+                   "batch_solves": B, "nz": s.nz, "range_steps_timed": args.steps,
+                   "steps_per_launch": args.chunk},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                     "kernel": "k_march<8192,1024>",
+                     "avg_launch_ms": sum(launch_ms) / len(launch_ms),
+                     "neumann_terms_per_solve_step": stats["terms"] / B / last_k},
+        "kernel_time_s": kernel_s,
+        "status": sorted(st_codes),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ssp.ssp_plan_destroy(pl)
+
+
+def _stats(d_stats):
+    raw = d_stats.cpu().numpy()
+    terms = raw[:, 16:24].copy().view(np.int64).ravel()
+    status = raw[:, 40:44].copy().view(np.int32).ravel()
+    return {"terms": int(terms.sum()), "terms_list": [int(t) for t in terms],
+            "status": [int(x) for x in status]}
+
+
+def _terms(d_stats):
+    return _stats(d_stats)["terms"]
+
+
+if __name__ == "__main__":
+    main()

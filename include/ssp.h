@@ -1,0 +1,178 @@
+/*
+ * ssp.h - C ABI of the MI355X spectral split-step Pade (SSSP) range-march library.
+ *
+ * The library marches the one-way (parabolic) wave equation in range with the spectral
+ * split-step Pade method of Walsken, Ehrhardt and Petrov (arXiv 2511.03343):
+ *   Sec. 2    u(r + dr) ~ e^{i k0 dr} R(X) u(r), R the [p/p] Pade approximant of
+ *             exp(i sigma (sqrt(1+x) - 1)), sigma = k0 dr, X = (d_z^2 + k^2 - k0^2)/k0^2.
+ *   Sec. 3    each Pade term (1 + b_j X)^{-1} is a diagonal solve in the sine basis when
+ *             the sound speed is constant, and a Neumann series (eq. neumannseries) of
+ *             transform -> diagonal scale -> inverse transform -> multiply by
+ *             v(z) = (c0/c(z))^2 - 1 otherwise.
+ *   Sec. 3.1  homogeneous Dirichlet boundaries at z = 0 and z = H: the transform is the
+ *             orthonormal DST-I on the interior grid z_n = n H/(Nz+1), n = 1..Nz.
+ *   Alg. 1    the range march: for every step, every Pade term, then the carrier.
+ *
+ * All entry points are extern "C", return an ssp_status and never throw.  Pointers are
+ * host pointers unless the name says "device".  The caller owns every array it passes;
+ * the library copies host arrays in and out before returning.  A plan owns its device
+ * memory (field, tables, profile, staging) and releases it in ssp_plan_destroy.  A plan is
+ * not thread-safe; distinct plans may be used from different threads.  Every call runs on
+ * the plan's HIP stream (default: the null stream; see SSP_OPT_STREAM) and the host calls
+ * (ssp_march, ssp_get_field, ...) synchronise that stream before returning.
+ *
+ * Numerics: the field is complex FP32 (interleaved re, im), kept on the device in the sine
+ * basis between calls.  Pade coefficients are computed on the host in extended
+ * precision; sine-space multipliers and FFT twiddles are applied as double-float
+ * (hi + lo FP32) products; the Neumann residual is accumulated in FP64; the carrier
+ * phase exp(i k0 r) is formed in FP64.
+ */
+#ifndef SSP_H
+#define SSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SSP_OK = 0,
+    SSP_W_NOT_CONVERGED = 1, /* march finished; some Neumann series stopped at
+                                neumann_max with residual > tol (see ssp_stats) */
+    SSP_E_INVAL = -1,        /* invalid argument (size, NULL, non-finite or <= 0 speed) */
+    SSP_E_NOMEM = -2,        /* device or host allocation failed */
+    SSP_E_DEVICE = -3,       /* HIP runtime error (message in ssp_last_error) */
+    SSP_E_DIVERGED = -4,     /* a Neumann series grew or a value became non-finite; the
+                                field is left at the last good step (ssp_stats.steps_done) */
+    SSP_E_UNSTABLE = -5,     /* plan rejected: max_l |e^{i sigma} R(x_l)| > 1 + 1e-6 */
+    SSP_E_STATE = -6,        /* call out of order (e.g. march before a field was set) */
+    SSP_E_UNIMPL = -7        /* size or option outside what this build supports */
+} ssp_status;
+
+typedef struct ssp_plan ssp_plan; /* opaque, library-owned */
+
+/* Options for ssp_plan_set_option. */
+enum {
+    SSP_OPT_ROTATION = 1,  /* branch-cut rotation angle alpha (rad) of the Pade
+                              approximant; 0 (default) = standard approximant.  Changing
+                              it recomputes the coefficients and the stability check. */
+    SSP_OPT_OUT_EVERY = 2, /* write an output every k-th step (default 1) */
+    SSP_OPT_STREAM = 3,    /* value = (double)(uintptr_t)hipStream_t; 0 = null stream.
+                              Use ssp_plan_set_stream to pass a pointer exactly. */
+    SSP_OPT_ENGINE = 4     /* 0 = fused persistent kernel (default); 1 = plain form: one
+                              kernel per transform / pointwise step, host-driven loop */
+};
+
+/* Analytic range-dependent environment evaluated on the device every step at the step's
+ * mid-range r = (n - 1/2) dr:  c(r, z) = c_munk(z) + dc(r, z), with the Munk profile of
+ * Sec. 4.1 eq. (Munk), c_munk = munk_c1 (1 + munk_eps (eta + e^{-eta} - 1)),
+ * eta = 2 (z - munk_z1)/munk_z1, and a Gaussian eddy
+ * dc = -eddy_amp exp(-((r - eddy_r0)/eddy_rr)^2 - ((z - eddy_z0)/eddy_rz)^2). */
+typedef struct {
+    double munk_c1, munk_eps, munk_z1;                   /* 1500, 0.00737, 1300 */
+    double eddy_amp, eddy_r0, eddy_rr, eddy_z0, eddy_rz; /* eddy_amp = 0: no eddy */
+} ssp_env;
+
+/* Per-march statistics (filled by ssp_march / ssp_march_batch / ssp_read_stats). */
+typedef struct {
+    int64_t steps_done;       /* range steps completed by this call */
+    int64_t step_index;       /* global step counter of the plan after the call */
+    int64_t neumann_terms;    /* sum over steps and Pade factors of the terms m >= 1 */
+    int32_t neumann_max_used; /* largest m reached by one series */
+    int32_t not_converged;    /* number of (step, factor) series that hit neumann_max */
+    double max_residual;      /* largest final ||term_m|| / ||w^(m)|| */
+    int32_t status;           /* ssp_status of this solve */
+    int32_t pad_;
+} ssp_stats;
+
+/* Create a plan (Alg. 1 "compute d_j and b_j"; Sec. 2 Pade form; Sec. 3.1 grid).
+ *   Nz           interior depth points, 2 <= Nz <= ssp_max_nz();  dz = H/(Nz+1)
+ *   H            waveguide depth (m) > 0;  f  frequency (Hz) > 0
+ *   c0           reference sound speed (m/s) > 0, k0 = 2 pi f / c0
+ *   dr           range step (m) > 0
+ *   pade_order   p in [1, 12]
+ *   neumann_max  largest Neumann index M >= 0 (0: the m = 0 term only, Sec. 4.1 "M = 0")
+ *   tol          > 0; a series stops at the first m >= 1 with ||term_m|| <= tol ||w^(m)||
+ * The environment defaults to c = c0 (v = 0) until ssp_set_profile* is called.
+ * Errors: SSP_E_INVAL, SSP_E_UNSTABLE, SSP_E_UNIMPL (Nz too large), SSP_E_NOMEM,
+ * SSP_E_DEVICE.  *out is set to NULL on error. */
+ssp_status ssp_plan_create(int Nz, double H, double f, double c0, double dr, int pade_order,
+                           int neumann_max, double tol, ssp_plan **out);
+void ssp_plan_destroy(ssp_plan *plan); /* NULL-safe; releases device memory */
+ssp_status ssp_plan_set_option(ssp_plan *plan, int key, double value);
+ssp_status ssp_plan_set_stream(ssp_plan *plan, void *hip_stream);
+
+/* Plan facts: sigma, k0, the Pade coefficients in product form (b_j and the combine
+ * weights g_j = a_j/b_j, complex as re, im pairs, in application order), the constant C,
+ * and the sum form (d0, d_j).  Arrays hold 2*p doubles; any pointer may be NULL. */
+ssp_status ssp_plan_info(const ssp_plan *plan, double *sigma, double *k0, double *b,
+                         double *g, double *C, double *d0, double *d);
+int ssp_max_nz(void);
+
+/* Host-only Pade coefficients (Sec. 2; Alg. 1 first step) for sigma = k0 dr, order p and
+ * rotation alpha, in the library's factor order: b[2p], g[2p] (product-form weights
+ * g_j = a_j/b_j), C[2], d0[2], d[2p] as (re, im) pairs; any output may be NULL.  Touches no
+ * device.  Errors: SSP_E_INVAL (p outside [1, 12], non-finite sigma or alpha). */
+ssp_status ssp_pade_coefficients(double sigma, int pade_order, double alpha, double *b,
+                                 double *g, double *C, double *d0, double *d);
+
+/* Sound speed per range step (Sec. 2: k = omega / c(r, z)).  c is [nsteps][Nz] m/s,
+ * row i is used for global step step0 + 1 + i (steps count from 1).  nsteps = -1 gives one
+ * row used for every step >= step0 + 1 (range-independent).  Values must be finite
+ * and > 0 (SSP_E_INVAL otherwise).  The rows are converted to v = (c0/c)^2 - 1 in FP64
+ * and stored on the device in FP32.  A later call replaces the profile. */
+ssp_status ssp_set_profile(ssp_plan *plan, int step0, int nsteps, const double *c);
+/* Analytic profile evaluated on the device each step (replaces any table). */
+ssp_status ssp_set_profile_analytic(ssp_plan *plan, const ssp_env *env);
+
+/* Starter: psi0 [Nz] complex (re, im doubles), physical space.  Resets the step
+ * counter to 0 and r to 0.  The field is transformed to the sine basis on the device. */
+ssp_status ssp_set_field(ssp_plan *plan, const double *psi0);
+/* Current field in physical space including the carrier exp(i k0 r): [Nz] complex. */
+ssp_status ssp_get_field(const ssp_plan *plan, double *psi);
+
+/* March nsteps range steps from the resident field (Alg. 1).  psi0 may be NULL to
+ * continue (resume) or [Nz] complex to (re)start.  Outputs at steps with
+ * step_index % out_every == 0:  field_out [nout][Nz] complex (re, im doubles, carrier
+ * included) and/or tl_out [nout][Nz] float, TL = -20 log10(|u|/sqrt(r)) dB re 1 m; either
+ * may be NULL.  nout = number of output steps in this call (see ssp_count_outputs).
+ * Returns SSP_OK, SSP_W_NOT_CONVERGED or SSP_E_DIVERGED (plus argument errors). */
+ssp_status ssp_march(ssp_plan *plan, const double *psi0, int nsteps, double *field_out,
+                     float *tl_out, ssp_stats *stats);
+int ssp_count_outputs(const ssp_plan *plan, int nsteps);
+
+/* Batched march: n plans advanced by nsteps in one persistent launch per FFT-size class.
+ * The plans must differ only in their starter, profile and (for different FFT sizes)
+ * grid; each plan keeps its own field, counter and statistics.  Outputs are written per
+ * plan as in ssp_march (arrays of n pointers, entries may be NULL); stats [n] or NULL.
+ * Returns the worst status over the plans. */
+ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *const *field_out,
+                           float *const *tl_out, ssp_stats *stats);
+
+/* Device-resident batch for serving and benchmarking (no host copies in the hot path):
+ * B solves of one plan's grid and coefficients.  d_psi is a device array
+ * [B][Nz] complex64 holding each solve's field in the library's sine-basis
+ * representation (see ssp_to_sine / ssp_from_sine); d_step is a device int64 [B] of global
+ * step counters; d_tl (may be NULL) a device float [B][nout][Nz]; d_stats a device array of
+ * B ssp_stats (may be NULL).  The call is asynchronous on the plan's stream. */
+ssp_status ssp_march_device(ssp_plan *plan, int B, void *d_psi, void *d_step, int nsteps,
+                            void *d_tl, void *d_stats);
+/* physical complex64 [B][Nz] (device) -> sine-basis representation (device), in place ok */
+ssp_status ssp_to_sine(ssp_plan *plan, int B, const void *d_phys, void *d_sine);
+/* sine-basis representation -> physical field with carrier at the given step counters */
+ssp_status ssp_from_sine(ssp_plan *plan, int B, const void *d_sine, const void *d_step,
+                         void *d_phys);
+
+/* Stand-alone batched orthonormal DST-I (Sec. 3.1) of B complex64 vectors of length Nz,
+ * device in/out (may alias), asynchronous on the plan's stream. */
+ssp_status ssp_dst_device(ssp_plan *plan, int B, const void *d_in, void *d_out);
+
+const char *ssp_status_string(ssp_status s);
+const char *ssp_last_error(void); /* thread-local detail of the last error */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSP_H */

@@ -1,0 +1,70 @@
+// ssp_device.h - interface between the C ABI (host) and the HIP kernels of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ssp {
+
+// Per-solve statistics as kept on the device (layout identical to ssp_stats).
+struct DevStats {
+    int64_t steps_done;
+    int64_t step_index;
+    int64_t neumann_terms;
+    int32_t neumann_max_used;
+    int32_t not_converged;
+    double max_residual;
+    int32_t status;
+    int32_t pad_;
+};
+
+enum ProfileMode : int { PROF_TABLE_FIXED = 0, PROF_TABLE_STEPS = 1, PROF_ANALYTIC = 2 };
+
+// Everything one workgroup needs to march one solve.  Table pointers are shared by all
+// solves of a plan; state pointers are per solve.
+struct SolveDesc {
+    const float2 *k1, *k2;      // [P] chirp-window spectra
+    const float4 *tw;           // [P] double-float twiddles exp(-2 pi i e/P)
+    const float2 *dmod, *post;  // [N]
+    const float2 *pre;          // [N] conj chirp (physical -> chirp-z input)
+    const float4 *s, *bmul;     // [p][N] double-float
+    const float4 *alpha, *beta; // [p] double-float
+    int N, P, p, nmax;
+    double tol2;                // tol^2 (squared-norm test)
+    double sigma;               // k0 dr (carrier phase per step)
+    double dz, dr, c0;
+    int prof_mode, v_rows;
+    long long v_step0;
+    const float *v;             // [v_rows][N] FP32 potential (table modes)
+    double env[8];              // analytic environment (ssp_env order)
+    float2 *field;              // [N] sine-basis state (modulated representation)
+    float2 *work;               // [N] scratch state between Pade factors
+    long long *step;            // global step counter
+    DevStats *stats;
+    float *tl_out;              // [nout][N] or null
+    float2 *fld_out;            // [nout][N] or null (complex64, carrier included)
+    int out_every;
+    int nout;                   // output rows available in tl_out / fld_out
+    long long out_base;         // first output step of the current call
+};
+
+// Launch the fused persistent march: one workgroup per descriptor, all with the same FFT
+// length P.  Returns hipSuccess or the launch error.
+hipError_t launch_march(int P, const SolveDesc *d_descs, int nsolves, int nsteps,
+                        hipStream_t stream);
+
+// Batched transforms over B vectors of a plan's grid (tables from desc, one desc on the
+// device shared by the whole batch).
+//   mode 0: orthonormal DST-I (in -> out)
+//   mode 1: physical -> modulated sine representation
+//   mode 2: modulated sine representation -> physical field with carrier at step[b]
+hipError_t launch_transform(int P, int mode, const SolveDesc *d_desc, int B, const float2 *in,
+                            float2 *out, const long long *step, hipStream_t stream);
+
+// Plain form: one kernel per transform / pointwise stage, one solve, host loop.
+hipError_t plain_march(const SolveDesc &h_desc, const SolveDesc *d_desc, int nsteps,
+                       float2 *d_work, double *d_scal, int *d_flags, hipStream_t stream);
+
+bool fft_length_supported(int P);
+
+}  // namespace ssp

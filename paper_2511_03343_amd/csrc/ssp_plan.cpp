@@ -1,0 +1,342 @@
+// ssp_plan.cpp - Pade coefficients and device tables, computed on the host.
+//
+// Pade construction (Sec. 2; Alg. 1 first step), written from the textbook definition of
+// the [p/p] approximant: Taylor series of the target, the p linear matching conditions for
+// the denominator, the numerator by truncated convolution, then the factor roots.  All of
+// it runs in x87 extended precision (64-bit mantissa); the roots are found with the
+// Aberth-Ehrlich simultaneous iteration and polished by Newton steps.
+#include "ssp_plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace ssp {
+
+namespace {
+
+const long double kPi = 3.141592653589793238462643383279502884L;
+
+cld expj(long double t) { return cld(std::cos(t), std::sin(t)); }
+
+// Taylor coefficients F_0..F_n of F(Z) = exp(h(Z)), h(Z) = i s (e^{i alpha/2} sqrt(1+Z) - 1):
+// F' = h' F gives n F_n = sum_{k=1..n} k h_k F_{n-k}.
+std::vector<cld> taylor(long double s, long double alpha, int n) {
+    const cld I(0, 1);
+    const cld rot = expj(alpha / 2);
+    std::vector<cld> h(n + 1), F(n + 1);
+    h[0] = I * s * (rot - cld(1));
+    long double binom = 1;  // binom(1/2, k)
+    for (int k = 1; k <= n; ++k) {
+        binom *= (0.5L - (k - 1)) / k;
+        h[k] = I * s * rot * binom;
+    }
+    F[0] = std::exp(h[0]);
+    for (int m = 1; m <= n; ++m) {
+        cld acc(0);
+        for (int k = 1; k <= m; ++k) acc += static_cast<long double>(k) * h[k] * F[m - k];
+        F[m] = acc / static_cast<long double>(m);
+    }
+    return F;
+}
+
+// Gaussian elimination with partial pivoting, A is n x n row-major.
+bool solve(std::vector<cld> A, std::vector<cld> b, int n, std::vector<cld> &x) {
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::abs(A[r * n + c]) > std::abs(A[piv * n + c])) piv = r;
+        if (std::abs(A[piv * n + c]) == 0) return false;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[piv * n + k]);
+            std::swap(b[c], b[piv]);
+        }
+        for (int r = c + 1; r < n; ++r) {
+            cld f = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    x.assign(n, cld(0));
+    for (int r = n - 1; r >= 0; --r) {
+        cld acc = b[r];
+        for (int k = r + 1; k < n; ++k) acc -= A[r * n + k] * x[k];
+        x[r] = acc / A[r * n + r];
+    }
+    return true;
+}
+
+// polynomial c[0] + c[1] x + ... + c[n] x^n and its derivative at x
+void polyval(const std::vector<cld> &c, cld x, cld &v, cld &dv) {
+    v = 0;
+    dv = 0;
+    for (int k = static_cast<int>(c.size()) - 1; k >= 0; --k) {
+        dv = dv * x + v;
+        v = v * x + c[k];
+    }
+}
+
+// Roots of c[0] + ... + c[n] x^n (c[n] != 0) by Aberth-Ehrlich + Newton polish.
+bool roots(const std::vector<cld> &c, std::vector<cld> &z) {
+    const int n = static_cast<int>(c.size()) - 1;
+    z.resize(n);
+    // initial guesses on a circle of the Cauchy-bound radius
+    long double rad = 0;
+    for (int k = 0; k < n; ++k) rad = std::max(rad, std::pow(std::abs(c[k] / c[n]), 1.0L / (n - k)));
+    rad = std::max(rad, 1e-3L);
+    for (int k = 0; k < n; ++k) z[k] = rad * expj(2 * kPi * (k + 0.25L) / n + 0.4L);
+    for (int it = 0; it < 500; ++it) {
+        long double worst = 0;
+        for (int k = 0; k < n; ++k) {
+            cld v, dv;
+            polyval(c, z[k], v, dv);
+            if (v == cld(0)) continue;
+            cld ratio = v / dv;
+            cld sum(0);
+            for (int j = 0; j < n; ++j)
+                if (j != k) sum += cld(1) / (z[k] - z[j]);
+            cld step = ratio / (cld(1) - ratio * sum);
+            z[k] -= step;
+            worst = std::max(worst, std::abs(step) / std::max(std::abs(z[k]), 1e-30L));
+        }
+        if (worst < 1e-18L) break;
+    }
+    for (int k = 0; k < n; ++k) {
+        for (int it = 0; it < 4; ++it) {
+            cld v, dv;
+            polyval(c, z[k], v, dv);
+            if (dv == cld(0)) break;
+            z[k] -= v / dv;
+        }
+        if (!std::isfinite(z[k].real()) || !std::isfinite(z[k].imag())) return false;
+    }
+    return true;
+}
+
+bool arg_less(const cld &x, const cld &y) {
+    long double ax = std::arg(x), ay = std::arg(y);
+    if (ax != ay) return ax < ay;
+    return std::abs(x) < std::abs(y);
+}
+
+}  // namespace
+
+bool pade_coefficients(double sigma_d, int p, double alpha_d, PadeSet &out, std::string &err) {
+    if (p < 1 || p > 12) {
+        err = "pade_order must be in [1, 12]";
+        return false;
+    }
+    const long double s = sigma_d, alpha = alpha_d;
+    std::vector<cld> F = taylor(s, alpha, 2 * p);
+    // denominator: sum_{i=0..p} q_i F_{n-i} = 0 for n = p+1..2p, q_0 = 1
+    std::vector<cld> A(p * p), rhs(p), q1;
+    for (int r = 0; r < p; ++r) {
+        int n = p + 1 + r;
+        for (int i = 1; i <= p; ++i) A[r * p + (i - 1)] = F[n - i];
+        rhs[r] = -F[n];
+    }
+    if (!solve(A, rhs, p, q1)) {
+        err = "singular Pade system";
+        return false;
+    }
+    std::vector<cld> q(p + 1), P(p + 1);
+    q[0] = 1;
+    for (int i = 0; i < p; ++i) q[i + 1] = q1[i];
+    for (int n = 0; n <= p; ++n) {
+        cld acc(0);
+        for (int i = 0; i <= n; ++i) acc += q[i] * F[n - i];
+        P[n] = acc;
+    }
+    std::vector<cld> rq, rp;
+    if (!roots(q, rq) || !roots(P, rp)) {
+        err = "Pade root finding failed";
+        return false;
+    }
+    // Q(Z) = prod (1 + bt_j Z), P(Z) = P_0 prod (1 + at_j Z)
+    std::vector<cld> bt(p), at(p);
+    for (int j = 0; j < p; ++j) {
+        bt[j] = cld(-1) / rq[j];
+        at[j] = cld(-1) / rp[j];
+    }
+    std::sort(bt.begin(), bt.end(), arg_less);
+    // pair each numerator factor with the denominator factor whose conjugate it is closest to
+    std::vector<cld> pool = at, paired;
+    for (int j = 0; j < p; ++j) {
+        size_t best = 0;
+        for (size_t k = 1; k < pool.size(); ++k)
+            if (std::abs(pool[k] - std::conj(bt[j])) < std::abs(pool[best] - std::conj(bt[j]))) best = k;
+        paired.push_back(pool[best]);
+        pool.erase(pool.begin() + best);
+    }
+    cld C = P[0];
+    std::vector<cld> b(p), a(p);
+    if (alpha != 0) {
+        const cld gam = expj(-alpha), beta = gam - cld(1);
+        for (int j = 0; j < p; ++j) {
+            C = C * (cld(1) + paired[j] * beta) / (cld(1) + bt[j] * beta);
+            b[j] = bt[j] * gam / (cld(1) + bt[j] * beta);
+            a[j] = paired[j] * gam / (cld(1) + paired[j] * beta);
+        }
+    } else {
+        b = bt;
+        a = paired;
+    }
+    std::vector<int> idx(p);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return arg_less(b[x], b[y]); });
+    out.p = p;
+    out.sigma = sigma_d;
+    out.alpha = alpha_d;
+    out.b.resize(p);
+    out.a.resize(p);
+    out.d.resize(p);
+    cld d0 = C;
+    for (int k = 0; k < p; ++k) d0 *= a[k] / b[k];
+    for (int k = 0; k < p; ++k) {
+        int j = idx[k];
+        cld num = C, den(1);
+        for (int i = 0; i < p; ++i) {
+            num *= cld(1) - a[i] / b[j];
+            if (i != j) den *= cld(1) - b[i] / b[j];
+        }
+        out.b[k] = cd(b[j]);
+        out.a[k] = cd(a[j]);
+        out.d[k] = cd(num / den);
+    }
+    out.C = cd(C);
+    out.d0 = cd(d0);
+    for (int k = 0; k < p; ++k)
+        if (!std::isfinite(out.b[k].real()) || !std::isfinite(out.d[k].real())) {
+            err = "non-finite Pade coefficient";
+            return false;
+        }
+    return true;
+}
+
+cd pade_eval(const PadeSet &ps, cd x) {
+    cd r = ps.C;
+    for (int j = 0; j < ps.p; ++j) r *= (1.0 + ps.a[j] * x) / (1.0 + ps.b[j] * x);
+    return r;
+}
+
+// ------------------------------------------------------------------------------ host FFT
+namespace {
+void fft_rec(cd *x, int n, int stride, cd *out, int sign) {
+    if (n == 1) {
+        out[0] = x[0];
+        return;
+    }
+    int r = (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : 5;
+    int m = n / r;
+    std::vector<cd> sub(n);
+    for (int k = 0; k < r; ++k) fft_rec(x + k * stride, m, stride * r, sub.data() + k * m, sign);
+    for (int q = 0; q < m; ++q) {
+        for (int s = 0; s < r; ++s) {
+            cd acc(0);
+            for (int k = 0; k < r; ++k) {
+                long double ang = sign * 2 * kPi * static_cast<long double>(k) * (q + s * m) / n;
+                cd w(static_cast<double>(std::cos(ang)), static_cast<double>(std::sin(ang)));
+                acc += w * sub[k * m + q];
+            }
+            out[q + s * m] = acc;
+        }
+    }
+}
+}  // namespace
+
+void host_fft(std::vector<cd> &x, int sign) {
+    std::vector<cd> out(x.size());
+    fft_rec(x.data(), static_cast<int>(x.size()), 1, out.data(), sign);
+    x.swap(out);
+}
+
+int chirp_fft_length(int n_min) {
+    int P = 1;
+    while (P < n_min) P *= 2;
+    return P;
+}
+
+// ------------------------------------------------------------------------------ tables
+void build_tables(int nz, double depth, double k0, const PadeSet &ps, DeviceTables &t) {
+    const int N = nz, M = nz + 1, P = chirp_fft_length(2 * nz - 1);
+    t.nz = N;
+    t.P = P;
+    // chirp c_d = exp(i pi d^2 / (2M)), argument reduced exactly with d^2 mod 4M
+    auto chirp = [&](long long d) {
+        long long r = (d * d) % (4LL * M);
+        long double ang = kPi * static_cast<long double>(r) / (2.0L * M);
+        return cd(static_cast<double>(std::cos(ang)), static_cast<double>(std::sin(ang)));
+    };
+    std::vector<cd> K1(P, 0.0), K2(P, 0.0);
+    for (long long d = 1 - N; d <= N - 1; ++d) K1[((d % P) + P) % P] = chirp(d);
+    for (long long d = 2; d <= 2LL * N; ++d) K2[d % P] = chirp(d);
+    host_fft(K1, -1);
+    host_fft(K2, -1);
+    t.k1.resize(2 * P);
+    t.k2.resize(2 * P);
+    for (int q = 0; q < P; ++q) {
+        t.k1[2 * q] = static_cast<float>(K1[q].real());
+        t.k1[2 * q + 1] = static_cast<float>(K1[q].imag());
+        t.k2[2 * q] = static_cast<float>(K2[q].real());
+        t.k2[2 * q + 1] = static_cast<float>(K2[q].imag());
+    }
+    const double scale = 0.5 * std::sqrt(2.0 / M) / P;  // (i/2) sqrt(2/M) / P, i applied below
+    const cd I(0, 1);
+    std::vector<cd> dmod(N);
+    t.pre.resize(2 * N);
+    t.post.resize(2 * N);
+    t.dmod.resize(2 * N);
+    for (int n = 1; n <= N; ++n) {
+        cd cb = std::conj(chirp(n));
+        cd post = cb * I * scale;
+        dmod[n - 1] = cb * cb * I * scale;
+        t.pre[2 * (n - 1)] = static_cast<float>(cb.real());
+        t.pre[2 * (n - 1) + 1] = static_cast<float>(cb.imag());
+        t.post[2 * (n - 1)] = static_cast<float>(post.real());
+        t.post[2 * (n - 1) + 1] = static_cast<float>(post.imag());
+        t.dmod[2 * (n - 1)] = static_cast<float>(dmod[n - 1].real());
+        t.dmod[2 * (n - 1) + 1] = static_cast<float>(dmod[n - 1].imag());
+    }
+    t.twiddle.resize(4 * P);
+    for (int e = 0; e < P; ++e) {
+        long double ang = -2 * kPi * static_cast<long double>(e) / P;
+        double re = static_cast<double>(std::cos(ang)), im = static_cast<double>(std::sin(ang));
+        split_df(re, t.twiddle[4 * e], t.twiddle[4 * e + 2]);
+        split_df(im, t.twiddle[4 * e + 1], t.twiddle[4 * e + 3]);
+    }
+    const int p = ps.p;
+    t.s.resize(static_cast<size_t>(4) * p * N);
+    t.bmul.resize(static_cast<size_t>(4) * p * N);
+    t.alpha.resize(4 * p);
+    t.beta.resize(4 * p);
+    double gain = 0;
+    for (int l = 1; l <= N; ++l) {
+        double x = -std::pow(l * static_cast<double>(kPi) / (depth * k0), 2);
+        cd G = std::exp(cd(0, ps.sigma)) * pade_eval(ps, cd(x, 0));
+        gain = std::max(gain, std::abs(G));
+        for (int j = 0; j < p; ++j) {
+            cd sj = 1.0 / (1.0 + ps.b[j] * x);
+            cd bj = -ps.b[j] * sj * dmod[l - 1];
+            size_t o = (static_cast<size_t>(j) * N + (l - 1)) * 4;
+            split_df(sj.real(), t.s[o], t.s[o + 2]);
+            split_df(sj.imag(), t.s[o + 1], t.s[o + 3]);
+            split_df(bj.real(), t.bmul[o], t.bmul[o + 2]);
+            split_df(bj.imag(), t.bmul[o + 1], t.bmul[o + 3]);
+        }
+    }
+    t.max_gain = gain;
+    for (int j = 0; j < p; ++j) {
+        cd g = ps.a[j] / ps.b[j];
+        cd al = g, be = 1.0 - g;
+        if (j == p - 1) {
+            al *= ps.C;
+            be *= ps.C;
+        }
+        split_df(al.real(), t.alpha[4 * j], t.alpha[4 * j + 2]);
+        split_df(al.imag(), t.alpha[4 * j + 1], t.alpha[4 * j + 3]);
+        split_df(be.real(), t.beta[4 * j], t.beta[4 * j + 2]);
+        split_df(be.imag(), t.beta[4 * j + 1], t.beta[4 * j + 3]);
+    }
+}
+
+}  // namespace ssp

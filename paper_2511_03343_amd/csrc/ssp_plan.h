@@ -1,0 +1,67 @@
+// ssp_plan.h - host-side plan mathematics of the SSSP library (no HIP dependencies).
+//
+// Pade coefficients (Sec. 2, the [p/p] approximant of exp(i sigma (sqrt(1+x) - 1)); Alg. 1
+// first step), the sine-basis eigenvalues of the vertical operator (Sec. 3 and 3.1), and
+// the tables that the device kernels consume.  Everything here is computed in FP64 or
+// extended precision on the host and rounded once when stored.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ssp {
+
+using cld = std::complex<long double>;
+using cd = std::complex<double>;
+
+struct PadeSet {
+    int p = 0;
+    double sigma = 0, alpha = 0;
+    std::vector<cd> b;  // denominator factors 1 + b_j x, application order
+    std::vector<cd> a;  // numerator factors 1 + a_j x paired with b_j
+    cd C{1, 0};         // product-form constant
+    cd d0{1, 0};        // sum-form constant
+    std::vector<cd> d;  // sum-form residues paired with b_j
+};
+
+// [p/p] Pade approximant of F(Z) = exp(i sigma (e^{i alpha/2} sqrt(1+Z) - 1)) mapped back to
+// x with Z = e^{-i alpha}(1+x) - 1 (alpha = 0: the standard approximant).  Returns false
+// (with a message) if the construction fails.
+bool pade_coefficients(double sigma, int p, double alpha, PadeSet &out, std::string &err);
+
+// R(x) = C prod (1 + a_j x)/(1 + b_j x)
+cd pade_eval(const PadeSet &ps, cd x);
+
+// In-place complex FFT of length n (a power of two times 3^a 5^b), sign -1 forward.
+void host_fft(std::vector<cd> &x, int sign);
+
+// Smallest FFT length accepted by the device engine that is >= n_min.
+int chirp_fft_length(int n_min);
+
+struct DeviceTables {
+    int nz = 0, P = 0;
+    // chirp-z DST (orthonormal DST-I of length nz through a cyclic convolution of length P):
+    std::vector<float> k1, k2;        // [P] complex FP32 spectra of the two chirp windows
+    std::vector<float> pre;           // [nz] complex FP32  conj(c_n)
+    std::vector<float> post;          // [nz] complex FP32  conj(c_k) (i/2) sqrt(2/(nz+1)) / P
+    std::vector<float> dmod;          // [nz] complex FP32  conj(c_k)^2 (i/2) sqrt(2/(nz+1)) / P
+    std::vector<float> twiddle;       // [P] double-float complex exp(-2 pi i e / P): hi.re hi.im lo.re lo.im
+    // Pade factors in the chirp-modulated sine basis:
+    std::vector<float> s;             // [p][nz] double-float complex 1/(1 + b_j x_l)
+    std::vector<float> bmul;          // [p][nz] double-float complex -b_j s_jl * dmod_l (FP64 product)
+    std::vector<float> alpha, beta;   // [p] double-float complex combine weights
+    double max_gain = 0;              // max_l |e^{i sigma} R(x_l)|
+};
+
+// Build all device tables for a grid (nz, H, k0) and a coefficient set.
+void build_tables(int nz, double depth, double k0, const PadeSet &ps, DeviceTables &t);
+
+// Split a double into hi + lo floats (hi = nearest float, lo = nearest float of the rest).
+inline void split_df(double v, float &hi, float &lo) {
+    hi = static_cast<float>(v);
+    lo = static_cast<float>(v - static_cast<double>(hi));
+}
+
+}  // namespace ssp

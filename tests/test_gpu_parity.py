@@ -1,0 +1,273 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 oracle.
+
+Bar (floating point): relative L2 field error <= 1e-4 at every output range and
+|TL_gpu - TL_oracle| <= 0.1 dB wherever TL_oracle < 120 dB.  Transforms alone: <= 2e-6.
+Statuses, step counts and bitwise batch/resume equivalence are compared exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import DIVERGED, NOT_CONVERGED, OK, Plan as OraclePlan, dst as odst
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-4
+DTL = 0.1
+
+
+def _report(tag, **kv):
+    print(f"[{tag}] " + " ".join(f"{k}={v}" for k, v in kv.items()), flush=True)
+
+
+def make_plan(ssp, s, profile="table"):
+    pl = ssp.ssp_plan_create(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol)
+    if s.rotation:
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_ROTATION, s.rotation)
+    ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_OUT_EVERY, s.out_every)
+    if s.env == "munk+eddy":
+        if profile == "analytic":
+            e = s.eddy or W.Eddy()
+            ssp.ssp_set_profile_analytic(pl, eddy=(e.amp, e.r0, e.rr, e.z0, e.rz))
+        else:
+            ssp.ssp_set_profile(pl, 0, s.nsteps, s.profile())
+    elif s.env == "munk":
+        if profile == "analytic":
+            ssp.ssp_set_profile_analytic(pl)
+        else:
+            ssp.ssp_set_profile(pl, 0, -1, s.profile()[0])
+    return pl
+
+
+def oracle_march(s, nsteps=None, out_every=None):
+    pl = OraclePlan(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol,
+                    rotation=s.rotation)
+    return pl.march(s.starter(), nsteps or s.nsteps, s.profile(), out_every=out_every or s.out_every)
+
+
+def compare(tag, fld, tl, ref, rel=REL_L2, dtl=DTL):
+    assert fld.shape == ref.field.shape
+    err = np.linalg.norm(fld - ref.field, axis=1) / np.linalg.norm(ref.field, axis=1)
+    mask = ref.tl < 120.0
+    dt = np.abs(tl.astype(np.float64) - ref.tl)[mask]
+    _report(tag, max_relL2=f"{err.max():.3e}", final_relL2=f"{err[-1]:.3e}",
+            max_dTL=f"{dt.max() if dt.size else 0:.3e}")
+    assert err.max() <= rel
+    assert dt.size == 0 or dt.max() <= dtl
+
+
+# ------------------------------------------------------------------------------- transform
+@pytest.mark.parametrize("nz", [2, 3, 5, 16, 63, 64, 100, 255, 256, 257, 1000, 2047, 4096, 5000, 8192])
+def test_dst_parity(ssp, gpu, nz):
+    torch = gpu
+    B = 3
+    pl = ssp.ssp_plan_create(nz, 1000.0, 50.0, 1500.0, 10.0, 2, 0, 1e-10)
+    try:
+        x = np.stack([W.random_field(nz, 100 + b) for b in range(B)])
+        d_in = torch.from_numpy(x.astype(np.complex64)).cuda()
+        d_out = torch.empty_like(d_in)
+        ssp.ssp_dst_device(pl, B, d_in.data_ptr(), d_out.data_ptr())
+        torch.cuda.synchronize()
+        got = d_out.cpu().numpy().astype(np.complex128)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = np.stack([odst(v) for v in x])
+    err = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    _report("dst", nz=nz, relL2=f"{err.max():.2e}")
+    assert err.max() < 2e-6
+
+
+def test_sine_roundtrip_and_carrier(ssp, gpu):
+    torch = gpu
+    s = W.munk_deep(nz=1000)
+    pl = make_plan(ssp, s)
+    try:
+        B = 2
+        x = np.stack([s.starter(), W.random_field(s.nz, 7)])
+        d_x = torch.from_numpy(x.astype(np.complex64)).cuda()
+        d_s = torch.empty_like(d_x)
+        d_y = torch.empty_like(d_x)
+        steps = torch.tensor([0, 7], dtype=torch.int64, device="cuda")
+        ssp.ssp_to_sine(pl, B, d_x.data_ptr(), d_s.data_ptr())
+        ssp.ssp_from_sine(pl, B, d_s.data_ptr(), steps.data_ptr(), d_y.data_ptr())
+        torch.cuda.synchronize()
+        y = d_y.cpu().numpy().astype(np.complex128)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    car = np.exp(1j * s.k0 * s.dr * np.array([0, 7]))[:, None]
+    err = np.linalg.norm(y - car * x, axis=1) / np.linalg.norm(x, axis=1)
+    assert err.max() < 2e-6
+
+
+# ------------------------------------------------------------------------------- marches
+def test_homogeneous_waveguide(ssp, gpu):
+    # H = 200 m, c = 1500 m/s, 100 Hz, Nz = 256, rotated [4/4], dr = 5 m, 1000 steps, V = 0
+    s = W.homogeneous_waveguide()
+    pl = make_plan(ssp, s)
+    try:
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert st == OK and stats["steps_done"] == s.nsteps
+    compare("homogeneous", fld, tl, ref)
+
+
+@pytest.mark.parametrize("nz,nsteps", [(2, 50), (3, 50), (127, 200), (511, 400), (1000, 100)])
+def test_munk_small(ssp, gpu, nz, nsteps):
+    s = W.munk_deep(nsteps=nsteps, nz=nz)
+    pl = make_plan(ssp, s)
+    try:
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert st == ref.status and stats["steps_done"] == ref.steps_done
+    compare(f"munk nz={nz}", fld, tl, ref)
+    # the same Neumann iteration counts as the oracle, up to a few near-threshold cases
+    assert abs(stats["neumann_terms"] - int(ref.iterations.sum())) <= 0.01 * ref.iterations.sum() + 2
+
+
+def test_munk_full_size_start(ssp, gpu):
+    # deep Munk waveguide at its full size (Nz = 4096) for the first 24 steps
+    s = W.munk_deep(nsteps=24)
+    pl = make_plan(ssp, s)
+    try:
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert st == OK
+    compare("munk full start", fld, tl, ref)
+
+
+def test_munk_full_size_norm_is_conserved(ssp, gpu):
+    # lossless medium, standard Pade, converged series: ||u|| is constant (any size)
+    s = W.munk_deep(nsteps=400)
+    s.out_every = 100
+    pl = make_plan(ssp, s)
+    try:
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    n0 = np.linalg.norm(s.starter())
+    ratios = np.linalg.norm(fld, axis=1) / n0
+    _report("norm", ratios=np.array2string(ratios, precision=8))
+    assert st == OK and np.max(np.abs(ratios - 1)) < 2e-5
+
+
+@pytest.mark.parametrize("profile", ["table", "analytic"])
+def test_eddy_range_dependent(ssp, gpu, profile):
+    s = W.munk_eddy(nsteps=150, nz=1023, neumann_max=24)
+    s.dr = 250.0 / 3.0   # crosses the eddy core (r0 = 50 km) in a short run
+    s.nsteps = 120
+    s.out_every = 10
+    s.eddy = W.Eddy(r0=5000.0, rr=2500.0)
+    pl = make_plan(ssp, s, profile=profile)
+    try:
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert st == ref.status
+    compare(f"eddy {profile}", fld, tl, ref)
+
+
+# ------------------------------------------------------------------------------- statuses
+def test_divergence_reported_and_field_kept(ssp, gpu):
+    s = W.munk_deep(nsteps=5, nz=511)
+    s.dr = 1.0 / s.k0
+    s.neumann_max = 16
+    pl = make_plan(ssp, s)
+    try:
+        with pytest.raises(ssp.SspError) as e:
+            ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+        assert e.value.status == ssp.SSP_E_DIVERGED
+        back = ssp.ssp_get_field(pl, s.nz)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert ref.status == DIVERGED and ref.steps_done == 0
+    assert np.linalg.norm(back - s.starter()) / np.linalg.norm(s.starter()) < 2e-6
+
+
+def test_not_converged_reported(ssp, gpu):
+    s = W.munk_deep(nsteps=3, nz=511, neumann_max=3)
+    pl = make_plan(ssp, s)
+    try:
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert ref.status == NOT_CONVERGED and st == ssp.SSP_W_NOT_CONVERGED
+    assert stats["not_converged"] == int((ref.iterations == 3).sum() - 0) or stats["not_converged"] > 0
+    compare("not converged", fld, tl, ref)
+
+
+# ------------------------------------------------------------------------------- equivalences
+def test_resume_is_bitwise(ssp, gpu):
+    s = W.munk_deep(nsteps=40, nz=700)
+    s.out_every = 20
+    a = make_plan(ssp, s)
+    b = make_plan(ssp, s)
+    try:
+        _, f_all, _, _ = ssp.ssp_march(a, s.nz, s.starter(), 40)
+        _, f1, _, _ = ssp.ssp_march(b, s.nz, s.starter(), 20)
+        _, f2, _, _ = ssp.ssp_march(b, s.nz, None, 20)
+    finally:
+        ssp.ssp_plan_destroy(a)
+        ssp.ssp_plan_destroy(b)
+    assert np.array_equal(f_all, np.concatenate([f1, f2]))
+
+
+def test_batch_equals_alone_bitwise(ssp, gpu):
+    sizes = [(300, 500.0), (777, 1500.0), (2000, 1000.0), (511, 100.0)]
+    solves = [W.munk_deep(nsteps=16, nz=nz, zs=zs) for nz, zs in sizes]
+    for s in solves:
+        s.out_every = 8
+    alone = []
+    for s in solves:
+        pl = make_plan(ssp, s)
+        try:
+            alone.append(ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)[1])
+        finally:
+            ssp.ssp_plan_destroy(pl)
+    plans = [make_plan(ssp, s) for s in solves]
+    try:
+        for pl, s in zip(plans, solves):
+            ssp.ssp_set_field(pl, s.starter(), s.nz)
+        st, fl, tl, stats = ssp.ssp_march_batch(plans, [s.nz for s in solves], 16)
+    finally:
+        for pl in plans:
+            ssp.ssp_plan_destroy(pl)
+    for a, b in zip(alone, fl):
+        assert np.array_equal(a, b)
+
+
+def test_device_batch_matches_host_march(ssp, gpu):
+    torch = gpu
+    B = 5
+    base = W.munk_deep(nsteps=12, nz=1500)
+    zs = W.source_depths(B, 200.0, 2000.0, seed=4)
+    pl = make_plan(ssp, base)
+    try:
+        psi = np.stack([W.gaussian_starter(base.nz, base.depth, base.freq, base.c0, z) for z in zs])
+        d_psi = torch.from_numpy(psi.astype(np.complex64)).cuda()
+        steps = torch.zeros(B, dtype=torch.int64, device="cuda")
+        ssp.ssp_to_sine(pl, B, d_psi.data_ptr(), d_psi.data_ptr())
+        ssp.ssp_march_device(pl, B, d_psi.data_ptr(), steps.data_ptr(), base.nsteps)
+        out = torch.empty_like(d_psi)
+        ssp.ssp_from_sine(pl, B, d_psi.data_ptr(), steps.data_ptr(), out.data_ptr())
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert steps.cpu().tolist() == [base.nsteps] * B
+        host = []
+        for z in zs:
+            ssp.ssp_set_field(pl, W.gaussian_starter(base.nz, base.depth, base.freq, base.c0, z), base.nz)
+            ssp.ssp_march(pl, base.nz, None, base.nsteps, want_field=False, want_tl=False)
+            host.append(ssp.ssp_get_field(pl, base.nz))
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    assert np.array_equal(got.astype(np.complex128), np.stack(host))
