@@ -251,7 +251,7 @@ void host_fft(std::vector<cd> &x, int sign) {
 }
 
 int chirp_fft_length(int n_min) {
-    int P = 1;
+    int P = 8;  // smallest length of the device FFT
     while (P < n_min) P *= 2;
     return P;
 }

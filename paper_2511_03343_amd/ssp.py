@@ -64,6 +64,13 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64 (same soname); if
+        # torch is importable it is loaded first so that libssp binds to that runtime and
+        # device pointers and streams from torch are valid in the library.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         S = C.c_int
         sig = {

@@ -41,10 +41,11 @@ def make_plan(ssp, s, profile="table"):
     return pl
 
 
-def oracle_march(s, nsteps=None, out_every=None):
+def oracle_march(s, nsteps=None, out_every=None, psi0=None):
     pl = OraclePlan(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol,
                     rotation=s.rotation)
-    return pl.march(s.starter(), nsteps or s.nsteps, s.profile(), out_every=out_every or s.out_every)
+    return pl.march(s.starter() if psi0 is None else psi0, nsteps or s.nsteps, s.profile(),
+                    out_every=out_every or s.out_every)
 
 
 def compare(tag, fld, tl, ref, rel=REL_L2, dtl=DTL):
@@ -118,12 +119,15 @@ def test_homogeneous_waveguide(ssp, gpu):
 @pytest.mark.parametrize("nz,nsteps", [(2, 50), (3, 50), (127, 200), (511, 400), (1000, 100)])
 def test_munk_small(ssp, gpu, nz, nsteps):
     s = W.munk_deep(nsteps=nsteps, nz=nz)
+    # on the coarsest grids the source Gaussian falls between grid points: use a seeded
+    # random starter there
+    psi0 = s.starter() if nz >= 16 else W.random_field(nz, 21)
     pl = make_plan(ssp, s)
     try:
-        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, psi0, s.nsteps)
     finally:
         ssp.ssp_plan_destroy(pl)
-    ref = oracle_march(s)
+    ref = oracle_march(s, psi0=psi0)
     assert st == ref.status and stats["steps_done"] == ref.steps_done
     compare(f"munk nz={nz}", fld, tl, ref)
     # the same Neumann iteration counts as the oracle, up to a few near-threshold cases
@@ -195,6 +199,7 @@ def test_divergence_reported_and_field_kept(ssp, gpu):
 
 def test_not_converged_reported(ssp, gpu):
     s = W.munk_deep(nsteps=3, nz=511, neumann_max=3)
+    s.out_every = 1
     pl = make_plan(ssp, s)
     try:
         st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
@@ -202,7 +207,7 @@ def test_not_converged_reported(ssp, gpu):
         ssp.ssp_plan_destroy(pl)
     ref = oracle_march(s)
     assert ref.status == NOT_CONVERGED and st == ssp.SSP_W_NOT_CONVERGED
-    assert stats["not_converged"] == int((ref.iterations == 3).sum() - 0) or stats["not_converged"] > 0
+    assert stats["not_converged"] == int((ref.iterations == 3).sum())
     compare("not converged", fld, tl, ref)
 
 
