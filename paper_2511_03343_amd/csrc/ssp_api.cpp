@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -56,7 +57,8 @@ struct ssp_plan {
     ssp::DeviceTables tab;
     // device tables
     float2 *d_k1 = nullptr, *d_k2 = nullptr, *d_dmod = nullptr, *d_post = nullptr, *d_pre = nullptr;
-    float4 *d_tw = nullptr, *d_s = nullptr, *d_bmul = nullptr, *d_alpha = nullptr, *d_beta = nullptr;
+    uint32_t *d_tw = nullptr;
+    float4 *d_s = nullptr, *d_bmul = nullptr, *d_alpha = nullptr, *d_beta = nullptr;
     // environment
     int prof_mode = ssp::PROF_TABLE_FIXED, v_rows = 0;
     long long v_step0 = 0;
@@ -75,6 +77,8 @@ struct ssp_plan {
     int descs_cap = 0;
     float2 *d_bwork = nullptr;          // scratch states of a device batch [cap][N]
     int bwork_cap = 0;
+    float2 *d_snap = nullptr;           // output snapshots of a device batch
+    size_t snap_cap = 0;
     // output staging
     float2 *d_out_fld = nullptr;
     float *d_out_tl = nullptr;
@@ -100,9 +104,9 @@ void free_tables(ssp_plan *pl) {
     dev_free(pl->d_beta);
 }
 
-template <typename D>
-hipError_t upload(D *dst, const std::vector<float> &src) {
-    return hipMemcpy(dst, src.data(), src.size() * sizeof(float), hipMemcpyHostToDevice);
+template <typename D, typename S>
+hipError_t upload(D *dst, const std::vector<S> &src) {
+    return hipMemcpy(dst, src.data(), src.size() * sizeof(S), hipMemcpyHostToDevice);
 }
 
 // (Re)compute Pade coefficients and all tables for the current (N, H, f, c0, dr, p, alpha).
@@ -120,7 +124,7 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     const int N = pl->N, P = tab.P, p = ps.p;
     HIP_TRY(dev_alloc(&pl->d_k1, P));
     HIP_TRY(dev_alloc(&pl->d_k2, P));
-    HIP_TRY(dev_alloc(&pl->d_tw, P));
+    HIP_TRY(dev_alloc(&pl->d_tw, tab.twiddle.size()));
     HIP_TRY(dev_alloc(&pl->d_dmod, N));
     HIP_TRY(dev_alloc(&pl->d_post, N));
     HIP_TRY(dev_alloc(&pl->d_pre, N));
@@ -340,6 +344,7 @@ void ssp_plan_destroy(ssp_plan *pl) {
     dev_free(pl->d_field);
     dev_free(pl->d_work);
     dev_free(pl->d_bwork);
+    dev_free(pl->d_snap);
     dev_free(pl->d_step);
     dev_free(pl->d_stats);
     dev_free(pl->d_desc);
@@ -460,6 +465,28 @@ ssp_status ssp_set_profile_analytic(ssp_plan *pl, const ssp_env *env) {
     // the profile must stay positive: c >= munk_c1 (1 + eps (eta + e^-eta - 1)) - |amp|
     if (env->munk_c1 * (1 + std::min(0.0, env->munk_eps) * 10) - std::fabs(env->eddy_amp) <= 0)
         return fail(SSP_E_INVAL, "environment may give c <= 0");
+    // range-independent part: the Munk potential on the grid, in FP64, stored as row 0 of
+    // the profile table; the device adds the eddy term each step
+    const int N = pl->N;
+    const double dz = pl->H / (N + 1);
+    std::vector<float> v(N);
+    for (int n = 1; n <= N; ++n) {
+        const double z = n * dz, eta = 2.0 * (z - e[2]) / e[2];
+        const double c = e[0] * (1.0 + e[1] * (eta + std::exp(-eta) - 1.0));
+        if (!(c > 0)) return fail(SSP_E_INVAL, "Munk profile gives c <= 0 on the grid");
+        const double q = pl->c0 / c;
+        v[n - 1] = static_cast<float>(q * q - 1.0);
+    }
+    if (static_cast<size_t>(N) > pl->v_cap) {
+        dev_free(pl->d_v);
+        pl->v_cap = 0;
+        HIP_TRY(dev_alloc(&pl->d_v, N));
+        pl->v_cap = N;
+    }
+    HIP_TRY(hipMemcpyAsync(pl->d_v, v.data(), N * sizeof(float), hipMemcpyHostToDevice, pl->stream));
+    HIP_TRY(hipStreamSynchronize(pl->stream));
+    pl->v_rows = 1;
+    pl->v_step0 = 0;
     for (int i = 0; i < 8; ++i) pl->env[i] = e[i];
     pl->prof_mode = ssp::PROF_ANALYTIC;
     return SSP_OK;
@@ -535,8 +562,10 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
         d.step = pl->d_step;
         d.nout = nout[i];
         d.stats = pl->d_stats;
+        // snapshots go to the field staging rows and are converted there in place
         d.fld_out = (field_out && field_out[i] && nout[i] > 0) ? pl->d_out_fld : nullptr;
         d.tl_out = (tl_out && tl_out[i] && nout[i] > 0) ? pl->d_out_tl : nullptr;
+        d.snap = (d.fld_out || d.tl_out) ? pl->d_out_fld : nullptr;
         d.out_base = first_output_step(pl->step_index, pl->out_every);
         descs[i] = d;
     }
@@ -565,6 +594,9 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
             int end = start;
             while (end < n && sorted[end].P == sorted[start].P) ++end;
             HIP_TRY(ssp::launch_march(sorted[start].P, owner->d_descs + start, end - start, nsteps, stream));
+            int rows = 0;
+            for (int k = start; k < end; ++k) rows = std::max(rows, sorted[k].snap ? sorted[k].nout : 0);
+            HIP_TRY(ssp::launch_output(sorted[start].P, owner->d_descs + start, end - start, rows, stream));
             start = end;
         }
     }
@@ -621,6 +653,13 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
     }
     std::vector<ssp::SolveDesc> descs(B);
     const int nout = count_outputs(pl->step_index, nsteps, pl->out_every);
+    const size_t snap_elems = d_tl ? static_cast<size_t>(B) * nout * pl->N : 0;
+    if (snap_elems > pl->snap_cap) {
+        dev_free(pl->d_snap);
+        pl->snap_cap = 0;
+        HIP_TRY(dev_alloc(&pl->d_snap, snap_elems));
+        pl->snap_cap = snap_elems;
+    }
     for (int b = 0; b < B; ++b) {
         ssp::SolveDesc d = base_desc(pl);
         d.field = static_cast<float2 *>(d_psi) + static_cast<size_t>(b) * pl->N;
@@ -632,11 +671,13 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
         d.fld_out = nullptr;
         d.out_base = first_output_step(pl->step_index, pl->out_every);
         if (nout == 0) d.tl_out = nullptr;
+        d.snap = d.tl_out ? pl->d_snap + static_cast<size_t>(b) * nout * pl->N : nullptr;
         descs[b] = d;
     }
     HIP_TRY(hipMemcpyAsync(pl->d_descs, descs.data(), B * sizeof(ssp::SolveDesc), hipMemcpyHostToDevice,
                            pl->stream));
     HIP_TRY(ssp::launch_march(pl->P, pl->d_descs, B, nsteps, pl->stream));
+    if (d_tl && nout > 0) HIP_TRY(ssp::launch_output(pl->P, pl->d_descs, B, nout, pl->stream));
     pl->step_index += nsteps;
     return SSP_OK;
 }

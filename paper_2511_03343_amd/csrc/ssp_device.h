@@ -24,7 +24,7 @@ enum ProfileMode : int { PROF_TABLE_FIXED = 0, PROF_TABLE_STEPS = 1, PROF_ANALYT
 // solves of a plan; state pointers are per solve.
 struct SolveDesc {
     const float2 *k1, *k2;      // [P] chirp-window spectra
-    const float4 *tw;           // [P] double-float twiddles exp(-2 pi i e/P)
+    const uint32_t *tw;         // first-octant twiddle table (see DeviceTables::twiddle)
     const float2 *dmod, *post;  // [N]
     const float2 *pre;          // [N] conj chirp (physical -> chirp-z input)
     const float4 *s, *bmul;     // [p][N] double-float
@@ -41,6 +41,7 @@ struct SolveDesc {
     float2 *work;               // [N] scratch state between Pade factors
     long long *step;            // global step counter
     DevStats *stats;
+    float2 *snap;               // [nout][N] sine-basis snapshots at output steps, or null
     float *tl_out;              // [nout][N] or null
     float2 *fld_out;            // [nout][N] or null (complex64, carrier included)
     int out_every;
@@ -52,6 +53,10 @@ struct SolveDesc {
 // length P.  Returns hipSuccess or the launch error.
 hipError_t launch_march(int P, const SolveDesc *d_descs, int nsolves, int nsteps,
                         hipStream_t stream);
+
+// Convert the snapshots of an earlier march into field / TL rows: one workgroup per
+// (solve, output row); rows beyond a solve's nout are skipped.
+hipError_t launch_output(int P, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream);
 
 // Batched transforms over B vectors of a plan's grid (tables from desc, one desc on the
 // device shared by the whole batch).

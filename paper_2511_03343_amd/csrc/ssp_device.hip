@@ -76,6 +76,9 @@ __device__ __forceinline__ float4 ld4(const float4 *p, int i) {
     return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
                        __uint_as_float(v[3]));
 }
+__device__ __forceinline__ uint32_t ldu(const uint32_t *p, int i) {
+    return __builtin_amdgcn_raw_buffer_load_b32(rsrc(p), i * 4, 0, 0);
+}
 __device__ __forceinline__ float ldf(const float *p, int i) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc(p), i * 4, 0, 0));
 }
@@ -151,109 +154,218 @@ struct Dft<1, INV> {
     __device__ __forceinline__ static void run(float2 *) {}
 };
 
-// ----------------------------------------------------------------------------- FFT in LDS
-// LDS index map.  Kept linear so that the per-radix element offsets fold into the
-// instructions' immediate offsets instead of occupying address registers.
-__device__ __forceinline__ int pad(int i) { return i; }
-constexpr int lds_len(int P) { return P; }
+// Thread index laundered through an empty asm: index arithmetic derived from it is
+// recomputed where it is used instead of being hoisted out of the range-step loops, which
+// would keep dozens of loop-invariant addresses alive in vector registers.
+__device__ __forceinline__ int opaque_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
 
-// One self-sorting (Stockham) radix-R pass over the P-point sequence in LDS:
-// butterfly j (k = j mod Ns) reads x_r = buf[j + r P/R], applies w_{Ns R}^{r k}, takes the
-// R-point DFT and writes buf[(j - k) R + k + r Ns].  All reads complete before any write.
-template <int P, int T, int R, bool INV>
-__device__ __forceinline__ void stockham_pass(float2 *buf, int Ns, const float4 *__restrict__ tw) {
-    constexpr int NB = P / R;
-    constexpr int PER = (NB + T - 1) / T;
-    const int tid = threadIdx.x;
-    float2 x[PER][R];
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int j = tid + i * T;
-        if (NB % T == 0 || j < NB) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) x[i][r] = buf[pad(j + r * NB)];
-        }
+// ----------------------------------------------------------------------------- FFT engine
+// One workgroup computes a P-point complex FFT (P a power of two).  Thread t owns the RT =
+// P/T elements at positions t + i T (i < RT) in registers.  The first pass (radix RT, no
+// twiddles) reads exactly those positions and the last pass (radix RT, stride T) produces
+// exactly those positions, so a transform goes registers -> LDS -> ... -> registers; the
+// middle passes are self-sorting (Stockham) radix passes through LDS:
+//   butterfly j (k = j mod Ns) reads positions j + r P/R, multiplies by w_{Ns R}^{r k},
+//   takes the R-point DFT and writes positions (j - k) R + k + r Ns.
+// LDS: padded index (one slot per 2^PADSH elements, spreads power-of-two strides over the
+// banks); two data buffers when they fit (one barrier per exchange), else one; twiddles
+// w_P^e from a first-octant table rebuilt by symmetry, double-float (FP32 + bf16 rest).
+template <int P>
+struct Cfg {
+    static constexpr int T = P <= 512 ? 64 : (P == 1024 ? 128 : (P <= 4096 ? 256 : 1024));
+    static constexpr int RT = P / T;
+    static constexpr int PADSH = P >= 16384 ? 5 : 4;
+    static constexpr int DLEN = P + (P >> PADSH);
+    static constexpr int O = P / 8;
+    static constexpr int LOG2O = __builtin_ctz(P / 8);
+    static constexpr bool PINGPONG = (2 * DLEN * 8 + (O + 1) * 12 + 512) <= 160 * 1024;
+};
+
+template <int P>
+__device__ __forceinline__ int lp(int i) { return i + (i >> Cfg<P>::PADSH); }
+
+// LDS of one transform.  Exchange phase k (a write, a barrier, then reads) uses buffer k mod 2
+// (buffer 0 only when two do not fit), chosen at compile time so that every access is a
+// plain ds_read/ds_write.
+struct LdsBufs {
+    float2 *b0, *b1;
+    const float2 *thi;
+    const uint32_t *tlo;
+};
+
+template <int P, int PH>
+__device__ __forceinline__ float2 *phase_buf(const LdsBufs &L) {
+    return (Cfg<P>::PINGPONG && (PH & 1)) ? L.b1 : L.b0;
+}
+// with a single buffer every thread must be done reading before anyone writes
+template <int P>
+__device__ __forceinline__ void before_write() {
+    if constexpr (!Cfg<P>::PINGPONG) __syncthreads();
+}
+
+// w_P^e, e in [0, P): first-octant table entry, mirrored for odd octants, rotated by (-i)^q
+template <int P>
+__device__ __forceinline__ float4 twid(const LdsBufs &L, int e) {
+    constexpr int O = Cfg<P>::O;
+    const int o = e >> Cfg<P>::LOG2O, r = e & (O - 1);
+    const bool odd = o & 1;
+    const int idx = odd ? O - r : r;
+    const float2 h = L.thi[idx];
+    const uint32_t l = L.tlo[idx];
+    float hr = h.x, hi = odd ? -h.y : h.y;
+    float lr = __uint_as_float(l & 0xffff0000u), li = __uint_as_float(l << 16);
+    if (odd) li = -li;
+    const int q = ((o + (odd ? 1 : 0)) >> 1) & 3;
+    float4 w;
+    if (q == 0) w = make_float4(hr, hi, lr, li);
+    else if (q == 1) w = make_float4(hi, -hr, li, -lr);
+    else if (q == 2) w = make_float4(-hr, -hi, -lr, -li);
+    else w = make_float4(-hi, hr, -li, lr);
+    return w;
+}
+
+template <bool INV>
+__device__ __forceinline__ float2 twmul(float2 x, float4 w) {
+    return INV ? cmul_df_conj(x, w) : cmul_df(x, w);
+}
+
+// Number of LDS exchange phases of one FFT (passes - 1).
+template <int P, int Ns>
+constexpr int mid_count() {
+    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    if constexpr (Ns >= T) {
+        return 0;
+    } else {
+        constexpr int R = (T / Ns) < RT ? (T / Ns) : RT;
+        return 1 + mid_count<P, Ns * R>();
     }
-    __syncthreads();
+}
+template <int P>
+constexpr int fft_phases() { return 1 + mid_count<P, Cfg<P>::RT>(); }
+
+// middle passes: read phase PH, write phase PH + 1; Ns = current stride until it reaches T
+template <int P, bool INV, int Ns, int PH>
+__device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBufs &L) {
+    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    if constexpr (Ns < T) {
+        constexpr int R = (T / Ns) < RT ? (T / Ns) : RT;
+        constexpr int PER = RT / R;
+        constexpr int NB = P / R;
+        constexpr int STRIDE = P / (Ns * R);
+        const int tid = opaque_tid();
+        const float2 *in = phase_buf<P, PH>(L);
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int j = tid + i * T;
-        if (NB % T == 0 || j < NB) {
+        for (int i = 0; i < PER; ++i) {
+            const int j = tid + i * T;
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[i * R + r] = in[lp<P>(j + r * NB)];
+        }
+        before_write<P>();
+        float2 *out = phase_buf<P, PH + 1>(L);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int j = tid + i * T;
             const int k = j & (Ns - 1);
-            if (Ns > 1) {
-                const int stride = P / (Ns * R);
+            float2 *v = &x[i * R];
 #pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    const float4 w = ld4(tw, r * k * stride);
-                    x[i][r] = INV ? cmul_df_conj(x[i][r], w) : cmul_df(x[i][r], w);
-                }
-            }
-            Dft<R, INV>::run(x[i]);
+            for (int r = 1; r < R; ++r) v[r] = twmul<INV>(v[r], twid<P>(L, r * k * STRIDE));
+            Dft<R, INV>::run(v);
             const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[pad(base + r * Ns)] = x[i][r];
+            for (int r = 0; r < R; ++r) out[lp<P>(base + r * Ns)] = v[r];
         }
+        __syncthreads();
+        mid_passes<P, INV, Ns * R, PH + 1>(x, L);
+    }
+}
+
+// Full FFT of the distributed vector x (registers in, registers out); its first exchange
+// uses phase PH.
+template <int P, bool INV, int PH>
+__device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L) {
+    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    const int tid = opaque_tid();
+    // first pass: Ns = 1, butterfly j = t on positions t + r T
+    Dft<RT, INV>::run(x);
+    before_write<P>();
+    {
+        float2 *out = phase_buf<P, PH>(L);
+#pragma unroll
+        for (int r = 0; r < RT; ++r) out[lp<P>(tid * RT + r)] = x[r];
     }
     __syncthreads();
-}
-
-// largest radix <= 16 that keeps every thread busy (P/R butterflies >= T threads)
-constexpr int pick_radix(int rem, int maxr) {
-    int r = maxr >= 16 ? 16 : (maxr >= 8 ? 8 : (maxr >= 4 ? 4 : 2));
-    return rem >= r ? r : rem;
-}
-
-template <int P, int T, bool INV, int Ns>
-__device__ __forceinline__ void fft_passes(float2 *buf, const float4 *__restrict__ tw) {
-    if constexpr (Ns < P) {
-        constexpr int R = pick_radix(P / Ns, P / T);
-        stockham_pass<P, T, R, INV>(buf, Ns, tw);
-        fft_passes<P, T, INV, Ns * R>(buf, tw);
+    mid_passes<P, INV, RT, PH>(x, L);
+    // last pass: Ns = T, butterfly j = t, twiddles w_P^{r t}, outputs at t + r T
+    {
+        const float2 *in = phase_buf<P, PH + fft_phases<P>() - 1>(L);
+        const int t2 = opaque_tid();
+#pragma unroll
+        for (int r = 0; r < RT; ++r) x[r] = in[lp<P>(t2 + r * T)];
+#pragma unroll
+        for (int r = 1; r < RT; ++r) x[r] = twmul<INV>(x[r], twid<P>(L, r * t2));
+        Dft<RT, INV>::run(x);
     }
 }
 
-// Z_q = Y_q K1_q - Y_{-q} K2_q in place; each thread owns the pair (q, P-q).
-template <int P, int T>
-__device__ __forceinline__ void chirp_combine(float2 *buf, const float2 *__restrict__ k1,
+// Z_q = Y_q K1_q - Y_{-q} K2_q for the distributed spectrum (one LDS exchange, phase PH).
+template <int P, int PH>
+__device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const LdsBufs &L,
+                                              const float2 *__restrict__ k1,
                                               const float2 *__restrict__ k2) {
-    for (int q = threadIdx.x; q <= P / 2; q += T) {
-        if (q == 0 || q == P / 2) {
-            const float2 y = buf[pad(q)];
-            buf[pad(q)] = cmul(y, csub(ld2(k1, q), ld2(k2, q)));
-        } else {
-            const float2 yq = buf[pad(q)], yr = buf[pad(P - q)];
-            buf[pad(q)] = csub(cmul(yq, ld2(k1, q)), cmul(yr, ld2(k2, q)));
-            buf[pad(P - q)] = csub(cmul(yr, ld2(k1, P - q)), cmul(yq, ld2(k2, P - q)));
-        }
+    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    const int tid = opaque_tid();
+    float2 K1[RT], K2[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        K1[i] = ld2(k1, tid + i * T);
+        K2[i] = ld2(k2, tid + i * T);
+    }
+    before_write<P>();
+    float2 *buf = phase_buf<P, PH>(L);
+#pragma unroll
+    for (int i = 0; i < RT; ++i) buf[lp<P>(tid + i * T)] = x[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        const int qr = (P - (tid + i * T)) & (P - 1);
+        const float2 yr = buf[lp<P>(qr)];
+        x[i] = csub(cmul(x[i], K1[i]), cmul(yr, K2[i]));
+    }
+}
+
+// The chirp-z core of one DST: x <- IFFT(comb(FFT(x))) (unnormalised), x distributed by
+// position; positions 0 and > N must hold zeros on entry.  Phases 0 .. 2F (F = passes - 1);
+// the opening barrier separates them from the previous core's last reads.
+template <int P>
+__device__ __forceinline__ void chirp_core(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, const SolveDesc &d) {
+    constexpr int F = fft_phases<P>();
+    __syncthreads();
+    fft<P, false, 0>(x, L);
+    chirp_combine<P, F>(x, L, d.k1, d.k2);
+    fft<P, true, F + 1>(x, L);
+}
+
+// Load the twiddle octant table into LDS (all threads; ends with a barrier).
+template <int P>
+__device__ __forceinline__ void load_twiddles(float2 *thi, uint32_t *tlo, const uint32_t *tw) {
+    constexpr int O = Cfg<P>::O;
+    for (int e = threadIdx.x; e <= O; e += Cfg<P>::T) {
+        thi[e] = make_float2(__uint_as_float(ldu(tw, 3 * e)), __uint_as_float(ldu(tw, 3 * e + 1)));
+        tlo[e] = ldu(tw, 3 * e + 2);
     }
     __syncthreads();
 }
 
-// The chirp-z core: z = IFFT(comb(FFT(x placed at positions 1..N))) at positions 1..N.
-// x and z are distributed as element i of thread t <-> index m = t + i T (position m+1).
-template <int P, int T>
-__device__ __forceinline__ void chirp_core(float2 *buf, const SolveDesc &d, int N, const float2 *x,
-                                           float2 *z) {
-    constexpr int EPT = (P / 2 + T - 1) / T;
-    const int tid = threadIdx.x;
-    for (int idx = tid; idx < P; idx += T)
-        if (idx == 0 || idx > N) buf[pad(idx)] = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int m = tid + i * T;
-        if (m < N) buf[pad(m + 1)] = x[i];
-    }
-    __syncthreads();
-    fft_passes<P, T, false, 1>(buf, d.tw);
-    chirp_combine<P, T>(buf, d.k1, d.k2);
-    fft_passes<P, T, true, 1>(buf, d.tw);
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int m = tid + i * T;
-        z[i] = (m < N) ? buf[pad(m + 1)] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-}
+#define SSP_LDS_DECL(P)                                                        \
+    __shared__ float2 lds_a[Cfg<P>::DLEN];                                     \
+    __shared__ float2 lds_b[Cfg<P>::PINGPONG ? Cfg<P>::DLEN : 1];              \
+    __shared__ float2 lds_thi[Cfg<P>::O + 1];                                  \
+    __shared__ uint32_t lds_tlo[Cfg<P>::O + 1];                                \
+    const LdsBufs L{lds_a, lds_b, lds_thi, lds_tlo}
 
 // Sum two doubles over the workgroup in a fixed order (wave butterfly, then waves in
 // index order); every thread returns the same values.
@@ -316,35 +428,40 @@ __device__ __forceinline__ float2 carrier(double sigma, long long n) {
     return make_float2(static_cast<float>(c), static_cast<float>(s));
 }
 
-// v(z) = (c0/c)^2 - 1 for the analytic Munk + Gaussian-eddy environment, in FP64.
-__device__ __forceinline__ float analytic_v(const SolveDesc &d, double z, double r) {
-    const double eta = 2.0 * (z - d.env[2]) / d.env[2];
-    double c = d.env[0] * (1.0 + d.env[1] * (eta + exp(-eta) - 1.0));
-    if (d.env[3] != 0.0) {
-        const double xr = (r - d.env[4]) / d.env[5], xz = (z - d.env[6]) / d.env[7];
-        c -= d.env[3] * exp(-(xr * xr) - (xz * xz));
-    }
-    const double q = d.c0 / c;
-    return static_cast<float>(q * q - 1.0);
+// Eddy correction of the potential in the analytic environment.  The range-independent
+// Munk part v_m = (c0/c_m)^2 - 1 comes from the FP64 host table (row 0 of d.v); with
+// e = dc/c_m the full potential is v = (c0/(c_m + dc))^2 - 1 = v_m + (1 + v_m) (-e (2 + e)/(1 + e)^2),
+// a small correction that FP32 evaluates to the precision of the stored table.
+__device__ __forceinline__ float eddy_correction(const SolveDesc &d, float vm, float z, float r) {
+    if (d.env[3] == 0.0) return 0.f;
+    const float xr = (r - static_cast<float>(d.env[4])) / static_cast<float>(d.env[5]);
+    const float xz = (z - static_cast<float>(d.env[6])) / static_cast<float>(d.env[7]);
+    const float dc = -static_cast<float>(d.env[3]) * expf(-(xr * xr) - (xz * xz));
+    const float q = 1.0f + vm;                                // (c0/c_m)^2
+    const float cm = static_cast<float>(d.c0) * rsqrtf(q);    // c_m
+    const float e = dc / cm;
+    return q * (-e * (2.0f + e) / ((1.0f + e) * (1.0f + e)));
 }
 
-template <int P, int T>
-__device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, float2 *A) {
-    constexpr int EPT = (P / 2 + T - 1) / T;
+// A = v (.) dmod at the thread's positions (zero outside 1..N); v of global step n.
+template <int P>
+__device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, float2 (&A)[Cfg<P>::RT]) {
+    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
     const int N = d.N;
     long long row = 0;
     if (d.prof_mode == PROF_TABLE_STEPS) {
         row = n - d.v_step0 - 1;
         row = row < 0 ? 0 : (row >= d.v_rows ? d.v_rows - 1 : row);
     }
-    const double r = (static_cast<double>(n) - 0.5) * d.dr;
+    const float *vrow = d.v + row * N;
+    const float r = static_cast<float>((static_cast<double>(n) - 0.5) * d.dr);
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int m = threadIdx.x + i * T;
-        if (m < N) {
-            const float v = (d.prof_mode == PROF_ANALYTIC)
-                                ? analytic_v(d, (m + 1) * d.dz, r)
-                                : ldf(d.v + row * N, m);
+    for (int i = 0; i < RT; ++i) {
+        const int pos = opaque_tid() + i * T, m = pos - 1;
+        if (pos >= 1 && pos <= N) {
+            float v = ldf(vrow, m);
+            if (d.prof_mode == PROF_ANALYTIC)
+                v += eddy_correction(d, v, static_cast<float>(pos * d.dz), r);
             const float2 dm = ld2(d.dmod, m);
             A[i] = make_float2(v * dm.x, v * dm.y);
         } else {
@@ -354,26 +471,28 @@ __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, 
 }
 
 // ----------------------------------------------------------------------------- march
-template <int P, int T>
-__global__ __launch_bounds__(T) void k_march(const SolveDesc *__restrict__ descs, int nsteps) {
-    __shared__ float2 buf[lds_len(P)];
+// One workgroup marches one solve (descriptor blockIdx.x) through nsteps range steps.
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict__ descs, int nsteps) {
+    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    // the Neumann multiplier stays in registers for up to 8 elements per thread
+    constexpr bool kBInRegs = (RT <= 8) && (T < 1024);
+    constexpr int EB = kBInRegs ? RT : 1;
+    SSP_LDS_DECL(P);
     __shared__ double red[2 * (T / 64)];
-    constexpr int EPT = (P / 2 + T - 1) / T;
-    // large fields keep the Neumann multiplier in L2 instead of registers
-    constexpr bool kBInRegs = (EPT <= 4);
-    constexpr int EB = kBInRegs ? EPT : 1;
     const SolveDesc &d = descs[blockIdx.x];
     const int tid = threadIdx.x;
     const int N = d.N, p = d.p, nmax = d.nmax;
+    load_twiddles<P>(lds_thi, lds_tlo, d.tw);
 
     // The state u is not held in registers: d.field holds the state at the start of the
     // step (the recovery point if the step diverges) and d.work the state between Pade
-    // factors.  Every thread reads and writes only its own elements m = tid + i T, so these
-    // global accesses need no barriers.
-    float2 w[EPT], a[EPT], A[EPT];
+    // factors.  Every thread reads and writes only its own positions, so these global
+    // accesses need no barriers.
+    float2 w[RT], a[RT], A[RT];
     float4 Bm[EB];
     long long n = *d.step;
-    if (d.prof_mode == PROF_TABLE_FIXED) load_potential<P, T>(d, n + 1, A);
+    if (d.prof_mode == PROF_TABLE_FIXED) load_potential<P>(d, n + 1, A);
 
     long long terms = 0, done = 0;
     int max_used = 0, notconv = 0, status = kOK;
@@ -381,15 +500,15 @@ __global__ __launch_bounds__(T) void k_march(const SolveDesc *__restrict__ descs
 
     for (int s = 0; s < nsteps; ++s) {
         const long long nn = n + 1;
-        if (d.prof_mode != PROF_TABLE_FIXED) load_potential<P, T>(d, nn, A);
+        if (d.prof_mode != PROF_TABLE_FIXED) load_potential<P>(d, nn, A);
         bool bad = false;
         for (int j = 0; j < p; ++j) {
             const float2 *cur = (j == 0) ? d.field : d.work;
             double t0 = 0.0, dummy = 0.0;
 #pragma unroll
-            for (int i = 0; i < EPT; ++i) {
-                const int m = tid + i * T;
-                if (m < N) {
+            for (int i = 0; i < RT; ++i) {
+                const int pos = opaque_tid() + i * T, m = pos - 1;
+                if (pos >= 1 && pos <= N) {
                     a[i] = cmul_df(ld2(cur, m), ld4(d.s, j * N + m));
                     if constexpr (kBInRegs) Bm[i] = ld4(d.bmul, j * N + m);
                 } else {
@@ -403,26 +522,31 @@ __global__ __launch_bounds__(T) void k_march(const SolveDesc *__restrict__ descs
             double tn = 0.0, wn = 0.0;
             int used = 0;
             bool conv = (nmax == 0);
-            for (int it = 1; it <= nmax; ++it) {
-                chirp_core<P, T>(buf, d, N, a, a);
+            // half-iteration h: even -> a = A (.) S a (multiply by v); odd -> a = B_j (.) S a
+            // (diagonal solve) and the term is accumulated; one transform site per loop
+            for (int h = 0; h < 2 * nmax; ++h) {
+                chirp_core<P>(a, L, d);
+                if ((h & 1) == 0) {
 #pragma unroll
-                for (int i = 0; i < EPT; ++i) a[i] = cmul(A[i], a[i]);
-                chirp_core<P, T>(buf, d, N, a, a);
+                    for (int i = 0; i < RT; ++i) a[i] = cmul(A[i], a[i]);
+                    continue;
+                }
                 tn = 0.0;
                 wn = 0.0;
 #pragma unroll
-                for (int i = 0; i < EPT; ++i) {
-                    const int m = tid + i * T;
+                for (int i = 0; i < RT; ++i) {
+                    const int pos = opaque_tid() + i * T;
                     float4 bm;
                     if constexpr (kBInRegs) bm = Bm[i];
-                    else bm = (m < N) ? ld4(d.bmul, j * N + m) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    else bm = (pos >= 1 && pos <= N) ? ld4(d.bmul, j * N + pos - 1)
+                                                     : make_float4(0.f, 0.f, 0.f, 0.f);
                     a[i] = cmul_df(a[i], bm);
                     w[i] = cadd(w[i], a[i]);
                     tn += cnorm2(a[i]);
                     wn += cnorm2(w[i]);
                 }
                 block_sum2<T>(tn, wn, red);
-                used = it;
+                used = (h >> 1) + 1;
                 if (!(isfinite(tn) && isfinite(wn))) {
                     bad = true;
                     break;
@@ -449,9 +573,9 @@ __global__ __launch_bounds__(T) void k_march(const SolveDesc *__restrict__ descs
             // product-form factor: u <- g_j u + (1 - g_j) w_j  (alpha, beta double-float)
             const float4 al = ld4(d.alpha, j), be = ld4(d.beta, j);
 #pragma unroll
-            for (int i = 0; i < EPT; ++i) {
-                const int m = tid + i * T;
-                if (m < N) st2(d.work, m, cadd(cmul_df(ld2(cur, m), al), cmul_df(w[i], be)));
+            for (int i = 0; i < RT; ++i) {
+                const int pos = opaque_tid() + i * T, m = pos - 1;
+                if (pos >= 1 && pos <= N) st2(d.work, m, cadd(cmul_df(ld2(cur, m), al), cmul_df(w[i], be)));
             }
         }
         if (bad) {
@@ -460,31 +584,21 @@ __global__ __launch_bounds__(T) void k_march(const SolveDesc *__restrict__ descs
         }
         // commit the step
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int m = tid + i * T;
-            if (m < N) st2(d.field, m, ld2(d.work, m));
+        for (int i = 0; i < RT; ++i) {
+            const int pos = opaque_tid() + i * T, m = pos - 1;
+            if (pos >= 1 && pos <= N) st2(d.field, m, ld2(d.work, m));
         }
         n = nn;
         ++done;
-        if (d.out_every > 0 && (n % d.out_every) == 0 && (d.tl_out || d.fld_out)) {
-            float2 *z = w;  // w is free between steps
-#pragma unroll
-            for (int i = 0; i < EPT; ++i) {
-                const int m = tid + i * T;
-                z[i] = (m < N) ? ld2(d.field, m) : make_float2(0.f, 0.f);
-            }
-            chirp_core<P, T>(buf, d, N, z, z);
-            const float2 car = carrier(d.sigma, n);
+        // output step: keep a snapshot of the sine-basis state; k_output turns it into the
+        // physical field and TL after the march
+        if (d.out_every > 0 && (n % d.out_every) == 0 && d.snap) {
             const long long slot = (n - d.out_base) / d.out_every;
-            const bool in_range = (n >= d.out_base) && (slot < d.nout);
-            const float lr = log10f(static_cast<float>(static_cast<double>(n) * d.dr));
+            if (n >= d.out_base && slot < d.nout) {
 #pragma unroll
-            for (int i = 0; i < EPT; ++i) {
-                const int m = tid + i * T;
-                if (m < N && in_range) {
-                    const float2 ph = cmul(cmul(ld2(d.post, m), z[i]), car);
-                    if (d.fld_out) st2(d.fld_out + slot * N, m, ph);
-                    if (d.tl_out) stf(d.tl_out + slot * N, m, -10.0f * (log10f(ph.x * ph.x + ph.y * ph.y) - lr));
+                for (int i = 0; i < RT; ++i) {
+                    const int pos = opaque_tid() + i * T, m = pos - 1;
+                    if (pos >= 1 && pos <= N) st2(d.snap + slot * N, m, ld2(d.field, m));
                 }
             }
         }
@@ -506,73 +620,104 @@ __global__ __launch_bounds__(T) void k_march(const SolveDesc *__restrict__ descs
 }
 
 // ----------------------------------------------------------------------------- transforms
-template <int P, int T>
-__global__ __launch_bounds__(T) void k_transform(const SolveDesc *__restrict__ desc, int mode,
-                                                 const float2 *__restrict__ in, float2 *out,
-                                                 const long long *__restrict__ step) {
-    __shared__ float2 buf[lds_len(P)];
-    constexpr int EPT = (P / 2 + T - 1) / T;
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::T) void k_transform(const SolveDesc *__restrict__ desc, int mode,
+                                                         const float2 *__restrict__ in, float2 *out,
+                                                         const long long *__restrict__ step) {
+    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    SSP_LDS_DECL(P);
     const SolveDesc &d = *desc;
     const int N = d.N, tid = threadIdx.x;
-    const size_t off = static_cast<size_t>(blockIdx.x) * N;
-    float2 x[EPT], z[EPT];
+    load_twiddles<P>(lds_thi, lds_tlo, d.tw);
+    const float2 *vin = in + static_cast<size_t>(blockIdx.x) * N;
+    float2 *vout = out + static_cast<size_t>(blockIdx.x) * N;
+    float2 x[RT];
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int m = tid + i * T;
-        float2 v = (m < N) ? ld2(in + off, m) : make_float2(0.f, 0.f);
-        if (mode != 2 && m < N) v = cmul(v, ld2(d.pre, m));
+    for (int i = 0; i < RT; ++i) {
+        const int pos = opaque_tid() + i * T, m = pos - 1;
+        float2 v = make_float2(0.f, 0.f);
+        if (pos >= 1 && pos <= N) {
+            v = ld2(vin, m);
+            if (mode != 2) v = cmul(v, ld2(d.pre, m));
+        }
         x[i] = v;
     }
-    chirp_core<P, T>(buf, d, N, x, z);
+    chirp_core<P>(x, L, d);
     float2 car = make_float2(1.f, 0.f);
-    if (mode == 2) {
-        car = carrier(d.sigma, step[blockIdx.x]);
-    }
+    if (mode == 2) car = carrier(d.sigma, step[blockIdx.x]);
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int m = tid + i * T;
-        if (m < N) {
-            float2 v = cmul(z[i], mode == 1 ? ld2(d.dmod, m) : ld2(d.post, m));
+    for (int i = 0; i < RT; ++i) {
+        const int pos = opaque_tid() + i * T, m = pos - 1;
+        if (pos >= 1 && pos <= N) {
+            float2 v = cmul(x[i], mode == 1 ? ld2(d.dmod, m) : ld2(d.post, m));
             if (mode == 2) v = cmul(v, car);
-            st2(out + off, m, v);
+            st2(vout, m, v);
         }
     }
 }
 
-// workgroup size per FFT length: enough waves to hide LDS latency, <= 1024 threads
+// Output rows: blockIdx.x = solve * nout + row.  Snapshot (sine basis) -> physical field
+// with the carrier of its step -> field row (complex64, in place over the snapshot when
+// fld_out == snap) and TL row.
 template <int P>
-constexpr int threads_for() {
-    return P <= 256 ? 64 : (P <= 1024 ? 128 : (P <= 4096 ? 256 : 1024));
+__global__ __launch_bounds__(Cfg<P>::T) void k_output(const SolveDesc *__restrict__ descs, int nout) {
+    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    SSP_LDS_DECL(P);
+    const int b = blockIdx.x / nout, row = blockIdx.x % nout;
+    const SolveDesc &d = descs[b];
+    if (row >= d.nout || !d.snap) return;  // uniform over the workgroup
+    const int N = d.N, tid = threadIdx.x;
+    load_twiddles<P>(lds_thi, lds_tlo, d.tw);
+    const long long n = d.out_base + static_cast<long long>(row) * d.out_every;
+    const float2 *src = d.snap + static_cast<size_t>(row) * N;
+    float2 x[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        const int pos = tid + i * T;
+        x[i] = (pos >= 1 && pos <= N) ? ld2(src, pos - 1) : make_float2(0.f, 0.f);
+    }
+    chirp_core<P>(x, L, d);
+    const float2 car = carrier(d.sigma, n);
+    const float lr = log10f(static_cast<float>(static_cast<double>(n) * d.dr));
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        const int pos = tid + i * T, m = pos - 1;
+        if (pos >= 1 && pos <= N) {
+            const float2 ph = cmul(cmul(ld2(d.post, m), x[i]), car);
+            if (d.fld_out) st2(d.fld_out + static_cast<size_t>(row) * N, m, ph);
+            if (d.tl_out) stf(d.tl_out + static_cast<size_t>(row) * N, m, -10.0f * (log10f(ph.x * ph.x + ph.y * ph.y) - lr));
+        }
+    }
+}
+
+template <int P>
+hipError_t launch_output_P(const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream) {
+    hipLaunchKernelGGL((k_output<P>), dim3(nsolves * nout), dim3(Cfg<P>::T), 0, stream, d_descs, nout);
+    return hipGetLastError();
 }
 
 template <int P>
 hipError_t launch_march_P(const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
-    constexpr int T = threads_for<P>();
-    hipLaunchKernelGGL((k_march<P, T>), dim3(nsolves), dim3(T), 0, stream, d_descs, nsteps);
+    hipLaunchKernelGGL((k_march<P>), dim3(nsolves), dim3(Cfg<P>::T), 0, stream, d_descs, nsteps);
     return hipGetLastError();
 }
 
 template <int P>
 hipError_t launch_transform_P(int mode, const SolveDesc *d_desc, int B, const float2 *in,
                               float2 *out, const long long *step, hipStream_t stream) {
-    constexpr int T = threads_for<P>();
-    hipLaunchKernelGGL((k_transform<P, T>), dim3(B), dim3(T), 0, stream, d_desc, mode, in, out, step);
+    hipLaunchKernelGGL((k_transform<P>), dim3(B), dim3(Cfg<P>::T), 0, stream, d_desc, mode, in, out, step);
     return hipGetLastError();
 }
 
 }  // namespace
 
 bool fft_length_supported(int P) {
-    return P == 8 || P == 16 || P == 32 || P == 64 || P == 128 || P == 256 || P == 512 ||
-           P == 1024 || P == 2048 || P == 4096 || P == 8192 || P == 16384;
+    return P == 128 || P == 256 || P == 512 || P == 1024 || P == 2048 || P == 4096 || P == 8192 ||
+           P == 16384;
 }
 
 #define SSP_DISPATCH_P(P, CALL) \
     switch (P) {                \
-        case 8: return CALL(8);         \
-        case 16: return CALL(16);       \
-        case 32: return CALL(32);       \
-        case 64: return CALL(64);       \
         case 128: return CALL(128);     \
         case 256: return CALL(256);     \
         case 512: return CALL(512);     \
@@ -589,6 +734,13 @@ hipError_t launch_march(int P, const SolveDesc *d_descs, int nsolves, int nsteps
 #define CALL_M(PP) launch_march_P<PP>(d_descs, nsolves, nsteps, stream)
     SSP_DISPATCH_P(P, CALL_M)
 #undef CALL_M
+}
+
+hipError_t launch_output(int P, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream) {
+    if (nsolves <= 0 || nout <= 0) return hipSuccess;
+#define CALL_O(PP) launch_output_P<PP>(d_descs, nsolves, nout, stream)
+    SSP_DISPATCH_P(P, CALL_O)
+#undef CALL_O
 }
 
 hipError_t launch_transform(int P, int mode, const SolveDesc *d_desc, int B, const float2 *in,

@@ -9,11 +9,24 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <numeric>
 
 namespace ssp {
 
 namespace {
+
+uint32_t float_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return u;
+}
+// nearest bfloat16 (round half to even) of a finite float, as its 16-bit pattern
+uint16_t bf16_round(float f) {
+    uint32_t u = float_bits(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
 
 const long double kPi = 3.141592653589793238462643383279502884L;
 
@@ -251,7 +264,7 @@ void host_fft(std::vector<cd> &x, int sign) {
 }
 
 int chirp_fft_length(int n_min) {
-    int P = 8;  // smallest length of the device FFT
+    int P = 128;  // smallest length of the device FFT (two waves of butterflies)
     while (P < n_min) P *= 2;
     return P;
 }
@@ -297,12 +310,17 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, DeviceTabl
         t.dmod[2 * (n - 1)] = static_cast<float>(dmod[n - 1].real());
         t.dmod[2 * (n - 1) + 1] = static_cast<float>(dmod[n - 1].imag());
     }
-    t.twiddle.resize(4 * P);
-    for (int e = 0; e < P; ++e) {
+    const int O = P / 8;
+    t.twiddle.resize(3 * static_cast<size_t>(O + 1));
+    for (int e = 0; e <= O; ++e) {
         long double ang = -2 * kPi * static_cast<long double>(e) / P;
         double re = static_cast<double>(std::cos(ang)), im = static_cast<double>(std::sin(ang));
-        split_df(re, t.twiddle[4 * e], t.twiddle[4 * e + 2]);
-        split_df(im, t.twiddle[4 * e + 1], t.twiddle[4 * e + 3]);
+        float hr, lr, hi, li;
+        split_df(re, hr, lr);
+        split_df(im, hi, li);
+        t.twiddle[3 * e] = float_bits(hr);
+        t.twiddle[3 * e + 1] = float_bits(hi);
+        t.twiddle[3 * e + 2] = (static_cast<uint32_t>(bf16_round(lr)) << 16) | bf16_round(li);
     }
     const int p = ps.p;
     t.s.resize(static_cast<size_t>(4) * p * N);

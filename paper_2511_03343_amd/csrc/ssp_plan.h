@@ -47,7 +47,10 @@ struct DeviceTables {
     std::vector<float> pre;           // [nz] complex FP32  conj(c_n)
     std::vector<float> post;          // [nz] complex FP32  conj(c_k) (i/2) sqrt(2/(nz+1)) / P
     std::vector<float> dmod;          // [nz] complex FP32  conj(c_k)^2 (i/2) sqrt(2/(nz+1)) / P
-    std::vector<float> twiddle;       // [P] double-float complex exp(-2 pi i e / P): hi.re hi.im lo.re lo.im
+    // exp(-2 pi i e / P) for e = 0..P/8 (the first octant; the device rebuilds the other
+    // octants by symmetry): per entry hi.re, hi.im (FP32 bit patterns) and the rounding
+    // remainders lo.re, lo.im packed as two bfloat16 (re in the high half)
+    std::vector<uint32_t> twiddle;
     // Pade factors in the chirp-modulated sine basis:
     std::vector<float> s;             // [p][nz] double-float complex 1/(1 + b_j x_l)
     std::vector<float> bmul;          // [p][nz] double-float complex -b_j s_jl * dmod_l (FP64 product)

