@@ -312,7 +312,7 @@ ssp_status ssp_plan_create(int Nz, double H, double f, double c0, double dr, int
     if (st == SSP_OK) {
         hipError_t e = hipSuccess;
         if (e == hipSuccess) e = dev_alloc(&pl->d_field, Nz);
-        if (e == hipSuccess) e = dev_alloc(&pl->d_work, Nz);
+        if (e == hipSuccess) e = dev_alloc(&pl->d_work, 2 * static_cast<size_t>(Nz));
         if (e == hipSuccess) e = dev_alloc(&pl->d_step, 1);
         if (e == hipSuccess) e = dev_alloc(&pl->d_stats, 1);
         if (e == hipSuccess) e = dev_alloc(&pl->d_desc, 1);
@@ -559,6 +559,7 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
         ssp::SolveDesc d = base_desc(pl);
         d.field = pl->d_field;
         d.work = pl->d_work;
+        d.pot = pl->d_work + pl->N;
         d.step = pl->d_step;
         d.nout = nout[i];
         d.stats = pl->d_stats;
@@ -648,7 +649,7 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
     if (pl->bwork_cap < B) {
         dev_free(pl->d_bwork);
         pl->bwork_cap = 0;
-        HIP_TRY(dev_alloc(&pl->d_bwork, static_cast<size_t>(B) * pl->N));
+        HIP_TRY(dev_alloc(&pl->d_bwork, 2 * static_cast<size_t>(B) * pl->N));
         pl->bwork_cap = B;
     }
     std::vector<ssp::SolveDesc> descs(B);
@@ -663,7 +664,8 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
     for (int b = 0; b < B; ++b) {
         ssp::SolveDesc d = base_desc(pl);
         d.field = static_cast<float2 *>(d_psi) + static_cast<size_t>(b) * pl->N;
-        d.work = pl->d_bwork + static_cast<size_t>(b) * pl->N;
+        d.work = pl->d_bwork + 2 * static_cast<size_t>(b) * pl->N;
+        d.pot = d.work + pl->N;
         d.nout = nout;
         d.step = static_cast<long long *>(d_step) + b;
         d.stats = d_stats ? static_cast<ssp::DevStats *>(d_stats) + b : nullptr;

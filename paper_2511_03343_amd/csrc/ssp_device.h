@@ -39,6 +39,7 @@ struct SolveDesc {
     double env[8];              // analytic environment (ssp_env order)
     float2 *field;              // [N] sine-basis state (modulated representation)
     float2 *work;               // [N] scratch state between Pade factors
+    float2 *pot;                // [N] scratch potential A = v (.) dmod of the current step
     long long *step;            // global step counter
     DevStats *stats;
     float2 *snap;               // [nout][N] sine-basis snapshots at output steps, or null

@@ -171,30 +171,132 @@ __device__ __forceinline__ int opaque_tid() {
 // middle passes are self-sorting (Stockham) radix passes through LDS:
 //   butterfly j (k = j mod Ns) reads positions j + r P/R, multiplies by w_{Ns R}^{r k},
 //   takes the R-point DFT and writes positions (j - k) R + k + r Ns.
-// LDS: padded index (one slot per 2^PADSH elements, spreads power-of-two strides over the
-// banks); two data buffers when they fit (one barrier per exchange), else one; twiddles
-// w_P^e from a first-octant table rebuilt by symmetry, double-float (FP32 + bf16 rest).
+// Because T is a multiple of every middle stride Ns, a thread's k is t mod Ns in every
+// pass, so its twiddles are the same in every transform of a launch: they are computed
+// once per launch and held in registers (double-float: FP32 value + bf16 pair remainder).
+// LDS: padded index (one slot per 16 elements, spreads power-of-two strides over the
+// banks); two data buffers when they fit (one barrier per exchange), else one.
 template <int P>
 struct Cfg {
     static constexpr int T = P <= 512 ? 64 : (P == 1024 ? 128 : (P <= 4096 ? 256 : 1024));
     static constexpr int RT = P / T;
-    static constexpr int PADSH = P >= 16384 ? 5 : 4;
+    static constexpr int PADSH = 4;
     static constexpr int DLEN = P + (P >> PADSH);
     static constexpr int O = P / 8;
     static constexpr int LOG2O = __builtin_ctz(P / 8);
-    static constexpr bool PINGPONG = (2 * DLEN * 8 + (O + 1) * 12 + 512) <= 160 * 1024;
+    static constexpr bool PINGPONG = (2 * DLEN * 8 + 12 * T + 1024) <= 160 * 1024;
 };
 
 template <int P>
 __device__ __forceinline__ int lp(int i) { return i + (i >> Cfg<P>::PADSH); }
 
-// LDS of one transform.  Exchange phase k (a write, a barrier, then reads) uses buffer k mod 2
-// (buffer 0 only when two do not fit), chosen at compile time so that every access is a
-// plain ds_read/ds_write.
+// radix of the middle pass at stride Ns
+template <int P, int Ns>
+constexpr int mid_radix() {
+    return (Cfg<P>::T / Ns) < Cfg<P>::RT ? (Cfg<P>::T / Ns) : Cfg<P>::RT;
+}
+template <int P, int Ns>
+constexpr int mid_count_from() {
+    if constexpr (Ns >= Cfg<P>::T) {
+        return 0;
+    } else {
+        return 1 + mid_count_from<P, Ns * mid_radix<P, Ns>()>();
+    }
+}
+template <int P>
+constexpr int fft_phases() { return 1 + mid_count_from<P, Cfg<P>::RT>(); }
+
+// entries of the middle-pass twiddle table from stride Ns on: Ns (R - 1) per pass
+template <int P, int Ns>
+constexpr int mid_tab_from() {
+    if constexpr (Ns >= Cfg<P>::T) {
+        return 0;
+    } else {
+        constexpr int R = mid_radix<P, Ns>();
+        return Ns * (R - 1) + mid_tab_from<P, Ns * R>();
+    }
+}
+template <int P>
+constexpr int mid_tab_len() { return mid_tab_from<P, Cfg<P>::RT>(); }
+template <int P, int Ns>
+constexpr int mid_tab_offset() { return mid_tab_len<P>() - mid_tab_from<P, Ns>(); }
+
+// Twiddles of the last pass (w_P^{r t}, r = 1..RT-1): per thread, held in registers.
+template <int P>
+struct Twiddles {
+    static constexpr int NTW = Cfg<P>::RT - 1;
+    float2 h[NTW];   // FP32 nearest value
+    uint32_t l[NTW]; // remainder as two bf16 (re high, im low)
+};
+
+// w_P^e (forward sign), e in [0, P), from the first-octant table in global memory:
+// entry e' = e mod P/8 (mirrored for odd octants), rotated by (-i)^q.
+template <int P>
+__device__ __forceinline__ void fetch_twiddle(const uint32_t *tab, int e, float2 &h, uint32_t &l) {
+    constexpr int O = Cfg<P>::O;
+    const int o = e >> Cfg<P>::LOG2O, r = e & (O - 1);
+    const bool odd = o & 1;
+    const int idx = odd ? O - r : r;
+    float hr = __uint_as_float(ldu(tab, 3 * idx)), hi = __uint_as_float(ldu(tab, 3 * idx + 1));
+    const uint32_t pk = ldu(tab, 3 * idx + 2);
+    float lr = __uint_as_float(pk & 0xffff0000u), li = __uint_as_float(pk << 16);
+    if (odd) {
+        hi = -hi;
+        li = -li;
+    }
+    const int q = ((o + (odd ? 1 : 0)) >> 1) & 3;
+    float a = hr, b = hi, c = lr, dd = li;
+    if (q == 1) { a = hi; b = -hr; c = li; dd = -lr; }
+    else if (q == 2) { a = -hr; b = -hi; c = -lr; dd = -li; }
+    else if (q == 3) { a = -hi; b = hr; c = -li; dd = lr; }
+    h = make_float2(a, b);
+    // c and dd are exact bfloat16 values: repack them
+    l = (__float_as_uint(c) & 0xffff0000u) | (__float_as_uint(dd) >> 16);
+}
+
+// Middle-pass table in LDS: pass at stride Ns holds w_{Ns R}^{r k} at
+// offset(Ns) + (r - 1) Ns + k, so lanes with consecutive k read consecutive entries.
+template <int P, int Ns>
+__device__ __forceinline__ void init_mid_table(float2 *th, uint32_t *tl, const uint32_t *tab) {
+    if constexpr (Ns < Cfg<P>::T) {
+        constexpr int R = mid_radix<P, Ns>();
+        constexpr int OFF = mid_tab_offset<P, Ns>();
+        constexpr int STRIDE = P / (Ns * R);
+        for (int idx = threadIdx.x; idx < Ns * (R - 1); idx += Cfg<P>::T) {
+            const int r = idx / Ns + 1, k = idx & (Ns - 1);
+            float2 h;
+            uint32_t l;
+            fetch_twiddle<P>(tab, r * k * STRIDE, h, l);
+            th[OFF + idx] = h;
+            tl[OFF + idx] = l;
+        }
+        init_mid_table<P, Ns * R>(th, tl, tab);
+    }
+}
+
+// All twiddles of a launch: the middle-pass table (LDS, ends with a barrier) and the
+// thread's last-pass twiddles (registers).
+template <int P>
+__device__ __forceinline__ void init_twiddles(Twiddles<P> &tw, float2 *th, uint32_t *tl, const uint32_t *tab) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int r = 1; r < Cfg<P>::RT; ++r) fetch_twiddle<P>(tab, r * tid, tw.h[r - 1], tw.l[r - 1]);
+    init_mid_table<P, Cfg<P>::RT>(th, tl, tab);
+    __syncthreads();
+}
+
+template <bool INV>
+__device__ __forceinline__ float2 twmul(float2 x, float2 h, uint32_t l) {
+    const float4 w = make_float4(h.x, h.y, __uint_as_float(l & 0xffff0000u), __uint_as_float(l << 16));
+    return INV ? cmul_df_conj(x, w) : cmul_df(x, w);
+}
+
+// LDS data buffers of one transform.  Exchange phase k (a write, a barrier, then reads)
+// uses buffer k mod 2 (buffer 0 only when two do not fit), chosen at compile time.
 struct LdsBufs {
     float2 *b0, *b1;
-    const float2 *thi;
-    const uint32_t *tlo;
+    const float2 *th;   // middle-pass twiddle table
+    const uint32_t *tl;
 };
 
 template <int P, int PH>
@@ -207,55 +309,16 @@ __device__ __forceinline__ void before_write() {
     if constexpr (!Cfg<P>::PINGPONG) __syncthreads();
 }
 
-// w_P^e, e in [0, P): first-octant table entry, mirrored for odd octants, rotated by (-i)^q
-template <int P>
-__device__ __forceinline__ float4 twid(const LdsBufs &L, int e) {
-    constexpr int O = Cfg<P>::O;
-    const int o = e >> Cfg<P>::LOG2O, r = e & (O - 1);
-    const bool odd = o & 1;
-    const int idx = odd ? O - r : r;
-    const float2 h = L.thi[idx];
-    const uint32_t l = L.tlo[idx];
-    float hr = h.x, hi = odd ? -h.y : h.y;
-    float lr = __uint_as_float(l & 0xffff0000u), li = __uint_as_float(l << 16);
-    if (odd) li = -li;
-    const int q = ((o + (odd ? 1 : 0)) >> 1) & 3;
-    float4 w;
-    if (q == 0) w = make_float4(hr, hi, lr, li);
-    else if (q == 1) w = make_float4(hi, -hr, li, -lr);
-    else if (q == 2) w = make_float4(-hr, -hi, -lr, -li);
-    else w = make_float4(-hi, hr, -li, lr);
-    return w;
-}
-
-template <bool INV>
-__device__ __forceinline__ float2 twmul(float2 x, float4 w) {
-    return INV ? cmul_df_conj(x, w) : cmul_df(x, w);
-}
-
-// Number of LDS exchange phases of one FFT (passes - 1).
-template <int P, int Ns>
-constexpr int mid_count() {
-    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
-    if constexpr (Ns >= T) {
-        return 0;
-    } else {
-        constexpr int R = (T / Ns) < RT ? (T / Ns) : RT;
-        return 1 + mid_count<P, Ns * R>();
-    }
-}
-template <int P>
-constexpr int fft_phases() { return 1 + mid_count<P, Cfg<P>::RT>(); }
-
 // middle passes: read phase PH, write phase PH + 1; Ns = current stride until it reaches T
 template <int P, bool INV, int Ns, int PH>
-__device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBufs &L) {
+__device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBufs &L,
+                                           const Twiddles<P> &tw) {
     constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
     if constexpr (Ns < T) {
-        constexpr int R = (T / Ns) < RT ? (T / Ns) : RT;
+        constexpr int R = mid_radix<P, Ns>();
         constexpr int PER = RT / R;
         constexpr int NB = P / R;
-        constexpr int STRIDE = P / (Ns * R);
+        constexpr int OFF = mid_tab_offset<P, Ns>();
         const int tid = opaque_tid();
         const float2 *in = phase_buf<P, PH>(L);
 #pragma unroll
@@ -272,21 +335,22 @@ __device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBuf
             const int k = j & (Ns - 1);
             float2 *v = &x[i * R];
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[r] = twmul<INV>(v[r], twid<P>(L, r * k * STRIDE));
+            for (int r = 1; r < R; ++r)
+                v[r] = twmul<INV>(v[r], L.th[OFF + (r - 1) * Ns + k], L.tl[OFF + (r - 1) * Ns + k]);
             Dft<R, INV>::run(v);
             const int base = (j - k) * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) out[lp<P>(base + r * Ns)] = v[r];
         }
         __syncthreads();
-        mid_passes<P, INV, Ns * R, PH + 1>(x, L);
+        mid_passes<P, INV, Ns * R, PH + 1>(x, L, tw);
     }
 }
 
 // Full FFT of the distributed vector x (registers in, registers out); its first exchange
 // uses phase PH.
 template <int P, bool INV, int PH>
-__device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L) {
+__device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, const Twiddles<P> &tw) {
     constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
     const int tid = opaque_tid();
     // first pass: Ns = 1, butterfly j = t on positions t + r T
@@ -298,7 +362,7 @@ __device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L) {
         for (int r = 0; r < RT; ++r) out[lp<P>(tid * RT + r)] = x[r];
     }
     __syncthreads();
-    mid_passes<P, INV, RT, PH>(x, L);
+    mid_passes<P, INV, RT, PH>(x, L, tw);
     // last pass: Ns = T, butterfly j = t, twiddles w_P^{r t}, outputs at t + r T
     {
         const float2 *in = phase_buf<P, PH + fft_phases<P>() - 1>(L);
@@ -306,7 +370,8 @@ __device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L) {
 #pragma unroll
         for (int r = 0; r < RT; ++r) x[r] = in[lp<P>(t2 + r * T)];
 #pragma unroll
-        for (int r = 1; r < RT; ++r) x[r] = twmul<INV>(x[r], twid<P>(L, r * t2));
+        for (int r = 1; r < RT; ++r)
+            x[r] = twmul<INV>(x[r], tw.h[r - 1], tw.l[r - 1]);
         Dft<RT, INV>::run(x);
     }
 }
@@ -318,22 +383,18 @@ __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const Lds
                                               const float2 *__restrict__ k2) {
     constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
     const int tid = opaque_tid();
-    float2 K1[RT], K2[RT];
-#pragma unroll
-    for (int i = 0; i < RT; ++i) {
-        K1[i] = ld2(k1, tid + i * T);
-        K2[i] = ld2(k2, tid + i * T);
-    }
     before_write<P>();
     float2 *buf = phase_buf<P, PH>(L);
 #pragma unroll
     for (int i = 0; i < RT; ++i) buf[lp<P>(tid + i * T)] = x[i];
     __syncthreads();
+    const int t2 = opaque_tid();
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-        const int qr = (P - (tid + i * T)) & (P - 1);
+        const int q = t2 + i * T;
+        const int qr = (P - q) & (P - 1);
         const float2 yr = buf[lp<P>(qr)];
-        x[i] = csub(cmul(x[i], K1[i]), cmul(yr, K2[i]));
+        x[i] = csub(cmul(x[i], ld2(k1, q)), cmul(yr, ld2(k2, q)));
     }
 }
 
@@ -341,31 +402,21 @@ __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const Lds
 // position; positions 0 and > N must hold zeros on entry.  Phases 0 .. 2F (F = passes - 1);
 // the opening barrier separates them from the previous core's last reads.
 template <int P>
-__device__ __forceinline__ void chirp_core(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, const SolveDesc &d) {
+__device__ __forceinline__ void chirp_core(float2 (&x)[Cfg<P>::RT], const LdsBufs &L,
+                                           const Twiddles<P> &tw, const SolveDesc &d) {
     constexpr int F = fft_phases<P>();
     __syncthreads();
-    fft<P, false, 0>(x, L);
+    fft<P, false, 0>(x, L, tw);
     chirp_combine<P, F>(x, L, d.k1, d.k2);
-    fft<P, true, F + 1>(x, L);
-}
-
-// Load the twiddle octant table into LDS (all threads; ends with a barrier).
-template <int P>
-__device__ __forceinline__ void load_twiddles(float2 *thi, uint32_t *tlo, const uint32_t *tw) {
-    constexpr int O = Cfg<P>::O;
-    for (int e = threadIdx.x; e <= O; e += Cfg<P>::T) {
-        thi[e] = make_float2(__uint_as_float(ldu(tw, 3 * e)), __uint_as_float(ldu(tw, 3 * e + 1)));
-        tlo[e] = ldu(tw, 3 * e + 2);
-    }
-    __syncthreads();
+    fft<P, true, F + 1>(x, L, tw);
 }
 
 #define SSP_LDS_DECL(P)                                                        \
     __shared__ float2 lds_a[Cfg<P>::DLEN];                                     \
     __shared__ float2 lds_b[Cfg<P>::PINGPONG ? Cfg<P>::DLEN : 1];              \
-    __shared__ float2 lds_thi[Cfg<P>::O + 1];                                  \
-    __shared__ uint32_t lds_tlo[Cfg<P>::O + 1];                                \
-    const LdsBufs L{lds_a, lds_b, lds_thi, lds_tlo}
+    __shared__ float2 lds_th[mid_tab_len<P>() + 1];                            \
+    __shared__ uint32_t lds_tl[mid_tab_len<P>() + 1];                          \
+    const LdsBufs L{lds_a, lds_b, lds_th, lds_tl}
 
 // Sum two doubles over the workgroup in a fixed order (wave butterfly, then waves in
 // index order); every thread returns the same values.
@@ -392,9 +443,7 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *red) {
     __syncthreads();
 }
 
-__device__ __forceinline__ double cnorm2(float2 v) {
-    return static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y;
-}
+__device__ __forceinline__ float cnorm2(float2 v) { return fmaf(v.x, v.x, v.y * v.y); }
 
 // exp(i sigma n) for the carrier of step n, in FP64: Cody-Waite reduction by pi/2 (two-part
 // constant) and Taylor series of sin and cos on [-pi/4, pi/4] (truncation < 1e-17).
@@ -444,8 +493,9 @@ __device__ __forceinline__ float eddy_correction(const SolveDesc &d, float vm, f
 }
 
 // A = v (.) dmod at the thread's positions (zero outside 1..N); v of global step n.
-template <int P>
-__device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, float2 (&A)[Cfg<P>::RT]) {
+// Written to registers (A) when the kernel keeps it there, else to the solve's pot array.
+template <int P, bool IN_REGS>
+__device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, float2 *A) {
     constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
     const int N = d.N;
     long long row = 0;
@@ -458,15 +508,16 @@ __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, 
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
         const int pos = opaque_tid() + i * T, m = pos - 1;
+        float2 val = make_float2(0.f, 0.f);
         if (pos >= 1 && pos <= N) {
             float v = ldf(vrow, m);
             if (d.prof_mode == PROF_ANALYTIC)
                 v += eddy_correction(d, v, static_cast<float>(pos * d.dz), r);
             const float2 dm = ld2(d.dmod, m);
-            A[i] = make_float2(v * dm.x, v * dm.y);
-        } else {
-            A[i] = make_float2(0.f, 0.f);
+            val = make_float2(v * dm.x, v * dm.y);
+            if constexpr (!IN_REGS) st2(d.pot, m, val);
         }
+        if constexpr (IN_REGS) A[i] = val;
     }
 }
 
@@ -478,21 +529,25 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
     // the Neumann multiplier stays in registers for up to 8 elements per thread
     constexpr bool kBInRegs = (RT <= 8) && (T < 1024);
     constexpr int EB = kBInRegs ? RT : 1;
+    // ... and so does the potential A = v (.) dmod; otherwise both come from L2
+    constexpr bool kAInRegs = kBInRegs;
+    constexpr int EA = kAInRegs ? RT : 1;
     SSP_LDS_DECL(P);
     __shared__ double red[2 * (T / 64)];
     const SolveDesc &d = descs[blockIdx.x];
     const int tid = threadIdx.x;
     const int N = d.N, p = d.p, nmax = d.nmax;
-    load_twiddles<P>(lds_thi, lds_tlo, d.tw);
+    Twiddles<P> tw;
+    init_twiddles<P>(tw, lds_th, lds_tl, d.tw);
 
     // The state u is not held in registers: d.field holds the state at the start of the
     // step (the recovery point if the step diverges) and d.work the state between Pade
     // factors.  Every thread reads and writes only its own positions, so these global
     // accesses need no barriers.
-    float2 w[RT], a[RT], A[RT];
+    float2 w[RT], a[RT], A[EA];
     float4 Bm[EB];
     long long n = *d.step;
-    if (d.prof_mode == PROF_TABLE_FIXED) load_potential<P>(d, n + 1, A);
+    if (d.prof_mode == PROF_TABLE_FIXED) load_potential<P, kAInRegs>(d, n + 1, A);
 
     long long terms = 0, done = 0;
     int max_used = 0, notconv = 0, status = kOK;
@@ -500,11 +555,13 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
 
     for (int s = 0; s < nsteps; ++s) {
         const long long nn = n + 1;
-        if (d.prof_mode != PROF_TABLE_FIXED) load_potential<P>(d, nn, A);
+        if (d.prof_mode != PROF_TABLE_FIXED) load_potential<P, kAInRegs>(d, nn, A);
         bool bad = false;
         for (int j = 0; j < p; ++j) {
             const float2 *cur = (j == 0) ? d.field : d.work;
-            double t0 = 0.0, dummy = 0.0;
+            // per-thread partial sums of |.|^2 in FP32 (a handful of terms), workgroup sums
+            // in FP64
+            float t0f = 0.f;
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T, m = pos - 1;
@@ -516,8 +573,9 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
                     if constexpr (kBInRegs) Bm[i] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
                 w[i] = a[i];
-                t0 += cnorm2(a[i]);
+                t0f += cnorm2(a[i]);
             }
+            double t0 = t0f, dummy = 0.0;
             block_sum2<T>(t0, dummy, red);
             double tn = 0.0, wn = 0.0;
             int used = 0;
@@ -525,14 +583,20 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
             // half-iteration h: even -> a = A (.) S a (multiply by v); odd -> a = B_j (.) S a
             // (diagonal solve) and the term is accumulated; one transform site per loop
             for (int h = 0; h < 2 * nmax; ++h) {
-                chirp_core<P>(a, L, d);
+                chirp_core<P>(a, L, tw, d);
                 if ((h & 1) == 0) {
 #pragma unroll
-                    for (int i = 0; i < RT; ++i) a[i] = cmul(A[i], a[i]);
+                    for (int i = 0; i < RT; ++i) {
+                        if constexpr (kAInRegs) {
+                            a[i] = cmul(A[i], a[i]);
+                        } else {
+                            const int pos = opaque_tid() + i * T;
+                            a[i] = (pos >= 1 && pos <= N) ? cmul(ld2(d.pot, pos - 1), a[i]) : make_float2(0.f, 0.f);
+                        }
+                    }
                     continue;
                 }
-                tn = 0.0;
-                wn = 0.0;
+                float tnf = 0.f, wnf = 0.f;
 #pragma unroll
                 for (int i = 0; i < RT; ++i) {
                     const int pos = opaque_tid() + i * T;
@@ -542,9 +606,11 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
                                                      : make_float4(0.f, 0.f, 0.f, 0.f);
                     a[i] = cmul_df(a[i], bm);
                     w[i] = cadd(w[i], a[i]);
-                    tn += cnorm2(a[i]);
-                    wn += cnorm2(w[i]);
+                    tnf += cnorm2(a[i]);
+                    wnf += cnorm2(w[i]);
                 }
+                tn = tnf;
+                wn = wnf;
                 block_sum2<T>(tn, wn, red);
                 used = (h >> 1) + 1;
                 if (!(isfinite(tn) && isfinite(wn))) {
@@ -628,7 +694,8 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_transform(const SolveDesc *__rest
     SSP_LDS_DECL(P);
     const SolveDesc &d = *desc;
     const int N = d.N, tid = threadIdx.x;
-    load_twiddles<P>(lds_thi, lds_tlo, d.tw);
+    Twiddles<P> tw;
+    init_twiddles<P>(tw, lds_th, lds_tl, d.tw);
     const float2 *vin = in + static_cast<size_t>(blockIdx.x) * N;
     float2 *vout = out + static_cast<size_t>(blockIdx.x) * N;
     float2 x[RT];
@@ -642,7 +709,7 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_transform(const SolveDesc *__rest
         }
         x[i] = v;
     }
-    chirp_core<P>(x, L, d);
+    chirp_core<P>(x, L, tw, d);
     float2 car = make_float2(1.f, 0.f);
     if (mode == 2) car = carrier(d.sigma, step[blockIdx.x]);
 #pragma unroll
@@ -667,7 +734,8 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_output(const SolveDesc *__restric
     const SolveDesc &d = descs[b];
     if (row >= d.nout || !d.snap) return;  // uniform over the workgroup
     const int N = d.N, tid = threadIdx.x;
-    load_twiddles<P>(lds_thi, lds_tlo, d.tw);
+    Twiddles<P> tw;
+    init_twiddles<P>(tw, lds_th, lds_tl, d.tw);
     const long long n = d.out_base + static_cast<long long>(row) * d.out_every;
     const float2 *src = d.snap + static_cast<size_t>(row) * N;
     float2 x[RT];
@@ -676,7 +744,7 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_output(const SolveDesc *__restric
         const int pos = tid + i * T;
         x[i] = (pos >= 1 && pos <= N) ? ld2(src, pos - 1) : make_float2(0.f, 0.f);
     }
-    chirp_core<P>(x, L, d);
+    chirp_core<P>(x, L, tw, d);
     const float2 car = carrier(d.sigma, n);
     const float lr = log10f(static_cast<float>(static_cast<double>(n) * d.dr));
 #pragma unroll
