@@ -7,8 +7,9 @@ Workload (deep-ocean Munk waveguide): H = 5000 m, c0 = 1500 m/s, f = 50 Hz, Nz =
 "step" is one range step of the whole batch (every Pade factor and every Neumann term of
 every solve); inputs are resident in HBM before the timed region.
 
-Prints ONE JSON line (contract of the driver) and, with --plain, also times the plain
-one-kernel-per-stage form for comparison.
+Prints ONE JSON line (contract of the driver).  Beside the metric it reports the roofline of
+the fused march kernel, the plain one-kernel-per-stage form and the fused kernel on a single
+solve (same arithmetic, identical results), and the FP64 oracle on the host cores.
 """
 from __future__ import annotations
 
@@ -76,6 +77,8 @@ def main():
     ap.add_argument("--nz", type=int, default=4096)
     ap.add_argument("--chunk", type=int, default=100, help="range steps per kernel launch")
     ap.add_argument("--roof-launches", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=8,
+                    help="range steps of the plain-form comparison (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
@@ -146,6 +149,26 @@ def main():
     achieved = sum(flops) / sum(launch_s)
     stats = _stats(d_stats)
 
+    # the plain one-kernel-per-stage form on one solve, and the fused kernel on one solve
+    plain = None
+    if args.plain_steps > 0:
+        plain = {}
+        for engine, key in ((1, "plain_one_solve"), (0, "fused_one_solve")):
+            p1 = ssp.ssp_plan_create(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order,
+                                     s.neumann_max, s.tol)
+            ssp.ssp_plan_set_option(p1, ssp.SSP_OPT_ENGINE, engine)
+            ssp.ssp_plan_set_option(p1, ssp.SSP_OPT_OUT_EVERY, s.out_every)
+            ssp.ssp_set_profile(p1, 0, -1, s.profile()[0])
+            ssp.ssp_march(p1, s.nz, s.starter(), 2, want_field=False, want_tl=False)
+            t1 = time.perf_counter()
+            ssp.ssp_march(p1, s.nz, None, args.plain_steps, want_field=False, want_tl=True)
+            dt = time.perf_counter() - t1
+            ssp.ssp_plan_destroy(p1)
+            plain[key] = s.nz * args.plain_steps / dt
+        plain["unit"] = "field updates/s"
+        plain["steps"] = args.plain_steps
+        plain["fused_batched_over_plain"] = value / plain["plain_one_solve"]
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(s.nz, args.cpu_seconds)
@@ -174,6 +197,7 @@ def main():
                      "steps_per_launch": args.chunk,
                      "neumann_terms_per_solve_step": stats["terms"] / B / args.chunk},
         "status": sorted(set(stats["status"])),
+        "plain_form": plain,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -85,8 +85,7 @@ struct ssp_plan {
     size_t out_cap = 0;
     // plain-form work buffers
     float2 *d_plain = nullptr;
-    double *d_plain_scal = nullptr;
-    int *d_plain_flags = nullptr;
+    void *d_plain_flags = nullptr;      // plain-form series state
 };
 
 namespace {
@@ -352,8 +351,7 @@ void ssp_plan_destroy(ssp_plan *pl) {
     dev_free(pl->d_out_fld);
     dev_free(pl->d_out_tl);
     dev_free(pl->d_plain);
-    dev_free(pl->d_plain_scal);
-    dev_free(pl->d_plain_flags);
+    if (pl->d_plain_flags) (void)hipFree(pl->d_plain_flags);
     delete pl;
 }
 
@@ -587,9 +585,20 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
                            hipMemcpyHostToDevice, stream));
     if (nsteps > 0) {
         if (n == 1 && owner->engine == 1) {
-            // plain form (not batched)
-            return fail(SSP_E_UNIMPL, "plain engine not available through ssp_march in this build");
-        }
+            // plain form: one kernel per stage, one solve
+            ssp_plan *pl = owner;
+            if (!pl->d_plain) {
+                HIP_TRY(dev_alloc(&pl->d_plain, 2 * static_cast<size_t>(pl->N)));
+                HIP_TRY(hipMalloc(reinterpret_cast<void **>(&pl->d_plain_flags), ssp::plain_state_bytes()));
+            }
+            HIP_TRY(hipMemsetAsync(pl->d_plain_flags, 0, ssp::plain_state_bytes(), stream));
+            long long idx = pl->step_index;
+            ssp::DevStats z{};
+            z.step_index = idx;
+            HIP_TRY(hipMemcpyAsync(pl->d_stats, &z, sizeof(z), hipMemcpyHostToDevice, stream));
+            HIP_TRY(ssp::plain_march(sorted[0], owner->d_descs, nsteps, pl->d_plain, pl->d_plain_flags, stream));
+            if (sorted[0].snap) HIP_TRY(ssp::launch_output(sorted[0].P, owner->d_descs, 1, sorted[0].nout, stream));
+        } else {
         int start = 0;
         while (start < n) {
             int end = start;
@@ -599,6 +608,7 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
             for (int k = start; k < end; ++k) rows = std::max(rows, sorted[k].snap ? sorted[k].nout : 0);
             HIP_TRY(ssp::launch_output(sorted[start].P, owner->d_descs + start, end - start, rows, stream));
             start = end;
+        }
         }
     }
     ssp_status worst = SSP_OK;
@@ -613,6 +623,8 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
             st = ssp::DevStats{};
             st.step_index = pl->step_index;
         }
+        if (pl->engine == 1 && n == 1 && st.status == SSP_OK && st.not_converged > 0)
+            st.status = SSP_W_NOT_CONVERGED;
         pl->step_index = st.step_index;
         const size_t cnt = static_cast<size_t>(nout[i]) * pl->N;
         if (field_out && field_out[i] && cnt) {

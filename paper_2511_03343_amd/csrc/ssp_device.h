@@ -67,9 +67,12 @@ hipError_t launch_output(int P, const SolveDesc *d_descs, int nsolves, int nout,
 hipError_t launch_transform(int P, int mode, const SolveDesc *d_desc, int B, const float2 *in,
                             float2 *out, const long long *step, hipStream_t stream);
 
-// Plain form: one kernel per transform / pointwise stage, one solve, host loop.
-hipError_t plain_march(const SolveDesc &h_desc, const SolveDesc *d_desc, int nsteps,
-                       float2 *d_work, double *d_scal, int *d_flags, hipStream_t stream);
+// Plain form: one kernel per stage (start, Neumann half-term, finish, commit) for the single
+// solve of h_desc / d_desc, host loop over steps, factors and half-terms.  d_work holds 2N
+// complex values, d_state plain_state_bytes().  d_desc->stats must be zeroed by the caller.
+hipError_t plain_march(const SolveDesc &h_desc, const SolveDesc *d_desc, int nsteps, float2 *d_work,
+                       void *d_state, hipStream_t stream);
+size_t plain_state_bytes();
 
 bool fft_length_supported(int P);
 

@@ -758,6 +758,194 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_output(const SolveDesc *__restric
     }
 }
 
+// ----------------------------------------------------------------------------- plain form
+// The same method as k_march, one kernel per stage and one solve per launch: the host loops
+// over steps, Pade factors and Neumann half-terms; every kernel reads the series state from
+// global memory and skips its work once the series has stopped (device-side flag), so the
+// host never waits on the device inside a march.  Arithmetic and reduction order are those
+// of k_march, so both forms give identical results.
+struct PlainState {
+    double t0, tn, wn;
+    int done, used, bad, halt;
+};
+
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::T) void k_plain_start(const SolveDesc *__restrict__ desc, float2 *a, float2 *w,
+                                                             PlainState *ps, int j) {
+    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    __shared__ double red[2 * (T / 64)];
+    const SolveDesc &d = *desc;
+    if (ps->halt) return;
+    const int N = d.N;
+    const float2 *cur = (j == 0) ? d.field : d.work;
+    float part = 0.f;
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        const int pos = opaque_tid() + i * T, m = pos - 1;
+        if (pos >= 1 && pos <= N) {
+            const float2 v = cmul_df(ld2(cur, m), ld4(d.s, j * N + m));
+            st2(a, m, v);
+            st2(w, m, v);
+            part += cnorm2(v);
+        }
+    }
+    double t0 = part, dummy = 0.0;
+    block_sum2<T>(t0, dummy, red);
+    if (threadIdx.x == 0) {
+        ps->t0 = t0;
+        ps->tn = 0.0;
+        ps->wn = 0.0;
+        ps->done = (d.nmax == 0);
+        ps->used = 0;
+        ps->bad = 0;
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::T) void k_plain_half(const SolveDesc *__restrict__ desc, float2 *a, float2 *w,
+                                                            PlainState *ps, int j, int h, long long n) {
+    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    SSP_LDS_DECL(P);
+    __shared__ double red[2 * (T / 64)];
+    const SolveDesc &d = *desc;
+    if (ps->halt || ps->done) return;  // uniform: the series has stopped
+    Twiddles<P> tw;
+    init_twiddles<P>(tw, lds_th, lds_tl, d.tw);
+    const int N = d.N;
+    float2 x[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        const int pos = opaque_tid() + i * T;
+        x[i] = (pos >= 1 && pos <= N) ? ld2(a, pos - 1) : make_float2(0.f, 0.f);
+    }
+    chirp_core<P>(x, L, tw, d);
+    if ((h & 1) == 0) {
+        float2 A[RT];
+        load_potential<P, true>(d, n, A);
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+            const int pos = opaque_tid() + i * T;
+            if (pos >= 1 && pos <= N) st2(a, pos - 1, cmul(A[i], x[i]));
+        }
+        return;
+    }
+    float tnf = 0.f, wnf = 0.f;
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        const int pos = opaque_tid() + i * T, m = pos - 1;
+        if (pos >= 1 && pos <= N) {
+            const float2 v = cmul_df(x[i], ld4(d.bmul, j * N + m));
+            const float2 ww = cadd(ld2(w, m), v);
+            st2(a, m, v);
+            st2(w, m, ww);
+            tnf += cnorm2(v);
+            wnf += cnorm2(ww);
+        }
+    }
+    double tn = tnf, wn = wnf;
+    block_sum2<T>(tn, wn, red);
+    if (threadIdx.x == 0) {
+        ps->tn = tn;
+        ps->wn = wn;
+        ps->used = (h >> 1) + 1;
+        if (!(isfinite(tn) && isfinite(wn))) {
+            ps->bad = 1;
+            ps->done = 1;
+        } else if (tn <= d.tol2 * wn) {
+            ps->done = 1;
+        }
+    }
+}
+
+// End of a Pade factor: statistics, divergence test, product-form combine into d.work.
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::T) void k_plain_finish(const SolveDesc *__restrict__ desc, const float2 *w,
+                                                              PlainState *ps, int j) {
+    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    const SolveDesc &d = *desc;
+    if (ps->halt) return;
+    const bool conv = ps->done && !ps->bad;
+    const bool diverged = ps->bad || (!conv && ps->tn >= ps->t0);
+    __syncthreads();  // every thread has read ps before thread 0 updates it
+    if (diverged) {
+        if (threadIdx.x == 0) {
+            ps->halt = 1;
+            d.stats->status = kDiverged;
+        }
+        return;
+    }
+    if (threadIdx.x == 0) {
+        DevStats *st = d.stats;
+        st->neumann_terms += ps->used;
+        if (ps->used > st->neumann_max_used) st->neumann_max_used = ps->used;
+        if (!conv && d.nmax > 0) st->not_converged += 1;
+        if (d.nmax > 0) {
+            const double res = ps->wn > 0.0 ? sqrt(ps->tn / ps->wn) : 0.0;
+            if (res > st->max_residual) st->max_residual = res;
+        }
+    }
+    const int N = d.N;
+    const float2 *cur = (j == 0) ? d.field : d.work;
+    const float4 al = ld4(d.alpha, j), be = ld4(d.beta, j);
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        const int pos = opaque_tid() + i * T, m = pos - 1;
+        if (pos >= 1 && pos <= N) st2(d.work, m, cadd(cmul_df(ld2(cur, m), al), cmul_df(ld2(w, m), be)));
+    }
+}
+
+// End of a step: commit, counters, output snapshot.
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::T) void k_plain_commit(const SolveDesc *__restrict__ desc, PlainState *ps) {
+    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    const SolveDesc &d = *desc;
+    if (ps->halt) return;
+    const int N = d.N;
+    const long long n = *d.step + 1;
+    const long long slot = d.out_every > 0 ? (n - d.out_base) / d.out_every : -1;
+    const bool snap = d.snap && d.out_every > 0 && (n % d.out_every) == 0 && n >= d.out_base && slot < d.nout;
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        const int pos = opaque_tid() + i * T, m = pos - 1;
+        if (pos >= 1 && pos <= N) {
+            const float2 v = ld2(d.work, m);
+            st2(d.field, m, v);
+            if (snap) st2(d.snap + slot * N, m, v);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *d.step = n;
+        d.stats->steps_done += 1;
+        d.stats->step_index = n;
+    }
+}
+
+template <int P>
+hipError_t plain_march_P(const SolveDesc &hd, const SolveDesc *dd, int nsteps, float2 *work,
+                         void *state, hipStream_t stream) {
+    constexpr int T = Cfg<P>::T;
+    float2 *a = work, *w = work + hd.N;
+    PlainState *ps = static_cast<PlainState *>(state);
+    long long n0 = 0;
+    hipError_t e = hipMemcpyAsync(&n0, hd.step, sizeof(n0), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return e;
+    for (int s = 0; s < nsteps; ++s) {
+        const long long n = n0 + s + 1;
+        for (int j = 0; j < hd.p; ++j) {
+            hipLaunchKernelGGL((k_plain_start<P>), dim3(1), dim3(T), 0, stream, dd, a, w, ps, j);
+            for (int h = 0; h < 2 * hd.nmax; ++h)
+                hipLaunchKernelGGL((k_plain_half<P>), dim3(1), dim3(T), 0, stream, dd, a, w, ps, j, h, n);
+            hipLaunchKernelGGL((k_plain_finish<P>), dim3(1), dim3(T), 0, stream, dd, w, ps, j);
+        }
+        hipLaunchKernelGGL((k_plain_commit<P>), dim3(1), dim3(T), 0, stream, dd, ps);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template <int P>
 hipError_t launch_output_P(const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream) {
     hipLaunchKernelGGL((k_output<P>), dim3(nsolves * nout), dim3(Cfg<P>::T), 0, stream, d_descs, nout);
@@ -810,6 +998,16 @@ hipError_t launch_output(int P, const SolveDesc *d_descs, int nsolves, int nout,
     SSP_DISPATCH_P(P, CALL_O)
 #undef CALL_O
 }
+
+hipError_t plain_march(const SolveDesc &h_desc, const SolveDesc *d_desc, int nsteps, float2 *d_work,
+                       void *d_state, hipStream_t stream) {
+    if (nsteps <= 0) return hipSuccess;
+#define CALL_PL(PP) plain_march_P<PP>(h_desc, d_desc, nsteps, d_work, d_state, stream)
+    SSP_DISPATCH_P(h_desc.P, CALL_PL)
+#undef CALL_PL
+}
+
+size_t plain_state_bytes() { return sizeof(PlainState); }
 
 hipError_t launch_transform(int P, int mode, const SolveDesc *d_desc, int B, const float2 *in,
                             float2 *out, const long long *step, hipStream_t stream) {

@@ -280,3 +280,37 @@ def test_device_batch_matches_host_march(ssp, gpu):
     finally:
         ssp.ssp_plan_destroy(pl)
     assert np.array_equal(got.astype(np.complex128), np.stack(host))
+
+
+@pytest.mark.parametrize("nz,env", [(511, "munk"), (300, "munk+eddy")])
+def test_plain_form_equals_fused_bitwise(ssp, gpu, nz, env):
+    # the one-kernel-per-stage form runs the same arithmetic in the same order
+    s = W.munk_deep(nsteps=8, nz=nz) if env == "munk" else W.munk_eddy(nsteps=8, nz=nz, neumann_max=24)
+    s.out_every = 4
+    out = []
+    for engine in (0, 1):
+        pl = make_plan(ssp, s, profile="analytic" if env != "munk" else "table")
+        try:
+            ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_ENGINE, engine)
+            out.append(ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps))
+        finally:
+            ssp.ssp_plan_destroy(pl)
+    (st0, f0, t0, s0), (st1, f1, t1, s1) = out
+    assert st0 == st1 and s0 == s1
+    assert np.array_equal(f0, f1) and np.array_equal(t0, t1)
+
+
+def test_plain_form_reports_divergence(ssp, gpu):
+    s = W.munk_deep(nsteps=3, nz=511)
+    s.dr = 1.0 / s.k0
+    s.neumann_max = 16
+    pl = make_plan(ssp, s)
+    try:
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_ENGINE, 1)
+        with pytest.raises(ssp.SspError) as e:
+            ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+        assert e.value.status == ssp.SSP_E_DIVERGED
+        back = ssp.ssp_get_field(pl, s.nz)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    assert np.linalg.norm(back - s.starter()) / np.linalg.norm(s.starter()) < 2e-6
