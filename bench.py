@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--roof-launches", type=int, default=3)
     ap.add_argument("--plain-steps", type=int, default=8,
                     help="range steps of the plain-form comparison (0: skip)")
+    ap.add_argument("--graph", type=int, default=1, help="replay recorded launches (HIP graph)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
@@ -91,13 +92,15 @@ def main():
     from paper_2511_03343_amd import ssp
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
+    stream = torch.cuda.Stream(dev)           # default priority
+    torch.cuda.set_stream(stream)
 
     s = W.munk_deep(nz=args.nz)
     B = args.batch
     pl = ssp.ssp_plan_create(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol)
     ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
     ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_OUT_EVERY, s.out_every)
+    ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_GRAPH, 1 if args.graph else 0)
     ssp.ssp_set_profile(pl, 0, -1, s.profile()[0])
 
     zs = W.source_depths(B, 50.0, 2000.0)
@@ -189,7 +192,7 @@ def main():
         "config": {"workload": "deep Munk waveguide, Nz=4096, [6/6] Pade, dr=25 m, 50 Hz, "
                                "Neumann tol 1e-10 (cap 48), TL every 4 steps",
                    "batch_solves": B, "nz": s.nz, "range_steps_timed": args.steps,
-                   "steps_per_launch": args.chunk},
+                   "steps_per_launch": args.chunk, "hip_graph": bool(args.graph)},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
                      "kernel": f"k_march<{_fft_len(s.nz)}>",

@@ -61,8 +61,12 @@ enum {
     SSP_OPT_OUT_EVERY = 2, /* write an output every k-th step (default 1) */
     SSP_OPT_STREAM = 3,    /* value = (double)(uintptr_t)hipStream_t; 0 = null stream.
                               Use ssp_plan_set_stream to pass a pointer exactly. */
-    SSP_OPT_ENGINE = 4     /* 0 = fused persistent kernel (default); 1 = plain form: one
+    SSP_OPT_ENGINE = 4,    /* 0 = fused persistent kernel (default); 1 = plain form: one
                               kernel per transform / pointwise step, host-driven loop */
+    SSP_OPT_GRAPH = 5      /* 1: ssp_march_device records its launches (march + outputs) in
+                              a HIP graph on the first call and replays the graph on later
+                              calls with the same arguments; needs a non-null stream.
+                              0 (default): plain launches */
 };
 
 /* Analytic range-dependent environment evaluated on the device every step at the step's
@@ -152,11 +156,14 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
                            float *const *tl_out, ssp_stats *stats);
 
 /* Device-resident batch for serving and benchmarking (no host copies in the hot path):
- * B solves of one plan's grid and coefficients.  d_psi is a device array
- * [B][Nz] complex64 holding each solve's field in the library's sine-basis
- * representation (see ssp_to_sine / ssp_from_sine); d_step is a device int64 [B] of global
- * step counters; d_tl (may be NULL) a device float [B][nout][Nz]; d_stats a device array of
- * B ssp_stats (may be NULL).  The call is asynchronous on the plan's stream. */
+ * B solves of one plan's grid and coefficients, each with its own state.  d_psi is a device
+ * array [B][Nz] complex64 holding each solve's field in the library's sine-basis
+ * representation (see ssp_to_sine / ssp_from_sine); d_step a device int64 [B] of step
+ * counters (they may differ between solves); d_tl (may be NULL) a device float
+ * [B][nsteps/out_every + 1][Nz] that receives, per solve, the TL rows of the output steps
+ * reached in this call, in order; d_stats a device array of B ssp_stats (may be NULL).
+ * The call is asynchronous on the plan's stream.  Scratch (per-solve state between Pade
+ * factors, output snapshots) is owned by the plan and reused by later calls. */
 ssp_status ssp_march_device(ssp_plan *plan, int B, void *d_psi, void *d_step, int nsteps,
                             void *d_tl, void *d_stats);
 /* physical complex64 [B][Nz] (device) -> sine-basis representation (device), in place ok */

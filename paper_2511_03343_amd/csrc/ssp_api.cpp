@@ -79,6 +79,21 @@ struct ssp_plan {
     int bwork_cap = 0;
     float2 *d_snap = nullptr;           // output snapshots of a device batch
     size_t snap_cap = 0;
+    ssp::DevStats *d_bstats = nullptr;  // statistics of a device batch when the caller passes none
+    int bstats_cap = 0;
+    // recorded launches of ssp_march_device (SSP_OPT_GRAPH)
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    struct GraphKey {
+        int B, nsteps;
+        void *psi, *step, *tl, *stats;
+        hipStream_t stream;
+        bool operator==(const GraphKey &o) const {
+            return B == o.B && nsteps == o.nsteps && psi == o.psi && step == o.step && tl == o.tl &&
+                   stats == o.stats && stream == o.stream;
+        }
+    } graph_key{};
     // output staging
     float2 *d_out_fld = nullptr;
     float *d_out_tl = nullptr;
@@ -89,6 +104,13 @@ struct ssp_plan {
 };
 
 namespace {
+
+void drop_graph(ssp_plan *pl) {
+    if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    pl->graph_exec = nullptr;
+    pl->graph = nullptr;
+}
 
 void free_tables(ssp_plan *pl) {
     dev_free(pl->d_k1);
@@ -338,12 +360,14 @@ void ssp_plan_destroy(ssp_plan *pl) {
     if (!pl) return;
     if (pl->stream) (void)hipStreamSynchronize(pl->stream);
     else (void)hipDeviceSynchronize();
+    drop_graph(pl);
     free_tables(pl);
     dev_free(pl->d_v);
     dev_free(pl->d_field);
     dev_free(pl->d_work);
     dev_free(pl->d_bwork);
     dev_free(pl->d_snap);
+    dev_free(pl->d_bstats);
     dev_free(pl->d_step);
     dev_free(pl->d_stats);
     dev_free(pl->d_desc);
@@ -357,12 +381,14 @@ void ssp_plan_destroy(ssp_plan *pl) {
 
 ssp_status ssp_plan_set_stream(ssp_plan *pl, void *hip_stream) {
     if (!pl) return fail(SSP_E_INVAL, "plan is NULL");
+    drop_graph(pl);
     pl->stream = static_cast<hipStream_t>(hip_stream);
     return SSP_OK;
 }
 
 ssp_status ssp_plan_set_option(ssp_plan *pl, int key, double value) {
     if (!pl) return fail(SSP_E_INVAL, "plan is NULL");
+    drop_graph(pl);
     switch (key) {
         case SSP_OPT_ROTATION: {
             if (!std::isfinite(value) || std::fabs(value) > M_PI / 2)
@@ -385,6 +411,11 @@ ssp_status ssp_plan_set_option(ssp_plan *pl, int key, double value) {
             return SSP_OK;
         case SSP_OPT_STREAM:
             pl->stream = reinterpret_cast<hipStream_t>(static_cast<uintptr_t>(value));
+            return SSP_OK;
+        case SSP_OPT_GRAPH:
+            if (value != 0 && value != 1) return fail(SSP_E_INVAL, "graph must be 0 or 1");
+            pl->use_graph = value == 1;
+            drop_graph(pl);
             return SSP_OK;
         case SSP_OPT_ENGINE:
             if (value != 0 && value != 1) return fail(SSP_E_INVAL, "engine must be 0 or 1");
@@ -428,6 +459,7 @@ ssp_status ssp_plan_info(const ssp_plan *pl, double *sigma, double *k0, double *
 
 ssp_status ssp_set_profile(ssp_plan *pl, int step0, int nsteps, const double *c) {
     if (!pl || !c) return fail(SSP_E_INVAL, "NULL argument");
+    drop_graph(pl);
     if (step0 < 0 || nsteps == 0 || nsteps < -1) return fail(SSP_E_INVAL, "bad step range");
     const int rows = nsteps == -1 ? 1 : nsteps;
     const size_t count = static_cast<size_t>(rows) * pl->N;
@@ -453,6 +485,7 @@ ssp_status ssp_set_profile(ssp_plan *pl, int step0, int nsteps, const double *c)
 
 ssp_status ssp_set_profile_analytic(ssp_plan *pl, const ssp_env *env) {
     if (!pl || !env) return fail(SSP_E_INVAL, "NULL argument");
+    drop_graph(pl);
     const double e[8] = {env->munk_c1, env->munk_eps, env->munk_z1, env->eddy_amp,
                          env->eddy_r0, env->eddy_rr, env->eddy_z0, env->eddy_rz};
     for (double x : e)
@@ -565,10 +598,10 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
         d.fld_out = (field_out && field_out[i] && nout[i] > 0) ? pl->d_out_fld : nullptr;
         d.tl_out = (tl_out && tl_out[i] && nout[i] > 0) ? pl->d_out_tl : nullptr;
         d.snap = (d.fld_out || d.tl_out) ? pl->d_out_fld : nullptr;
-        d.out_base = first_output_step(pl->step_index, pl->out_every);
         descs[i] = d;
     }
     ssp_plan *owner = plans[0];
+    drop_graph(owner);  // d_descs is rewritten below
     if (owner->descs_cap < n) {
         dev_free(owner->d_descs);
         owner->descs_cap = 0;
@@ -646,6 +679,12 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
 ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int nsteps, void *d_tl,
                             void *d_stats) {
     if (!pl || B <= 0 || !d_psi || !d_step || nsteps < 0) return fail(SSP_E_INVAL, "bad argument");
+    const ssp_plan::GraphKey key{B, nsteps, d_psi, d_step, d_tl, d_stats, pl->stream};
+    if (pl->use_graph && pl->graph_exec && pl->graph_key == key) {
+        HIP_TRY(hipGraphLaunch(pl->graph_exec, pl->stream));
+        return SSP_OK;
+    }
+    if (pl->use_graph && !pl->stream) return fail(SSP_E_INVAL, "graph replay needs a non-null stream");
     ssp_status st = check_profile_range(pl, 0, 0);
     if (st != SSP_OK) return st;
     if (pl->descs_cap < B) {
@@ -654,18 +693,23 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
         HIP_TRY(dev_alloc(&pl->d_descs, B));
         pl->descs_cap = B;
     }
-    // the caller's step counters are on the device; output slots count from the first
-    // output step after the counter value in d_stats-less mode, so d_tl is indexed per solve
-    // with out_base taken from the host mirror of the first solve's counter (all solves of a
-    // device batch advance together).
+    // step counters live on the device and may differ between solves: each solve's output
+    // rows are the output steps after its own counter (computed in the kernels)
     if (pl->bwork_cap < B) {
         dev_free(pl->d_bwork);
         pl->bwork_cap = 0;
         HIP_TRY(dev_alloc(&pl->d_bwork, 2 * static_cast<size_t>(B) * pl->N));
         pl->bwork_cap = B;
     }
+    if (!d_stats && pl->bstats_cap < B) {
+        dev_free(pl->d_bstats);
+        pl->bstats_cap = 0;
+        HIP_TRY(dev_alloc(&pl->d_bstats, B));
+        pl->bstats_cap = B;
+    }
     std::vector<ssp::SolveDesc> descs(B);
-    const int nout = count_outputs(pl->step_index, nsteps, pl->out_every);
+    // rows available per solve: the largest number of output steps in nsteps steps
+    const int nout = pl->out_every > 0 ? nsteps / pl->out_every + 1 : 0;
     const size_t snap_elems = d_tl ? static_cast<size_t>(B) * nout * pl->N : 0;
     if (snap_elems > pl->snap_cap) {
         dev_free(pl->d_snap);
@@ -680,18 +724,35 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
         d.pot = d.work + pl->N;
         d.nout = nout;
         d.step = static_cast<long long *>(d_step) + b;
-        d.stats = d_stats ? static_cast<ssp::DevStats *>(d_stats) + b : nullptr;
+        d.stats = (d_stats ? static_cast<ssp::DevStats *>(d_stats) : pl->d_bstats) + b;
         d.tl_out = d_tl ? static_cast<float *>(d_tl) + static_cast<size_t>(b) * nout * pl->N : nullptr;
         d.fld_out = nullptr;
-        d.out_base = first_output_step(pl->step_index, pl->out_every);
         if (nout == 0) d.tl_out = nullptr;
         d.snap = d.tl_out ? pl->d_snap + static_cast<size_t>(b) * nout * pl->N : nullptr;
         descs[b] = d;
     }
     HIP_TRY(hipMemcpyAsync(pl->d_descs, descs.data(), B * sizeof(ssp::SolveDesc), hipMemcpyHostToDevice,
                            pl->stream));
-    HIP_TRY(ssp::launch_march(pl->P, pl->d_descs, B, nsteps, pl->stream));
-    if (d_tl && nout > 0) HIP_TRY(ssp::launch_output(pl->P, pl->d_descs, B, nout, pl->stream));
+    if (pl->use_graph) {
+        // record the launches once; the descriptors above stay valid for later replays
+        drop_graph(pl);
+        HIP_TRY(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = ssp::launch_march(pl->P, pl->d_descs, B, nsteps, pl->stream);
+        if (e == hipSuccess && d_tl && nout > 0) e = ssp::launch_output(pl->P, pl->d_descs, B, nout, pl->stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(pl->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(SSP_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        pl->graph = g;
+        HIP_TRY(hipGraphInstantiate(&pl->graph_exec, g, nullptr, nullptr, 0));
+        pl->graph_key = key;
+        HIP_TRY(hipGraphLaunch(pl->graph_exec, pl->stream));
+    } else {
+        HIP_TRY(ssp::launch_march(pl->P, pl->d_descs, B, nsteps, pl->stream));
+        if (d_tl && nout > 0) HIP_TRY(ssp::launch_output(pl->P, pl->d_descs, B, nout, pl->stream));
+    }
     pl->step_index += nsteps;
     return SSP_OK;
 }

@@ -46,8 +46,7 @@ struct SolveDesc {
     float *tl_out;              // [nout][N] or null
     float2 *fld_out;            // [nout][N] or null (complex64, carrier included)
     int out_every;
-    int nout;                   // output rows available in tl_out / fld_out
-    long long out_base;         // first output step of the current call
+    int nout;                   // output rows available in snap / tl_out / fld_out
 };
 
 // Launch the fused persistent march: one workgroup per descriptor, all with the same FFT
@@ -55,8 +54,11 @@ struct SolveDesc {
 hipError_t launch_march(int P, const SolveDesc *d_descs, int nsolves, int nsteps,
                         hipStream_t stream);
 
-// Convert the snapshots of an earlier march into field / TL rows: one workgroup per
-// (solve, output row); rows beyond a solve's nout are skipped.
+// Convert the snapshots of the preceding march into field / TL rows: one workgroup per
+// (solve, output row); rows beyond a solve's nout are skipped.  Output rows of a launch that
+// starts at step n0 are the steps (n0/out_every + 1) out_every + row out_every; the step at
+// the start is recovered from the solve's statistics (step_index - steps_done), so stats
+// must be present whenever snapshots are.
 hipError_t launch_output(int P, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream);
 
 // Batched transforms over B vectors of a plan's grid (tables from desc, one desc on the

@@ -547,6 +547,8 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
     float2 w[RT], a[RT], A[EA];
     float4 Bm[EB];
     long long n = *d.step;
+    // outputs of this launch: steps out_base, out_base + out_every, ... (row = slot)
+    const long long out_base = d.out_every > 0 ? (n / d.out_every + 1) * d.out_every : 0;
     if (d.prof_mode == PROF_TABLE_FIXED) load_potential<P, kAInRegs>(d, n + 1, A);
 
     long long terms = 0, done = 0;
@@ -659,8 +661,8 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
         // output step: keep a snapshot of the sine-basis state; k_output turns it into the
         // physical field and TL after the march
         if (d.out_every > 0 && (n % d.out_every) == 0 && d.snap) {
-            const long long slot = (n - d.out_base) / d.out_every;
-            if (n >= d.out_base && slot < d.nout) {
+            const long long slot = (n - out_base) / d.out_every;
+            if (n >= out_base && slot < d.nout) {
 #pragma unroll
                 for (int i = 0; i < RT; ++i) {
                     const int pos = opaque_tid() + i * T, m = pos - 1;
@@ -732,11 +734,14 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_output(const SolveDesc *__restric
     SSP_LDS_DECL(P);
     const int b = blockIdx.x / nout, row = blockIdx.x % nout;
     const SolveDesc &d = descs[b];
-    if (row >= d.nout || !d.snap) return;  // uniform over the workgroup
+    if (row >= d.nout || !d.snap || !d.stats || d.out_every <= 0) return;  // uniform
     const int N = d.N, tid = threadIdx.x;
     Twiddles<P> tw;
     init_twiddles<P>(tw, lds_th, lds_tl, d.tw);
-    const long long n = d.out_base + static_cast<long long>(row) * d.out_every;
+    // the march that wrote the snapshots started at step step_index - steps_done
+    const long long n0 = d.stats->step_index - d.stats->steps_done;
+    const long long n = (n0 / d.out_every + 1) * d.out_every + static_cast<long long>(row) * d.out_every;
+    if (n > d.stats->step_index) return;  // output step not reached in this launch: row untouched
     const float2 *src = d.snap + static_cast<size_t>(row) * N;
     float2 x[RT];
 #pragma unroll
@@ -902,8 +907,10 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_plain_commit(const SolveDesc *__r
     if (ps->halt) return;
     const int N = d.N;
     const long long n = *d.step + 1;
-    const long long slot = d.out_every > 0 ? (n - d.out_base) / d.out_every : -1;
-    const bool snap = d.snap && d.out_every > 0 && (n % d.out_every) == 0 && n >= d.out_base && slot < d.nout;
+    const long long n0 = d.stats->step_index - d.stats->steps_done;  // step at the call's start
+    const long long out_base = d.out_every > 0 ? (n0 / d.out_every + 1) * d.out_every : 0;
+    const long long slot = d.out_every > 0 ? (n - out_base) / d.out_every : -1;
+    const bool snap = d.snap && d.out_every > 0 && (n % d.out_every) == 0 && n >= out_base && slot < d.nout;
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
         const int pos = opaque_tid() + i * T, m = pos - 1;

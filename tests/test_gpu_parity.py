@@ -314,3 +314,40 @@ def test_plain_form_reports_divergence(ssp, gpu):
     finally:
         ssp.ssp_plan_destroy(pl)
     assert np.linalg.norm(back - s.starter()) / np.linalg.norm(s.starter()) < 2e-6
+
+
+def test_graph_replays_match_plain_launches(ssp, gpu):
+    # device batch advanced in chunks: recorded-graph replays vs ordinary launches, with
+    # eager work and synchronisations between the replays; every replay is compared
+    torch = gpu
+    B, chunk, nchunks = 3, 6, 3
+    base = W.munk_deep(nsteps=chunk, nz=900)
+    zs = [300.0, 900.0, 1700.0]
+    results = []
+    for graph in (0, 1):
+        stream = torch.cuda.Stream()
+        pl = make_plan(ssp, base)
+        try:
+            ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
+            ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_GRAPH, graph)
+            psi = np.stack([W.gaussian_starter(base.nz, base.depth, base.freq, base.c0, z) for z in zs])
+            with torch.cuda.stream(stream):
+                d_psi = torch.from_numpy(psi.astype(np.complex64)).cuda()
+                steps = torch.zeros(B, dtype=torch.int64, device="cuda")
+                tl = torch.zeros((B, chunk // base.out_every + 1, base.nz), dtype=torch.float32, device="cuda")
+            stream.synchronize()
+            ssp.ssp_to_sine(pl, B, d_psi.data_ptr(), d_psi.data_ptr())
+            snaps = []
+            for c in range(nchunks):
+                ssp.ssp_march_device(pl, B, d_psi.data_ptr(), steps.data_ptr(), chunk, tl.data_ptr())
+                stream.synchronize()
+                junk = torch.randn(1000, device="cuda").sum().item()  # eager work in between
+                snaps.append((d_psi.cpu().numpy().copy(), tl.cpu().numpy().copy(), steps.cpu().tolist()))
+                assert np.isfinite(junk)
+        finally:
+            ssp.ssp_plan_destroy(pl)
+        results.append(snaps)
+    for (a_psi, a_tl, a_st), (b_psi, b_tl, b_st) in zip(*results):
+        assert a_st == b_st
+        assert np.array_equal(a_psi, b_psi) and np.array_equal(a_tl, b_tl)
+    assert results[0][-1][2] == [chunk * nchunks] * B
