@@ -351,3 +351,24 @@ def test_graph_replays_match_plain_launches(ssp, gpu):
         assert a_st == b_st
         assert np.array_equal(a_psi, b_psi) and np.array_equal(a_tl, b_tl)
     assert results[0][-1][2] == [chunk * nchunks] * B
+
+
+def test_munk_full_size_full_range_vs_stored_oracle(ssp, gpu):
+    # the benchmark workload at its full size and range (Nz = 4096, 4000 steps, 100 km)
+    # against the oracle's field every 10 km (tests/golden/make_golden.py munk4096)
+    import os
+    from oracle import transmission_loss
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "munk4096_zs1000.npz"))
+    s = W.munk_deep()
+    s.out_every = int(g["out_every"])
+    pl = make_plan(ssp, s)
+    try:
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), int(g["nsteps"]))
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    assert st == int(g["status"]) == OK
+
+    class Ref:
+        field = g["field"]
+        tl = transmission_loss(g["field"], g["ranges"])
+    compare("munk full range", fld, tl, Ref)
