@@ -31,8 +31,9 @@ ssp_status fail(ssp_status s, const std::string &msg) {
                         std::string(#expr) + ": " + hipGetErrorString(e_));               \
     } while (0)
 
-// Largest supported FFT length of the chirp-z transform (LDS capacity of one workgroup).
-constexpr int kMaxP = 16384;
+// Largest supported convolution length of the chirp-z transform: two halves of the largest
+// FFT one workgroup holds in LDS.
+constexpr int kMaxP = 2 * ssp::kMaxEngineFFT;
 
 template <typename T>
 hipError_t dev_alloc(T **p, size_t count) {
@@ -59,6 +60,7 @@ struct ssp_plan {
     float2 *d_k1 = nullptr, *d_k2 = nullptr, *d_dmod = nullptr, *d_post = nullptr, *d_pre = nullptr;
     uint32_t *d_tw = nullptr;
     float4 *d_s = nullptr, *d_bmul = nullptr, *d_alpha = nullptr, *d_beta = nullptr;
+    float4 *d_twist = nullptr;
     // environment
     int prof_mode = ssp::PROF_TABLE_FIXED, v_rows = 0;
     long long v_step0 = 0;
@@ -75,7 +77,7 @@ struct ssp_plan {
     // batched descriptors (device-resident march)
     ssp::SolveDesc *d_descs = nullptr;
     int descs_cap = 0;
-    float2 *d_bwork = nullptr;          // scratch states of a device batch [cap][N]
+    float2 *d_bwork = nullptr;          // scratch of a device batch [cap][kWorkPerSolve N]
     int bwork_cap = 0;
     float2 *d_snap = nullptr;           // output snapshots of a device batch
     size_t snap_cap = 0;
@@ -123,6 +125,7 @@ void free_tables(ssp_plan *pl) {
     dev_free(pl->d_bmul);
     dev_free(pl->d_alpha);
     dev_free(pl->d_beta);
+    dev_free(pl->d_twist);
 }
 
 template <typename D, typename S>
@@ -153,6 +156,7 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     HIP_TRY(dev_alloc(&pl->d_bmul, static_cast<size_t>(p) * N));
     HIP_TRY(dev_alloc(&pl->d_alpha, p));
     HIP_TRY(dev_alloc(&pl->d_beta, p));
+    HIP_TRY(dev_alloc(&pl->d_twist, tab.twist.size() / 4));
     HIP_TRY(upload(pl->d_k1, tab.k1));
     HIP_TRY(upload(pl->d_k2, tab.k2));
     HIP_TRY(upload(pl->d_tw, tab.twiddle));
@@ -163,6 +167,7 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     HIP_TRY(upload(pl->d_bmul, tab.bmul));
     HIP_TRY(upload(pl->d_alpha, tab.alpha));
     HIP_TRY(upload(pl->d_beta, tab.beta));
+    if (!tab.twist.empty()) HIP_TRY(upload(pl->d_twist, tab.twist));
     pl->ps = ps;
     pl->P = P;
     pl->tab = std::move(tab);
@@ -181,6 +186,7 @@ ssp::SolveDesc base_desc(const ssp_plan *pl) {
     d.bmul = pl->d_bmul;
     d.alpha = pl->d_alpha;
     d.beta = pl->d_beta;
+    d.twist = pl->d_twist;
     d.N = pl->N;
     d.P = pl->P;
     d.p = pl->p;
@@ -333,7 +339,7 @@ ssp_status ssp_plan_create(int Nz, double H, double f, double c0, double dr, int
     if (st == SSP_OK) {
         hipError_t e = hipSuccess;
         if (e == hipSuccess) e = dev_alloc(&pl->d_field, Nz);
-        if (e == hipSuccess) e = dev_alloc(&pl->d_work, 2 * static_cast<size_t>(Nz));
+        if (e == hipSuccess) e = dev_alloc(&pl->d_work, ssp::kWorkPerSolve * static_cast<size_t>(Nz));
         if (e == hipSuccess) e = dev_alloc(&pl->d_step, 1);
         if (e == hipSuccess) e = dev_alloc(&pl->d_stats, 1);
         if (e == hipSuccess) e = dev_alloc(&pl->d_desc, 1);
@@ -589,8 +595,7 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
         if (st != SSP_OK) return st;
         ssp::SolveDesc d = base_desc(pl);
         d.field = pl->d_field;
-        d.work = pl->d_work;
-        d.pot = pl->d_work + pl->N;
+        ssp::set_work(d, pl->d_work);
         d.step = pl->d_step;
         d.nout = nout[i];
         d.stats = pl->d_stats;
@@ -698,7 +703,7 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
     if (pl->bwork_cap < B) {
         dev_free(pl->d_bwork);
         pl->bwork_cap = 0;
-        HIP_TRY(dev_alloc(&pl->d_bwork, 2 * static_cast<size_t>(B) * pl->N));
+        HIP_TRY(dev_alloc(&pl->d_bwork, ssp::kWorkPerSolve * static_cast<size_t>(B) * pl->N));
         pl->bwork_cap = B;
     }
     if (!d_stats && pl->bstats_cap < B) {
@@ -720,8 +725,7 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
     for (int b = 0; b < B; ++b) {
         ssp::SolveDesc d = base_desc(pl);
         d.field = static_cast<float2 *>(d_psi) + static_cast<size_t>(b) * pl->N;
-        d.work = pl->d_bwork + 2 * static_cast<size_t>(b) * pl->N;
-        d.pot = d.work + pl->N;
+        ssp::set_work(d, pl->d_bwork + ssp::kWorkPerSolve * static_cast<size_t>(b) * pl->N);
         d.nout = nout;
         d.step = static_cast<long long *>(d_step) + b;
         d.stats = (d_stats ? static_cast<ssp::DevStats *>(d_stats) : pl->d_bstats) + b;

@@ -29,6 +29,7 @@ struct SolveDesc {
     const float2 *pre;          // [N] conj chirp (physical -> chirp-z input)
     const float4 *s, *bmul;     // [p][N] double-float
     const float4 *alpha, *beta; // [p] double-float
+    const float4 *twist;        // [P/2] double-float w_P^n (split transforms, P > 16384), else null
     int N, P, p, nmax;
     double tol2;                // tol^2 (squared-norm test)
     double sigma;               // k0 dr (carrier phase per step)
@@ -40,6 +41,8 @@ struct SolveDesc {
     float2 *field;              // [N] sine-basis state (modulated representation)
     float2 *work;               // [N] scratch state between Pade factors
     float2 *pot;                // [N] scratch potential A = v (.) dmod of the current step
+    float2 *wacc;               // [N] scratch Neumann partial sum (kernels that do not hold it in registers)
+    float2 *xs;                 // [2N] scratch of split transforms
     long long *step;            // global step counter
     DevStats *stats;
     float2 *snap;               // [nout][N] sine-basis snapshots at output steps, or null
@@ -51,6 +54,15 @@ struct SolveDesc {
 
 // Launch the fused persistent march: one workgroup per descriptor, all with the same FFT
 // length P.  Returns hipSuccess or the launch error.
+// Scratch elements (complex) per solve behind SolveDesc::work: work, pot, wacc, xs.
+constexpr int kWorkPerSolve = 5;
+inline void set_work(SolveDesc &d, float2 *base) {
+    d.work = base;
+    d.pot = base + d.N;
+    d.wacc = base + 2 * static_cast<size_t>(d.N);
+    d.xs = base + 3 * static_cast<size_t>(d.N);
+}
+
 hipError_t launch_march(int P, const SolveDesc *d_descs, int nsolves, int nsteps,
                         hipStream_t stream);
 

@@ -2,12 +2,20 @@
 //
 // Transform (Sec. 3.1): the orthonormal DST-I of length N on the interior Dirichlet grid
 // is evaluated as a chirp-z transform.  With M = N+1 and c_d = exp(i pi d^2/(2M)),
-//   DST(x)_k = (i/2) sqrt(2/M) conj(c_k) sum_{n=1..N} conj(c_n) x_n (c_{k-n} - c_{k+n}),
-// i.e. a Toeplitz term (kernel window d in [1-N, N-1]) minus a Hankel term (window
-// d in [2, 2N]).  Both are cyclic convolutions of length P >= 2N-1 (a power of two), and the
-// Hankel term is the Toeplitz form of the index-reversed input, whose spectrum is the
-// reflected spectrum Y_{-q}.  One DST therefore costs one forward FFT of length P, a
-// pointwise combine Z_q = Y_q K1_q - Y_{-q} K2_q, and one inverse FFT.
+//   DST(x)_k = (i/2) sqrt(2/M) conj(c_k) sum_{n=1..N} conj(c_n) x_n (c_{k-n} - c_{k+n}).
+// Element n of a vector sits at chirp position n-1 (0 .. N-1), so the sum is a Toeplitz
+// term (kernel window d in [1-N, N-1]) minus a Hankel term (c_{d+2}, d in [0, 2N-2]).  Both
+// are cyclic convolutions of length P >= 2N-1 (a power of two), and the Hankel term is the
+// Toeplitz form of the index-reversed input, whose spectrum is the reflected spectrum
+// Y_{-q}.  One DST therefore costs one forward FFT of length P, a pointwise combine
+// Z_q = Y_q K1_q - Y_{-q} K2_q, and one inverse FFT.
+//
+// Lengths above the largest FFT one workgroup holds in LDS (P = 2H, H = 16384): the input
+// occupies positions below H, so the even-frequency half of FFT_P(y) is FFT_H(y) and the
+// odd half is FFT_H(y (.) w_P^n).  The reflection q -> -q maps each half onto itself (even:
+// k -> -k mod H; odd: k -> H-1-k), so the combine never mixes them, and the inverse is
+// z_n = IFFT_H(Z_even)_n + w_P^{-n} IFFT_H(Z_odd)_n.  One DST is then two independent
+// H-point chirp cores.
 //
 // Range step (Sec. 3 eq. neumannseries; Alg. 1): the state is kept in the sine basis
 // multiplied by conj(c_l) (the "modulated" representation), so that the chirp factors of
@@ -30,6 +38,7 @@ namespace ssp {
 namespace {
 
 constexpr int kOK = 0, kNotConverged = 1, kDiverged = -4;
+
 
 // ----------------------------------------------------------------------------- complex
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -377,7 +386,8 @@ __device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, c
 }
 
 // Z_q = Y_q K1_q - Y_{-q} K2_q for the distributed spectrum (one LDS exchange, phase PH).
-template <int P, int PH>
+// ODD: the odd-frequency half of a split transform, whose reflection is q -> P-1-q.
+template <int P, int PH, bool ODD>
 __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const LdsBufs &L,
                                               const float2 *__restrict__ k1,
                                               const float2 *__restrict__ k2) {
@@ -392,23 +402,84 @@ __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const Lds
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
         const int q = t2 + i * T;
-        const int qr = (P - q) & (P - 1);
+        const int qr = ODD ? (P - 1 - q) : ((P - q) & (P - 1));
         const float2 yr = buf[lp<P>(qr)];
         x[i] = csub(cmul(x[i], ld2(k1, q)), cmul(yr, ld2(k2, q)));
     }
 }
 
-// The chirp-z core of one DST: x <- IFFT(comb(FFT(x))) (unnormalised), x distributed by
-// position; positions 0 and > N must hold zeros on entry.  Phases 0 .. 2F (F = passes - 1);
-// the opening barrier separates them from the previous core's last reads.
-template <int P>
+// The chirp-z core of one DST on P positions: x <- IFFT(comb(FFT(x))) (unnormalised), x
+// distributed by position; positions >= N must hold zeros on entry.  Phases 0 .. 2F
+// (F = passes - 1); the opening barrier separates them from the previous core's last reads.
+template <int P, bool ODD>
 __device__ __forceinline__ void chirp_core(float2 (&x)[Cfg<P>::RT], const LdsBufs &L,
-                                           const Twiddles<P> &tw, const SolveDesc &d) {
+                                           const Twiddles<P> &tw, const float2 *k1, const float2 *k2) {
     constexpr int F = fft_phases<P>();
     __syncthreads();
     fft<P, false, 0>(x, L, tw);
-    chirp_combine<P, F>(x, L, d.k1, d.k2);
+    chirp_combine<P, F, ODD>(x, L, k1, k2);
     fft<P, true, F + 1>(x, L, tw);
+}
+
+// Largest FFT held by one workgroup, and the engine length of a convolution length P.
+constexpr int kMaxEngine = 16384;
+template <int P>
+constexpr int eng_len() { return P > kMaxEngine ? P / 2 : P; }
+template <int P>
+using ECfg = Cfg<eng_len<P>()>;
+
+// One DST core for convolution length P (positions 0 .. eng_len-1 distributed as in the
+// engine).  For P above kMaxEngine the odd-frequency half needs the input again after the
+// even half has overwritten x: KEEP_GLOBAL keeps it (and the even result) in the solve's
+// scratch keep[0 .. 2N), else in registers.  Both give identical results.  Positions >= N
+// of the result are zero.
+template <int P, bool KEEP_GLOBAL>
+__device__ __forceinline__ void dst_core(float2 (&x)[ECfg<P>::RT], const LdsBufs &L,
+                                         const Twiddles<eng_len<P>()> &tw, const SolveDesc &d,
+                                         float2 *keep) {
+    constexpr int H = eng_len<P>();
+    if constexpr (H == P) {
+        chirp_core<P, false>(x, L, tw, d.k1, d.k2);
+    } else {
+        constexpr int T = Cfg<H>::T, RT = Cfg<H>::RT;
+        const int N = d.N;
+        float2 y[KEEP_GLOBAL ? 1 : RT];
+        // odd-frequency input y = x (.) w_P^n
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+            const int pos = opaque_tid() + i * T;
+            float2 v = make_float2(0.f, 0.f);
+            if (pos < N) v = cmul_df(x[i], ld4(d.twist, pos));
+            if constexpr (KEEP_GLOBAL) {
+                if (pos < N) st2(keep, pos, v);
+            } else {
+                y[i] = v;
+            }
+        }
+        chirp_core<H, false>(x, L, tw, d.k1, d.k2);
+        if constexpr (KEEP_GLOBAL) {
+#pragma unroll
+            for (int i = 0; i < RT; ++i) {
+                const int pos = opaque_tid() + i * T;
+                if (pos < N) st2(keep + N, pos, x[i]);
+                x[i] = pos < N ? ld2(keep, pos) : make_float2(0.f, 0.f);
+            }
+            chirp_core<H, true>(x, L, tw, d.k1 + H, d.k2 + H);
+#pragma unroll
+            for (int i = 0; i < RT; ++i) {
+                const int pos = opaque_tid() + i * T;
+                x[i] = pos < N ? cadd(ld2(keep + N, pos), cmul_df_conj(x[i], ld4(d.twist, pos)))
+                               : make_float2(0.f, 0.f);
+            }
+        } else {
+            chirp_core<H, true>(y, L, tw, d.k1 + H, d.k2 + H);
+#pragma unroll
+            for (int i = 0; i < RT; ++i) {
+                const int pos = opaque_tid() + i * T;
+                x[i] = pos < N ? cadd(x[i], cmul_df_conj(y[i], ld4(d.twist, pos))) : make_float2(0.f, 0.f);
+            }
+        }
+    }
 }
 
 #define SSP_LDS_DECL(P)                                                        \
@@ -492,11 +563,11 @@ __device__ __forceinline__ float eddy_correction(const SolveDesc &d, float vm, f
     return q * (-e * (2.0f + e) / ((1.0f + e) * (1.0f + e)));
 }
 
-// A = v (.) dmod at the thread's positions (zero outside 1..N); v of global step n.
+// A = v (.) dmod at the thread's positions (zero at positions >= N); v of global step n.
 // Written to registers (A) when the kernel keeps it there, else to the solve's pot array.
 template <int P, bool IN_REGS>
 __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, float2 *A) {
-    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
     const int N = d.N;
     long long row = 0;
     if (d.prof_mode == PROF_TABLE_STEPS) {
@@ -507,12 +578,12 @@ __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, 
     const float r = static_cast<float>((static_cast<double>(n) - 0.5) * d.dr);
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-        const int pos = opaque_tid() + i * T, m = pos - 1;
+        const int pos = opaque_tid() + i * T, m = pos;
         float2 val = make_float2(0.f, 0.f);
-        if (pos >= 1 && pos <= N) {
+        if (pos < N) {
             float v = ldf(vrow, m);
             if (d.prof_mode == PROF_ANALYTIC)
-                v += eddy_correction(d, v, static_cast<float>(pos * d.dz), r);
+                v += eddy_correction(d, v, static_cast<float>((pos + 1) * d.dz), r);
             const float2 dm = ld2(d.dmod, m);
             val = make_float2(v * dm.x, v * dm.y);
             if constexpr (!IN_REGS) st2(d.pot, m, val);
@@ -524,27 +595,32 @@ __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, 
 // ----------------------------------------------------------------------------- march
 // One workgroup marches one solve (descriptor blockIdx.x) through nsteps range steps.
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict__ descs, int nsteps) {
-    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+__global__ __launch_bounds__(ECfg<P>::T) void k_march(const SolveDesc *__restrict__ descs, int nsteps) {
+    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
     // the Neumann multiplier stays in registers for up to 8 elements per thread
     constexpr bool kBInRegs = (RT <= 8) && (T < 1024);
     constexpr int EB = kBInRegs ? RT : 1;
     // ... and so does the potential A = v (.) dmod; otherwise both come from L2
     constexpr bool kAInRegs = kBInRegs;
     constexpr int EA = kAInRegs ? RT : 1;
-    SSP_LDS_DECL(P);
+    // the series sum w_j stays in registers below 1024 threads (else in d.wacc)
+    constexpr bool kWInRegs = T < 1024;
+    constexpr int EW = kWInRegs ? RT : 1;
+    // split transforms keep their second input in the solve's scratch (fewer spills)
+    constexpr bool kKeepGlobal = true;
+    SSP_LDS_DECL(eng_len<P>());
     __shared__ double red[2 * (T / 64)];
     const SolveDesc &d = descs[blockIdx.x];
     const int tid = threadIdx.x;
     const int N = d.N, p = d.p, nmax = d.nmax;
-    Twiddles<P> tw;
-    init_twiddles<P>(tw, lds_th, lds_tl, d.tw);
+    Twiddles<eng_len<P>()> tw;
+    init_twiddles<eng_len<P>()>(tw, lds_th, lds_tl, d.tw);
 
     // The state u is not held in registers: d.field holds the state at the start of the
     // step (the recovery point if the step diverges) and d.work the state between Pade
     // factors.  Every thread reads and writes only its own positions, so these global
     // accesses need no barriers.
-    float2 w[RT], a[RT], A[EA];
+    float2 w[EW], a[RT], A[EA];
     float4 Bm[EB];
     long long n = *d.step;
     // outputs of this launch: steps out_base, out_base + out_every, ... (row = slot)
@@ -566,15 +642,16 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
             float t0f = 0.f;
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
-                const int pos = opaque_tid() + i * T, m = pos - 1;
-                if (pos >= 1 && pos <= N) {
+                const int pos = opaque_tid() + i * T, m = pos;
+                if (pos < N) {
                     a[i] = cmul_df(ld2(cur, m), ld4(d.s, j * N + m));
                     if constexpr (kBInRegs) Bm[i] = ld4(d.bmul, j * N + m);
                 } else {
                     a[i] = make_float2(0.f, 0.f);
                     if constexpr (kBInRegs) Bm[i] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                w[i] = a[i];
+                if constexpr (kWInRegs) w[i] = a[i];
+                else if (pos < N) st2(d.wacc, m, a[i]);
                 t0f += cnorm2(a[i]);
             }
             double t0 = t0f, dummy = 0.0;
@@ -585,7 +662,7 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
             // half-iteration h: even -> a = A (.) S a (multiply by v); odd -> a = B_j (.) S a
             // (diagonal solve) and the term is accumulated; one transform site per loop
             for (int h = 0; h < 2 * nmax; ++h) {
-                chirp_core<P>(a, L, tw, d);
+                dst_core<P, kKeepGlobal>(a, L, tw, d, d.xs);
                 if ((h & 1) == 0) {
 #pragma unroll
                     for (int i = 0; i < RT; ++i) {
@@ -593,7 +670,7 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
                             a[i] = cmul(A[i], a[i]);
                         } else {
                             const int pos = opaque_tid() + i * T;
-                            a[i] = (pos >= 1 && pos <= N) ? cmul(ld2(d.pot, pos - 1), a[i]) : make_float2(0.f, 0.f);
+                            a[i] = (pos < N) ? cmul(ld2(d.pot, pos), a[i]) : make_float2(0.f, 0.f);
                         }
                     }
                     continue;
@@ -604,12 +681,18 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
                     const int pos = opaque_tid() + i * T;
                     float4 bm;
                     if constexpr (kBInRegs) bm = Bm[i];
-                    else bm = (pos >= 1 && pos <= N) ? ld4(d.bmul, j * N + pos - 1)
+                    else bm = (pos < N) ? ld4(d.bmul, j * N + pos)
                                                      : make_float4(0.f, 0.f, 0.f, 0.f);
                     a[i] = cmul_df(a[i], bm);
-                    w[i] = cadd(w[i], a[i]);
                     tnf += cnorm2(a[i]);
-                    wnf += cnorm2(w[i]);
+                    if constexpr (kWInRegs) {
+                        w[i] = cadd(w[i], a[i]);
+                        wnf += cnorm2(w[i]);
+                    } else if (pos < N) {
+                        const float2 ws = cadd(ld2(d.wacc, pos), a[i]);
+                        st2(d.wacc, pos, ws);
+                        wnf += cnorm2(ws);
+                    }
                 }
                 tn = tnf;
                 wn = wnf;
@@ -642,8 +725,11 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
             const float4 al = ld4(d.alpha, j), be = ld4(d.beta, j);
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
-                const int pos = opaque_tid() + i * T, m = pos - 1;
-                if (pos >= 1 && pos <= N) st2(d.work, m, cadd(cmul_df(ld2(cur, m), al), cmul_df(w[i], be)));
+                const int pos = opaque_tid() + i * T, m = pos;
+                if (pos < N) {
+                    const float2 ws = kWInRegs ? w[i] : ld2(d.wacc, m);
+                    st2(d.work, m, cadd(cmul_df(ld2(cur, m), al), cmul_df(ws, be)));
+                }
             }
         }
         if (bad) {
@@ -653,8 +739,8 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
         // commit the step
 #pragma unroll
         for (int i = 0; i < RT; ++i) {
-            const int pos = opaque_tid() + i * T, m = pos - 1;
-            if (pos >= 1 && pos <= N) st2(d.field, m, ld2(d.work, m));
+            const int pos = opaque_tid() + i * T, m = pos;
+            if (pos < N) st2(d.field, m, ld2(d.work, m));
         }
         n = nn;
         ++done;
@@ -665,8 +751,8 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
             if (n >= out_base && slot < d.nout) {
 #pragma unroll
                 for (int i = 0; i < RT; ++i) {
-                    const int pos = opaque_tid() + i * T, m = pos - 1;
-                    if (pos >= 1 && pos <= N) st2(d.snap + slot * N, m, ld2(d.field, m));
+                    const int pos = opaque_tid() + i * T, m = pos;
+                    if (pos < N) st2(d.snap + slot * N, m, ld2(d.field, m));
                 }
             }
         }
@@ -689,35 +775,35 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_march(const SolveDesc *__restrict
 
 // ----------------------------------------------------------------------------- transforms
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::T) void k_transform(const SolveDesc *__restrict__ desc, int mode,
+__global__ __launch_bounds__(ECfg<P>::T) void k_transform(const SolveDesc *__restrict__ desc, int mode,
                                                          const float2 *__restrict__ in, float2 *out,
                                                          const long long *__restrict__ step) {
-    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
-    SSP_LDS_DECL(P);
+    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
+    SSP_LDS_DECL(eng_len<P>());
     const SolveDesc &d = *desc;
     const int N = d.N, tid = threadIdx.x;
-    Twiddles<P> tw;
-    init_twiddles<P>(tw, lds_th, lds_tl, d.tw);
+    Twiddles<eng_len<P>()> tw;
+    init_twiddles<eng_len<P>()>(tw, lds_th, lds_tl, d.tw);
     const float2 *vin = in + static_cast<size_t>(blockIdx.x) * N;
     float2 *vout = out + static_cast<size_t>(blockIdx.x) * N;
     float2 x[RT];
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-        const int pos = opaque_tid() + i * T, m = pos - 1;
+        const int pos = opaque_tid() + i * T, m = pos;
         float2 v = make_float2(0.f, 0.f);
-        if (pos >= 1 && pos <= N) {
+        if (pos < N) {
             v = ld2(vin, m);
             if (mode != 2) v = cmul(v, ld2(d.pre, m));
         }
         x[i] = v;
     }
-    chirp_core<P>(x, L, tw, d);
+    dst_core<P, false>(x, L, tw, d, nullptr);
     float2 car = make_float2(1.f, 0.f);
     if (mode == 2) car = carrier(d.sigma, step[blockIdx.x]);
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-        const int pos = opaque_tid() + i * T, m = pos - 1;
-        if (pos >= 1 && pos <= N) {
+        const int pos = opaque_tid() + i * T, m = pos;
+        if (pos < N) {
             float2 v = cmul(x[i], mode == 1 ? ld2(d.dmod, m) : ld2(d.post, m));
             if (mode == 2) v = cmul(v, car);
             st2(vout, m, v);
@@ -729,15 +815,15 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_transform(const SolveDesc *__rest
 // with the carrier of its step -> field row (complex64, in place over the snapshot when
 // fld_out == snap) and TL row.
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::T) void k_output(const SolveDesc *__restrict__ descs, int nout) {
-    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
-    SSP_LDS_DECL(P);
+__global__ __launch_bounds__(ECfg<P>::T) void k_output(const SolveDesc *__restrict__ descs, int nout) {
+    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
+    SSP_LDS_DECL(eng_len<P>());
     const int b = blockIdx.x / nout, row = blockIdx.x % nout;
     const SolveDesc &d = descs[b];
     if (row >= d.nout || !d.snap || !d.stats || d.out_every <= 0) return;  // uniform
     const int N = d.N, tid = threadIdx.x;
-    Twiddles<P> tw;
-    init_twiddles<P>(tw, lds_th, lds_tl, d.tw);
+    Twiddles<eng_len<P>()> tw;
+    init_twiddles<eng_len<P>()>(tw, lds_th, lds_tl, d.tw);
     // the march that wrote the snapshots started at step step_index - steps_done
     const long long n0 = d.stats->step_index - d.stats->steps_done;
     const long long n = (n0 / d.out_every + 1) * d.out_every + static_cast<long long>(row) * d.out_every;
@@ -747,15 +833,15 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_output(const SolveDesc *__restric
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
         const int pos = tid + i * T;
-        x[i] = (pos >= 1 && pos <= N) ? ld2(src, pos - 1) : make_float2(0.f, 0.f);
+        x[i] = (pos < N) ? ld2(src, pos) : make_float2(0.f, 0.f);
     }
-    chirp_core<P>(x, L, tw, d);
+    dst_core<P, false>(x, L, tw, d, nullptr);
     const float2 car = carrier(d.sigma, n);
     const float lr = log10f(static_cast<float>(static_cast<double>(n) * d.dr));
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-        const int pos = tid + i * T, m = pos - 1;
-        if (pos >= 1 && pos <= N) {
+        const int pos = tid + i * T, m = pos;
+        if (pos < N) {
             const float2 ph = cmul(cmul(ld2(d.post, m), x[i]), car);
             if (d.fld_out) st2(d.fld_out + static_cast<size_t>(row) * N, m, ph);
             if (d.tl_out) stf(d.tl_out + static_cast<size_t>(row) * N, m, -10.0f * (log10f(ph.x * ph.x + ph.y * ph.y) - lr));
@@ -775,9 +861,9 @@ struct PlainState {
 };
 
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::T) void k_plain_start(const SolveDesc *__restrict__ desc, float2 *a, float2 *w,
+__global__ __launch_bounds__(ECfg<P>::T) void k_plain_start(const SolveDesc *__restrict__ desc, float2 *a, float2 *w,
                                                              PlainState *ps, int j) {
-    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
     __shared__ double red[2 * (T / 64)];
     const SolveDesc &d = *desc;
     if (ps->halt) return;
@@ -786,8 +872,8 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_plain_start(const SolveDesc *__re
     float part = 0.f;
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-        const int pos = opaque_tid() + i * T, m = pos - 1;
-        if (pos >= 1 && pos <= N) {
+        const int pos = opaque_tid() + i * T, m = pos;
+        if (pos < N) {
             const float2 v = cmul_df(ld2(cur, m), ld4(d.s, j * N + m));
             st2(a, m, v);
             st2(w, m, v);
@@ -807,38 +893,38 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_plain_start(const SolveDesc *__re
 }
 
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::T) void k_plain_half(const SolveDesc *__restrict__ desc, float2 *a, float2 *w,
+__global__ __launch_bounds__(ECfg<P>::T) void k_plain_half(const SolveDesc *__restrict__ desc, float2 *a, float2 *w,
                                                             PlainState *ps, int j, int h, long long n) {
-    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
-    SSP_LDS_DECL(P);
+    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
+    SSP_LDS_DECL(eng_len<P>());
     __shared__ double red[2 * (T / 64)];
     const SolveDesc &d = *desc;
     if (ps->halt || ps->done) return;  // uniform: the series has stopped
-    Twiddles<P> tw;
-    init_twiddles<P>(tw, lds_th, lds_tl, d.tw);
+    Twiddles<eng_len<P>()> tw;
+    init_twiddles<eng_len<P>()>(tw, lds_th, lds_tl, d.tw);
     const int N = d.N;
     float2 x[RT];
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
         const int pos = opaque_tid() + i * T;
-        x[i] = (pos >= 1 && pos <= N) ? ld2(a, pos - 1) : make_float2(0.f, 0.f);
+        x[i] = (pos < N) ? ld2(a, pos) : make_float2(0.f, 0.f);
     }
-    chirp_core<P>(x, L, tw, d);
+    dst_core<P, false>(x, L, tw, d, nullptr);
     if ((h & 1) == 0) {
         float2 A[RT];
         load_potential<P, true>(d, n, A);
 #pragma unroll
         for (int i = 0; i < RT; ++i) {
             const int pos = opaque_tid() + i * T;
-            if (pos >= 1 && pos <= N) st2(a, pos - 1, cmul(A[i], x[i]));
+            if (pos < N) st2(a, pos, cmul(A[i], x[i]));
         }
         return;
     }
     float tnf = 0.f, wnf = 0.f;
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-        const int pos = opaque_tid() + i * T, m = pos - 1;
-        if (pos >= 1 && pos <= N) {
+        const int pos = opaque_tid() + i * T, m = pos;
+        if (pos < N) {
             const float2 v = cmul_df(x[i], ld4(d.bmul, j * N + m));
             const float2 ww = cadd(ld2(w, m), v);
             st2(a, m, v);
@@ -864,9 +950,9 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_plain_half(const SolveDesc *__res
 
 // End of a Pade factor: statistics, divergence test, product-form combine into d.work.
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::T) void k_plain_finish(const SolveDesc *__restrict__ desc, const float2 *w,
+__global__ __launch_bounds__(ECfg<P>::T) void k_plain_finish(const SolveDesc *__restrict__ desc, const float2 *w,
                                                               PlainState *ps, int j) {
-    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
     const SolveDesc &d = *desc;
     if (ps->halt) return;
     const bool conv = ps->done && !ps->bad;
@@ -894,15 +980,15 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_plain_finish(const SolveDesc *__r
     const float4 al = ld4(d.alpha, j), be = ld4(d.beta, j);
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-        const int pos = opaque_tid() + i * T, m = pos - 1;
-        if (pos >= 1 && pos <= N) st2(d.work, m, cadd(cmul_df(ld2(cur, m), al), cmul_df(ld2(w, m), be)));
+        const int pos = opaque_tid() + i * T, m = pos;
+        if (pos < N) st2(d.work, m, cadd(cmul_df(ld2(cur, m), al), cmul_df(ld2(w, m), be)));
     }
 }
 
 // End of a step: commit, counters, output snapshot.
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::T) void k_plain_commit(const SolveDesc *__restrict__ desc, PlainState *ps) {
-    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+__global__ __launch_bounds__(ECfg<P>::T) void k_plain_commit(const SolveDesc *__restrict__ desc, PlainState *ps) {
+    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
     const SolveDesc &d = *desc;
     if (ps->halt) return;
     const int N = d.N;
@@ -913,8 +999,8 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_plain_commit(const SolveDesc *__r
     const bool snap = d.snap && d.out_every > 0 && (n % d.out_every) == 0 && n >= out_base && slot < d.nout;
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-        const int pos = opaque_tid() + i * T, m = pos - 1;
-        if (pos >= 1 && pos <= N) {
+        const int pos = opaque_tid() + i * T, m = pos;
+        if (pos < N) {
             const float2 v = ld2(d.work, m);
             st2(d.field, m, v);
             if (snap) st2(d.snap + slot * N, m, v);
@@ -931,7 +1017,7 @@ __global__ __launch_bounds__(Cfg<P>::T) void k_plain_commit(const SolveDesc *__r
 template <int P>
 hipError_t plain_march_P(const SolveDesc &hd, const SolveDesc *dd, int nsteps, float2 *work,
                          void *state, hipStream_t stream) {
-    constexpr int T = Cfg<P>::T;
+    constexpr int T = ECfg<P>::T;
     float2 *a = work, *w = work + hd.N;
     PlainState *ps = static_cast<PlainState *>(state);
     long long n0 = 0;
@@ -955,20 +1041,20 @@ hipError_t plain_march_P(const SolveDesc &hd, const SolveDesc *dd, int nsteps, f
 
 template <int P>
 hipError_t launch_output_P(const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream) {
-    hipLaunchKernelGGL((k_output<P>), dim3(nsolves * nout), dim3(Cfg<P>::T), 0, stream, d_descs, nout);
+    hipLaunchKernelGGL((k_output<P>), dim3(nsolves * nout), dim3(ECfg<P>::T), 0, stream, d_descs, nout);
     return hipGetLastError();
 }
 
 template <int P>
 hipError_t launch_march_P(const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
-    hipLaunchKernelGGL((k_march<P>), dim3(nsolves), dim3(Cfg<P>::T), 0, stream, d_descs, nsteps);
+    hipLaunchKernelGGL((k_march<P>), dim3(nsolves), dim3(ECfg<P>::T), 0, stream, d_descs, nsteps);
     return hipGetLastError();
 }
 
 template <int P>
 hipError_t launch_transform_P(int mode, const SolveDesc *d_desc, int B, const float2 *in,
                               float2 *out, const long long *step, hipStream_t stream) {
-    hipLaunchKernelGGL((k_transform<P>), dim3(B), dim3(Cfg<P>::T), 0, stream, d_desc, mode, in, out, step);
+    hipLaunchKernelGGL((k_transform<P>), dim3(B), dim3(ECfg<P>::T), 0, stream, d_desc, mode, in, out, step);
     return hipGetLastError();
 }
 
@@ -976,7 +1062,7 @@ hipError_t launch_transform_P(int mode, const SolveDesc *d_desc, int B, const fl
 
 bool fft_length_supported(int P) {
     return P == 128 || P == 256 || P == 512 || P == 1024 || P == 2048 || P == 4096 || P == 8192 ||
-           P == 16384;
+           P == 16384 || P == 32768;
 }
 
 #define SSP_DISPATCH_P(P, CALL) \
@@ -989,6 +1075,7 @@ bool fft_length_supported(int P) {
         case 4096: return CALL(4096);   \
         case 8192: return CALL(8192);   \
         case 16384: return CALL(16384); \
+        case 32768: return CALL(32768); \
         default: return hipErrorInvalidValue; \
     }
 

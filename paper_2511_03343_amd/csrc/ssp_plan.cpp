@@ -281,17 +281,30 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, DeviceTabl
         return cd(static_cast<double>(std::cos(ang)), static_cast<double>(std::sin(ang)));
     };
     std::vector<cd> K1(P, 0.0), K2(P, 0.0);
+    // element n (1..N) at position n-1: Toeplitz window c_{k-n}, Hankel window c_{(k-1)+(n-1)+2}
     for (long long d = 1 - N; d <= N - 1; ++d) K1[((d % P) + P) % P] = chirp(d);
-    for (long long d = 2; d <= 2LL * N; ++d) K2[d % P] = chirp(d);
+    for (long long d = 0; d <= 2LL * N - 2; ++d) K2[d % P] = chirp(d + 2);
     host_fft(K1, -1);
     host_fft(K2, -1);
+    const bool split = P > kMaxEngineFFT;
+    const int PE = split ? P / 2 : P;
     t.k1.resize(2 * P);
     t.k2.resize(2 * P);
     for (int q = 0; q < P; ++q) {
-        t.k1[2 * q] = static_cast<float>(K1[q].real());
-        t.k1[2 * q + 1] = static_cast<float>(K1[q].imag());
-        t.k2[2 * q] = static_cast<float>(K2[q].real());
-        t.k2[2 * q + 1] = static_cast<float>(K2[q].imag());
+        const int slot = split ? ((q & 1) ? PE + q / 2 : q / 2) : q;
+        t.k1[2 * slot] = static_cast<float>(K1[q].real());
+        t.k1[2 * slot + 1] = static_cast<float>(K1[q].imag());
+        t.k2[2 * slot] = static_cast<float>(K2[q].real());
+        t.k2[2 * slot + 1] = static_cast<float>(K2[q].imag());
+    }
+    t.twist.clear();
+    if (split) {
+        t.twist.resize(4 * static_cast<size_t>(PE));
+        for (int n = 0; n < PE; ++n) {
+            long double ang = -2 * kPi * static_cast<long double>(n) / P;
+            split_df(static_cast<double>(std::cos(ang)), t.twist[4 * n], t.twist[4 * n + 2]);
+            split_df(static_cast<double>(std::sin(ang)), t.twist[4 * n + 1], t.twist[4 * n + 3]);
+        }
     }
     const double scale = 0.5 * std::sqrt(2.0 / M) / P;  // (i/2) sqrt(2/M) / P, i applied below
     const cd I(0, 1);
@@ -310,10 +323,10 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, DeviceTabl
         t.dmod[2 * (n - 1)] = static_cast<float>(dmod[n - 1].real());
         t.dmod[2 * (n - 1) + 1] = static_cast<float>(dmod[n - 1].imag());
     }
-    const int O = P / 8;
+    const int O = PE / 8;
     t.twiddle.resize(3 * static_cast<size_t>(O + 1));
     for (int e = 0; e <= O; ++e) {
-        long double ang = -2 * kPi * static_cast<long double>(e) / P;
+        long double ang = -2 * kPi * static_cast<long double>(e) / PE;
         double re = static_cast<double>(std::cos(ang)), im = static_cast<double>(std::sin(ang));
         float hr, lr, hi, li;
         split_df(re, hr, lr);

@@ -40,17 +40,26 @@ void host_fft(std::vector<cd> &x, int sign);
 // Smallest FFT length accepted by the device engine that is >= n_min.
 int chirp_fft_length(int n_min);
 
+// Largest FFT one workgroup computes in LDS; longer convolutions are split in two.
+constexpr int kMaxEngineFFT = 16384;
+
 struct DeviceTables {
     int nz = 0, P = 0;
     // chirp-z DST (orthonormal DST-I of length nz through a cyclic convolution of length P):
-    std::vector<float> k1, k2;        // [P] complex FP32 spectra of the two chirp windows
+    // [P] complex FP32 spectra of the two chirp windows (Toeplitz c_d, d in [1-nz, nz-1];
+    // Hankel c_{d+2}, d in [0, 2nz-2]).  For P > kMaxEngineFFT they are stored as the even
+    // frequencies followed by the odd ones (the two halves of a split transform).
+    std::vector<float> k1, k2;
     std::vector<float> pre;           // [nz] complex FP32  conj(c_n)
     std::vector<float> post;          // [nz] complex FP32  conj(c_k) (i/2) sqrt(2/(nz+1)) / P
     std::vector<float> dmod;          // [nz] complex FP32  conj(c_k)^2 (i/2) sqrt(2/(nz+1)) / P
-    // exp(-2 pi i e / P) for e = 0..P/8 (the first octant; the device rebuilds the other
-    // octants by symmetry): per entry hi.re, hi.im (FP32 bit patterns) and the rounding
-    // remainders lo.re, lo.im packed as two bfloat16 (re in the high half)
+    // exp(-2 pi i e / PE) for e = 0..PE/8, PE = the engine FFT length (P, or P/2 when split;
+    // the first octant, the device rebuilds the other octants by symmetry): per entry
+    // hi.re, hi.im (FP32 bit patterns) and the rounding remainders lo.re, lo.im packed as two
+    // bfloat16 (re in the high half)
     std::vector<uint32_t> twiddle;
+    // split transforms only: [P/2] double-float complex exp(-2 pi i n / P)
+    std::vector<float> twist;
     // Pade factors in the chirp-modulated sine basis:
     std::vector<float> s;             // [p][nz] double-float complex 1/(1 + b_j x_l)
     std::vector<float> bmul;          // [p][nz] double-float complex -b_j s_jl * dmod_l (FP64 product)

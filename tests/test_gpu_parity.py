@@ -60,7 +60,9 @@ def compare(tag, fld, tl, ref, rel=REL_L2, dtl=DTL):
 
 
 # ------------------------------------------------------------------------------- transform
-@pytest.mark.parametrize("nz", [2, 3, 5, 16, 63, 64, 100, 255, 256, 257, 1000, 2047, 4096, 5000, 8192])
+# up to 8192: one FFT per transform; above: the split transform (two half-length cores)
+@pytest.mark.parametrize("nz", [2, 3, 5, 16, 63, 64, 100, 255, 256, 257, 1000, 2047, 4096, 5000, 8192,
+                                8193, 12345, 16384])
 def test_dst_parity(ssp, gpu, nz):
     torch = gpu
     B = 3
@@ -116,7 +118,7 @@ def test_homogeneous_waveguide(ssp, gpu):
     compare("homogeneous", fld, tl, ref)
 
 
-@pytest.mark.parametrize("nz,nsteps", [(2, 50), (3, 50), (127, 200), (511, 400), (1000, 100)])
+@pytest.mark.parametrize("nz,nsteps", [(2, 50), (3, 50), (127, 200), (511, 400), (1000, 100), (9000, 12)])
 def test_munk_small(ssp, gpu, nz, nsteps):
     s = W.munk_deep(nsteps=nsteps, nz=nz)
     # on the coarsest grids the source Gaussian falls between grid points: use a seeded
@@ -177,6 +179,25 @@ def test_eddy_range_dependent(ssp, gpu, profile):
     ref = oracle_march(s)
     assert st == ref.status
     compare(f"eddy {profile}", fld, tl, ref)
+
+
+@pytest.mark.parametrize("profile", ["table", "analytic"])
+def test_eddy_full_size_start(ssp, gpu, profile):
+    # Munk + eddy at its full size (200 Hz, Nz = 16384, [8/8], Neumann <= 12, dr = 20 m):
+    # the first 10 steps, split transforms throughout
+    s = W.munk_eddy(nsteps=10)
+    pl = make_plan(ssp, s, profile=profile)
+    try:
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    _report(f"eddy full start {profile}", status=st, oracle_status=ref.status,
+            terms=stats["neumann_terms"], oracle_terms=int(ref.iterations.sum()),
+            not_converged=stats["not_converged"])
+    assert st in (OK, NOT_CONVERGED) and ref.status in (OK, NOT_CONVERGED)
+    assert stats["steps_done"] == ref.steps_done == s.nsteps
+    compare(f"eddy full start {profile}", fld, tl, ref)
 
 
 # ------------------------------------------------------------------------------- statuses
@@ -282,7 +303,7 @@ def test_device_batch_matches_host_march(ssp, gpu):
     assert np.array_equal(got.astype(np.complex128), np.stack(host))
 
 
-@pytest.mark.parametrize("nz,env", [(511, "munk"), (300, "munk+eddy")])
+@pytest.mark.parametrize("nz,env", [(511, "munk"), (300, "munk+eddy"), (9000, "munk")])
 def test_plain_form_equals_fused_bitwise(ssp, gpu, nz, env):
     # the one-kernel-per-stage form runs the same arithmetic in the same order
     s = W.munk_deep(nsteps=8, nz=nz) if env == "munk" else W.munk_eddy(nsteps=8, nz=nz, neumann_max=24)
