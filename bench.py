@@ -1,11 +1,17 @@
 """Benchmark: field updates (Nz x range steps) per second of the batched spectral
 split-step Pade march on one MI355X.
 
-Workload (deep-ocean Munk waveguide): H = 5000 m, c0 = 1500 m/s, f = 50 Hz, Nz = 4096,
-[6/6] Pade, dr = 25 m, Neumann tol 1e-10 (series capped at 48 terms), TL written every
-4 steps, a batch of B such solves with seeded source depths zs ~ U[50, 2000] m.  A bench
-"step" is one range step of the whole batch (every Pade factor and every Neumann term of
-every solve); inputs are resident in HBM before the timed region.
+Default workload (deep-ocean Munk waveguide): H = 5000 m, c0 = 1500 m/s, f = 50 Hz,
+Nz = 4096, [6/6] Pade, dr = 25 m, Neumann tol 1e-10 (series capped at 48 terms), TL written
+every 4 steps, a batch of B such solves with seeded source depths zs ~ U[50, 2000] m.  A
+bench "step" is one range step of the whole batch (every Pade factor and every Neumann term
+of every solve); inputs are resident in HBM before the timed region.
+
+--workload eddy16384: Munk + Gaussian eddy at 200 Hz, Nz = 16384 (split transforms), [8/8],
+dr = 20 m, Neumann <= 12, potential rebuilt on the device every step, TL every 5 steps.
+--workload broadband: 256 frequencies 50..300 Hz on the Munk profile with uneven
+Nz = 2667..16000, [6/6], dr = 25 m, one plan each, marched together by ssp_march_batch
+(TL every 40 steps copied to the host).
 
 Prints ONE JSON line (contract of the driver).  Beside the metric it reports the roofline of
 the fused march kernel, the plain one-kernel-per-stage form and the fused kernel on a single
@@ -40,68 +46,108 @@ def algorithmic_flops(nz, pade_order, terms, steps, outputs):
     return terms * 2 * (tr + 8 * nz) + steps * pade_order * 16 * nz + outputs * tr
 
 
+def _solve(workload, nz=None, nsteps=None, zs=None, index=None):
+    """The Solve of one job of a workload (index: frequency index of the broadband set)."""
+    if workload == "munk4096":
+        s = W.munk_deep(nz=nz or 4096)
+    elif workload == "eddy16384":
+        s = W.munk_eddy(nz=nz or 16384)
+    else:
+        s = W.broadband()[index]
+    if nsteps is not None:
+        s.nsteps = nsteps
+    if zs is not None:
+        s.zs = zs
+    return s
+
+
 def _oracle_worker(args):
-    nz, nsteps, zs = args
+    workload, nz, nsteps, zs, index = args
     import scipy.fft  # noqa: F401
     from oracle import Plan
-    s = W.munk_deep(nsteps=nsteps, nz=nz, zs=zs)
+    s = _solve(workload, nz, nsteps, zs, index)
     pl = Plan(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol)
     t = time.perf_counter()
     pl.march(s.starter(), nsteps, s.profile(), out_every=s.out_every)
     return s.nz * nsteps, time.perf_counter() - t
 
 
-def cpu_baseline(nz, seconds_target=20.0):
+def cpu_baseline(workload, nz, seconds_target=20.0):
     """The FP64 oracle on the host cores: one solve per process, a bounded number of steps."""
     cores = max(1, min(16, os.cpu_count() or 1))
-    # calibrate: one step of one solve
-    upd, dt = _oracle_worker((nz, 1, 1000.0))
-    steps = max(1, int(seconds_target / max(dt, 1e-3)))
-    zs = W.source_depths(cores, 50.0, 2000.0)
+    if workload == "broadband":
+        # every 16th frequency (uneven Nz), the same bounded step count each
+        jobs = [(workload, None, 1, None, i) for i in range(0, 256, 256 // cores)][:cores]
+        upd, dt = _oracle_worker(jobs[len(jobs) // 2])
+        steps = max(1, int(seconds_target / max(dt, 1e-3)))
+        jobs = [(w, n, steps, z, i) for (w, n, _, z, i) in jobs]
+        what = f"{len(jobs)} of the 256 frequencies (every {256 // cores}th) x {steps} range steps"
+    else:
+        upd, dt = _oracle_worker((workload, nz, 1, 1000.0, None))
+        steps = max(1, int(seconds_target / max(dt, 1e-3)))
+        zs = W.source_depths(cores, 50.0, 2000.0)
+        jobs = [(workload, nz, steps, float(z), None) for z in zs]
+        what = f"{cores} solves x {steps} range steps of the Nz={nz} {workload} workload"
     t = time.perf_counter()
     with mp.get_context("spawn").Pool(cores) as pool:
-        res = pool.map(_oracle_worker, [(nz, steps, float(z)) for z in zs])
+        res = pool.map(_oracle_worker, jobs)
     wall = time.perf_counter() - t
     total = sum(r[0] for r in res)
     return {"value": total / wall, "unit": "field updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{cores} solves x {steps} range steps of the Nz={nz} Munk workload "
-                      f"(FP64, one solve per process, {wall:.1f} s wall)"}
+            "sample": f"{what} (FP64, one solve per process, {wall:.1f} s wall)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400, help="timed range steps")
-    ap.add_argument("--warmup", type=int, default=20, help="untimed range steps")
-    ap.add_argument("--batch", type=int, default=512, help="solves marched together")
-    ap.add_argument("--nz", type=int, default=4096)
-    ap.add_argument("--chunk", type=int, default=100, help="range steps per kernel launch")
-    ap.add_argument("--roof-launches", type=int, default=3)
-    ap.add_argument("--plain-steps", type=int, default=8,
-                    help="range steps of the plain-form comparison (0: skip)")
-    ap.add_argument("--graph", type=int, default=1, help="replay recorded launches (HIP graph)")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); every solve of the batch is "
-              "independent, so several GPUs would each run their own batch", file=sys.stderr)
-        sys.exit(2)
+DEFAULTS = {  # batch, timed steps, warmup steps, steps per launch
+    "munk4096": (512, 400, 20, 100),
+    "eddy16384": (256, 100, 10, 50),
+    "broadband": (256, 200, 40, 200),
+}
+DESCRIPTIONS = {
+    "munk4096": "deep Munk waveguide, Nz=4096, [6/6] Pade, dr=25 m, 50 Hz, Neumann tol 1e-10 "
+                "(cap 48), TL every 4 steps",
+    "eddy16384": "Munk + Gaussian eddy, Nz=16384, [8/8] Pade, dr=20 m, 200 Hz, Neumann tol 1e-10 "
+                 "(cap 12), potential on device every step, TL every 5 steps",
+    "broadband": "256 frequencies 50..300 Hz, Munk, Nz=2667..16000 (16 pts/wavelength), [6/6] Pade, "
+                 "dr=25 m, Neumann tol 1e-10 (cap 48), TL every 40 steps to host",
+}
 
-    import torch
-    from paper_2511_03343_amd import ssp
-    assert torch.cuda.is_available(), "bench needs a GPU"
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.Stream(dev)           # default priority
-    torch.cuda.set_stream(stream)
 
-    s = W.munk_deep(nz=args.nz)
-    B = args.batch
+def make_plan(ssp, s):
     pl = ssp.ssp_plan_create(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol)
-    ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
     ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_OUT_EVERY, s.out_every)
+    if s.env == "munk+eddy":
+        e = s.eddy or W.Eddy()
+        ssp.ssp_set_profile_analytic(pl, eddy=(e.amp, e.r0, e.rr, e.z0, e.rz))
+    else:
+        ssp.ssp_set_profile(pl, 0, -1, s.profile()[0])
+    return pl
+
+
+def plain_vs_fused(ssp, s, nsteps):
+    """The plain one-kernel-per-stage form and the fused kernel, each on one solve."""
+    out = {}
+    for engine, key in ((1, "plain_one_solve"), (0, "fused_one_solve")):
+        p1 = make_plan(ssp, s)
+        ssp.ssp_plan_set_option(p1, ssp.SSP_OPT_ENGINE, engine)
+        ssp.ssp_march(p1, s.nz, s.starter(), 2, want_field=False, want_tl=False)
+        t1 = time.perf_counter()
+        ssp.ssp_march(p1, s.nz, None, nsteps, want_field=False, want_tl=True)
+        dt = time.perf_counter() - t1
+        ssp.ssp_plan_destroy(p1)
+        out[key] = s.nz * nsteps / dt
+    out["unit"] = "field updates/s"
+    out["steps"] = nsteps
+    out["nz"] = s.nz
+    return out
+
+
+def run_device_batch(args, ssp, torch, stream, dev):
+    """One plan, a batch of B solves marched on the device (munk4096, eddy16384)."""
+    s = _solve(args.workload, args.nz)
+    B = args.batch
+    pl = make_plan(ssp, s)
+    ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
     ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_GRAPH, 1 if args.graph else 0)
-    ssp.ssp_set_profile(pl, 0, -1, s.profile()[0])
 
     zs = W.source_depths(B, 50.0, 2000.0)
     psi = np.stack([W.gaussian_starter(s.nz, s.depth, s.freq, s.c0, z) for z in zs])
@@ -130,13 +176,11 @@ def main():
     # warm-up, then the timed region: the whole workload (march + TL outputs)
     run(args.warmup)
     torch.cuda.synchronize()
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     run(args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     updates = B * s.nz * args.steps
-    value = updates / wall
 
     # roofline of the dominant kernel (the fused march): launches without outputs, timed
     # with events on the stream they run on; algorithmic work from the per-solve Neumann
@@ -151,30 +195,112 @@ def main():
     launch_s = [a.elapsed_time(b) / 1e3 for a, b, _ in events]
     achieved = sum(flops) / sum(launch_s)
     stats = _stats(d_stats)
-
-    # the plain one-kernel-per-stage form on one solve, and the fused kernel on one solve
+    ssp.ssp_plan_destroy(pl)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+            "kernel": f"k_march<{_fft_len(s.nz)}>",
+            "avg_launch_ms": 1e3 * sum(launch_s) / len(launch_s),
+            "steps_per_launch": args.chunk,
+            "neumann_terms_per_solve_step": stats["terms"] / B / args.chunk}
+    config = {"batch_solves": B, "nz": s.nz, "range_steps_timed": args.steps,
+              "steps_per_launch": args.chunk, "hip_graph": bool(args.graph)}
     plain = None
     if args.plain_steps > 0:
-        plain = {}
-        for engine, key in ((1, "plain_one_solve"), (0, "fused_one_solve")):
-            p1 = ssp.ssp_plan_create(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order,
-                                     s.neumann_max, s.tol)
-            ssp.ssp_plan_set_option(p1, ssp.SSP_OPT_ENGINE, engine)
-            ssp.ssp_plan_set_option(p1, ssp.SSP_OPT_OUT_EVERY, s.out_every)
-            ssp.ssp_set_profile(p1, 0, -1, s.profile()[0])
-            ssp.ssp_march(p1, s.nz, s.starter(), 2, want_field=False, want_tl=False)
-            t1 = time.perf_counter()
-            ssp.ssp_march(p1, s.nz, None, args.plain_steps, want_field=False, want_tl=True)
-            dt = time.perf_counter() - t1
-            ssp.ssp_plan_destroy(p1)
-            plain[key] = s.nz * args.plain_steps / dt
-        plain["unit"] = "field updates/s"
-        plain["steps"] = args.plain_steps
-        plain["fused_batched_over_plain"] = value / plain["plain_one_solve"]
+        plain = plain_vs_fused(ssp, s, args.plain_steps)
+        plain["fused_batched_over_plain"] = (updates / wall) / plain["plain_one_solve"]
+    return updates, wall, roof, config, sorted(set(stats["status"])), plain, s.nz
+
+
+def run_broadband(args, ssp, torch, stream, dev):
+    """256 plans of uneven Nz marched together through ssp_march_batch (host outputs)."""
+    solves = W.broadband()
+    plans = [make_plan(ssp, s) for s in solves]
+    nzs = [s.nz for s in solves]
+    for pl in plans:
+        ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
+    for pl, s in zip(plans, solves):
+        ssp.ssp_set_field(pl, s.starter(), s.nz)
+
+    def run(nsteps):
+        done = 0
+        terms = [0] * len(plans)
+        statuses = set()
+        while done < nsteps:
+            k = min(args.chunk, nsteps - done)
+            st, _, _, stats = ssp.ssp_march_batch(plans, nzs, k, want_field=False, want_tl=True)
+            for i, x in enumerate(stats):
+                terms[i] += x["neumann_terms"]
+            statuses |= {x["status"] for x in stats}
+            done += k
+        return terms, statuses
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    terms, statuses = run(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    updates = sum(nzs) * args.steps
+    # whole-call roofline: algorithmic work of every solve / wall time (outputs included)
+    flops = sum(algorithmic_flops(s.nz, s.pade_order, t, args.steps, args.steps // s.out_every)
+                for s, t in zip(solves, terms))
+    avg_terms = sum(terms) / len(plans) / args.steps
+    achieved = flops / wall
+    for pl in plans:
+        ssp.ssp_plan_destroy(pl)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+            "kernel": "k_march<8192|16384|32768> (grouped by FFT length) + outputs, whole call",
+            "neumann_terms_per_solve_step": avg_terms}
+    config = {"solves": len(plans), "nz_min": min(nzs), "nz_max": max(nzs), "sum_nz": sum(nzs),
+              "range_steps_timed": args.steps, "steps_per_call": args.chunk}
+    plain = None
+    if args.plain_steps > 0:
+        plain = plain_vs_fused(ssp, solves[-1], args.plain_steps)
+        plain["fused_batched_over_plain"] = (updates / wall) / plain["plain_one_solve"]
+    return updates, wall, roof, config, sorted(statuses), plain, None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(DEFAULTS), default="munk4096")
+    ap.add_argument("--steps", type=int, default=None, help="timed range steps")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed range steps")
+    ap.add_argument("--batch", type=int, default=None, help="solves marched together")
+    ap.add_argument("--nz", type=int, default=None)
+    ap.add_argument("--chunk", type=int, default=None, help="range steps per kernel launch")
+    ap.add_argument("--roof-launches", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=8,
+                    help="range steps of the plain-form comparison (0: skip)")
+    ap.add_argument("--graph", type=int, default=1, help="replay recorded launches (HIP graph)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); every solve of the batch is "
+              "independent, so several GPUs would each run their own batch", file=sys.stderr)
+        sys.exit(2)
+    b, st, wu, ch = DEFAULTS[args.workload]
+    args.batch = args.batch or b
+    args.steps = args.steps if args.steps is not None else st
+    args.warmup = args.warmup if args.warmup is not None else wu
+    args.chunk = args.chunk or ch
+
+    import torch
+    from paper_2511_03343_amd import ssp
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)           # default priority
+    torch.cuda.set_stream(stream)
+
+    runner = run_broadband if args.workload == "broadband" else run_device_batch
+    updates, wall, roof, config, statuses, plain, nz = runner(args, ssp, torch, stream, dev)
+    value = updates / wall
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(s.nz, args.cpu_seconds)
+        cpu = cpu_baseline(args.workload, nz, args.cpu_seconds)
 
     out = {
         "metric": "field updates (Nz x range steps)/s at TL err<=0.1 dB",
@@ -189,22 +315,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded Munk profile and Gaussian starters)",
-        "config": {"workload": "deep Munk waveguide, Nz=4096, [6/6] Pade, dr=25 m, 50 Hz, "
-                               "Neumann tol 1e-10 (cap 48), TL every 4 steps",
-                   "batch_solves": B, "nz": s.nz, "range_steps_timed": args.steps,
-                   "steps_per_launch": args.chunk, "hip_graph": bool(args.graph)},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
-                     "kernel": f"k_march<{_fft_len(s.nz)}>",
-                     "avg_launch_ms": 1e3 * sum(launch_s) / len(launch_s),
-                     "steps_per_launch": args.chunk,
-                     "neumann_terms_per_solve_step": stats["terms"] / B / args.chunk},
-        "status": sorted(set(stats["status"])),
+        "config": {"workload": DESCRIPTIONS[args.workload], **config},
+        "roofline": roof,
+        "status": statuses,
         "plain_form": plain,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    ssp.ssp_plan_destroy(pl)
 
 
 def _stats(d_stats):

@@ -613,10 +613,12 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
         HIP_TRY(dev_alloc(&owner->d_descs, n));
         owner->descs_cap = n;
     }
-    // order by FFT length so each launch gets a contiguous range
+    // order by FFT length, longest first: each length is a contiguous range, the lengths that
+    // share the 1024-thread kernel come first (one launch), and the longest solves are
+    // dispatched first
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return descs[x].P < descs[y].P; });
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return descs[x].P > descs[y].P; });
     std::vector<ssp::SolveDesc> sorted(n);
     for (int i = 0; i < n; ++i) sorted[i] = descs[order[i]];
     HIP_TRY(hipMemcpyAsync(owner->d_descs, sorted.data(), n * sizeof(ssp::SolveDesc),
@@ -637,11 +639,23 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
             HIP_TRY(ssp::plain_march(sorted[0], owner->d_descs, nsteps, pl->d_plain, pl->d_plain_flags, stream));
             if (sorted[0].snap) HIP_TRY(ssp::launch_output(sorted[0].P, owner->d_descs, 1, sorted[0].nout, stream));
         } else {
-        int start = 0;
-        while (start < n) {
+        // marches: one launch for the 1024-thread lengths together, one per other length
+        int fam = 0;
+        while (fam < n && ssp::march_family_member(sorted[fam].P)) ++fam;
+        if (fam > 0 && sorted[0].P != sorted[fam - 1].P)
+            HIP_TRY(ssp::launch_march_family(owner->d_descs, fam, nsteps, stream));
+        else
+            fam = 0;
+        for (int start = fam; start < n;) {
             int end = start;
             while (end < n && sorted[end].P == sorted[start].P) ++end;
             HIP_TRY(ssp::launch_march(sorted[start].P, owner->d_descs + start, end - start, nsteps, stream));
+            start = end;
+        }
+        // outputs: one launch per length
+        for (int start = 0; start < n;) {
+            int end = start;
+            while (end < n && sorted[end].P == sorted[start].P) ++end;
             int rows = 0;
             for (int k = start; k < end; ++k) rows = std::max(rows, sorted[k].snap ? sorted[k].nout : 0);
             HIP_TRY(ssp::launch_output(sorted[start].P, owner->d_descs + start, end - start, rows, stream));

@@ -66,6 +66,11 @@ inline void set_work(SolveDesc &d, float2 *base) {
 hipError_t launch_march(int P, const SolveDesc *d_descs, int nsolves, int nsteps,
                         hipStream_t stream);
 
+// One launch for solves of different FFT lengths, all members of the 1024-thread family
+// (march_family_member): each workgroup runs the code of its own descriptor's P.
+bool march_family_member(int P);
+hipError_t launch_march_family(const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream);
+
 // Convert the snapshots of the preceding march into field / TL rows: one workgroup per
 // (solve, output row); rows beyond a solve's nout are skipped.  Output rows of a launch that
 // starts at step n0 are the steps (n0/out_every + 1) out_every + row out_every; the step at

@@ -304,8 +304,8 @@ __device__ __forceinline__ float2 twmul(float2 x, float2 h, uint32_t l) {
 // uses buffer k mod 2 (buffer 0 only when two do not fit), chosen at compile time.
 struct LdsBufs {
     float2 *b0, *b1;
-    const float2 *th;   // middle-pass twiddle table
-    const uint32_t *tl;
+    float2 *th;   // middle-pass twiddle table
+    uint32_t *tl;
 };
 
 template <int P, int PH>
@@ -482,12 +482,21 @@ __device__ __forceinline__ void dst_core(float2 (&x)[ECfg<P>::RT], const LdsBufs
     }
 }
 
-#define SSP_LDS_DECL(P)                                                        \
-    __shared__ float2 lds_a[Cfg<P>::DLEN];                                     \
-    __shared__ float2 lds_b[Cfg<P>::PINGPONG ? Cfg<P>::DLEN : 1];              \
-    __shared__ float2 lds_th[mid_tab_len<P>() + 1];                            \
-    __shared__ uint32_t lds_tl[mid_tab_len<P>() + 1];                          \
-    const LdsBufs L{lds_a, lds_b, lds_th, lds_tl}
+// LDS of one workgroup for engine length PE, carved from one array: the data buffer(s),
+// then the middle-pass twiddle table (FP32 values, then the bf16 remainders).
+template <int PE>
+constexpr int lds_words() {  // in float2 units
+    return (Cfg<PE>::PINGPONG ? 2 : 1) * Cfg<PE>::DLEN + (mid_tab_len<PE>() + 1) + (mid_tab_len<PE>() + 2) / 2;
+}
+template <int PE>
+__device__ __forceinline__ LdsBufs carve_lds(float2 *raw) {
+    float2 *th = raw + (Cfg<PE>::PINGPONG ? 2 : 1) * Cfg<PE>::DLEN;
+    return LdsBufs{raw, Cfg<PE>::PINGPONG ? raw + Cfg<PE>::DLEN : raw, th,
+                   reinterpret_cast<uint32_t *>(th + mid_tab_len<PE>() + 1)};
+}
+#define SSP_LDS_DECL(PE)                          \
+    __shared__ float2 lds_raw[lds_words<PE>()];   \
+    const LdsBufs L = carve_lds<PE>(lds_raw)
 
 // Sum two doubles over the workgroup in a fixed order (wave butterfly, then waves in
 // index order); every thread returns the same values.
@@ -593,9 +602,9 @@ __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, 
 }
 
 // ----------------------------------------------------------------------------- march
-// One workgroup marches one solve (descriptor blockIdx.x) through nsteps range steps.
+// One workgroup marches one solve through nsteps range steps.
 template <int P>
-__global__ __launch_bounds__(ECfg<P>::T) void k_march(const SolveDesc *__restrict__ descs, int nsteps) {
+__device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float2 *lds_raw, double *red) {
     constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
     // the Neumann multiplier stays in registers for up to 8 elements per thread
     constexpr bool kBInRegs = (RT <= 8) && (T < 1024);
@@ -603,18 +612,17 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_march(const SolveDesc *__restric
     // ... and so does the potential A = v (.) dmod; otherwise both come from L2
     constexpr bool kAInRegs = kBInRegs;
     constexpr int EA = kAInRegs ? RT : 1;
-    // the series sum w_j stays in registers below 1024 threads (else in d.wacc)
-    constexpr bool kWInRegs = T < 1024;
+    // the series sum w_j stays in registers up to 8 elements per thread or below 1024
+    // threads (else in d.wacc)
+    constexpr bool kWInRegs = T < 1024 || RT <= 8;
     constexpr int EW = kWInRegs ? RT : 1;
     // split transforms keep their second input in the solve's scratch (fewer spills)
     constexpr bool kKeepGlobal = true;
-    SSP_LDS_DECL(eng_len<P>());
-    __shared__ double red[2 * (T / 64)];
-    const SolveDesc &d = descs[blockIdx.x];
+    const LdsBufs L = carve_lds<eng_len<P>()>(lds_raw);
     const int tid = threadIdx.x;
     const int N = d.N, p = d.p, nmax = d.nmax;
     Twiddles<eng_len<P>()> tw;
-    init_twiddles<eng_len<P>()>(tw, lds_th, lds_tl, d.tw);
+    init_twiddles<eng_len<P>()>(tw, L.th, L.tl, d.tw);
 
     // The state u is not held in registers: d.field holds the state at the start of the
     // step (the recovery point if the step diverges) and d.work the state between Pade
@@ -773,6 +781,32 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_march(const SolveDesc *__restric
     }
 }
 
+// One solve per workgroup (descriptor blockIdx.x), all with convolution length P.
+template <int P>
+__global__ __launch_bounds__(ECfg<P>::T) void k_march(const SolveDesc *__restrict__ descs, int nsteps) {
+    __shared__ float2 lds_raw[lds_words<eng_len<P>()>()];
+    __shared__ double red[2 * (ECfg<P>::T / 64)];
+    march_body<P>(descs[blockIdx.x], nsteps, lds_raw, red);
+}
+
+// Solves of uneven length in one launch: every length that runs with 1024-thread workgroups
+// (P = 8192, 16384, 32768); each workgroup takes the code path of its own descriptor's P.
+constexpr int kFamilyT = 1024;
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kFamilyLds = cmax(lds_words<8192>(), lds_words<16384>());
+static_assert(Cfg<8192>::T == kFamilyT && Cfg<16384>::T == kFamilyT, "family thread count");
+__global__ __launch_bounds__(kFamilyT) void k_march_family(const SolveDesc *__restrict__ descs, int nsteps) {
+    __shared__ float2 lds_raw[kFamilyLds];
+    __shared__ double red[2 * (kFamilyT / 64)];
+    const SolveDesc &d = descs[blockIdx.x];
+    switch (d.P) {  // uniform over the workgroup
+        case 8192: march_body<8192>(d, nsteps, lds_raw, red); break;
+        case 16384: march_body<16384>(d, nsteps, lds_raw, red); break;
+        case 32768: march_body<32768>(d, nsteps, lds_raw, red); break;
+        default: break;
+    }
+}
+
 // ----------------------------------------------------------------------------- transforms
 template <int P>
 __global__ __launch_bounds__(ECfg<P>::T) void k_transform(const SolveDesc *__restrict__ desc, int mode,
@@ -783,7 +817,7 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_transform(const SolveDesc *__res
     const SolveDesc &d = *desc;
     const int N = d.N, tid = threadIdx.x;
     Twiddles<eng_len<P>()> tw;
-    init_twiddles<eng_len<P>()>(tw, lds_th, lds_tl, d.tw);
+    init_twiddles<eng_len<P>()>(tw, L.th, L.tl, d.tw);
     const float2 *vin = in + static_cast<size_t>(blockIdx.x) * N;
     float2 *vout = out + static_cast<size_t>(blockIdx.x) * N;
     float2 x[RT];
@@ -823,7 +857,7 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_output(const SolveDesc *__restri
     if (row >= d.nout || !d.snap || !d.stats || d.out_every <= 0) return;  // uniform
     const int N = d.N, tid = threadIdx.x;
     Twiddles<eng_len<P>()> tw;
-    init_twiddles<eng_len<P>()>(tw, lds_th, lds_tl, d.tw);
+    init_twiddles<eng_len<P>()>(tw, L.th, L.tl, d.tw);
     // the march that wrote the snapshots started at step step_index - steps_done
     const long long n0 = d.stats->step_index - d.stats->steps_done;
     const long long n = (n0 / d.out_every + 1) * d.out_every + static_cast<long long>(row) * d.out_every;
@@ -901,7 +935,7 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_plain_half(const SolveDesc *__re
     const SolveDesc &d = *desc;
     if (ps->halt || ps->done) return;  // uniform: the series has stopped
     Twiddles<eng_len<P>()> tw;
-    init_twiddles<eng_len<P>()>(tw, lds_th, lds_tl, d.tw);
+    init_twiddles<eng_len<P>()>(tw, L.th, L.tl, d.tw);
     const int N = d.N;
     float2 x[RT];
 #pragma unroll
@@ -1059,6 +1093,14 @@ hipError_t launch_transform_P(int mode, const SolveDesc *d_desc, int B, const fl
 }
 
 }  // namespace
+
+bool march_family_member(int P) { return P == 8192 || P == 16384 || P == 32768; }
+
+hipError_t launch_march_family(const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
+    if (nsolves <= 0 || nsteps <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_march_family, dim3(nsolves), dim3(kFamilyT), 0, stream, d_descs, nsteps);
+    return hipGetLastError();
+}
 
 bool fft_length_supported(int P) {
     return P == 128 || P == 256 || P == 512 || P == 1024 || P == 2048 || P == 4096 || P == 8192 ||

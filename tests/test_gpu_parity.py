@@ -276,6 +276,35 @@ def test_batch_equals_alone_bitwise(ssp, gpu):
         assert np.array_equal(a, b)
 
 
+def test_uneven_lengths_one_launch_equal_alone_bitwise(ssp, gpu):
+    # FFT lengths 8192, 16384 and 32768 (broadband frequencies) share one launch; each solve
+    # must give exactly what it gives alone
+    solves = []
+    for nz, f in [(3000, 56.25), (6000, 112.5), (12000, 225.0), (16000, 300.0)]:
+        s = W.munk_deep(nsteps=6, nz=nz)
+        s.freq = f
+        s.out_every = 3
+        solves.append(s)
+    alone = []
+    for s in solves:
+        pl = make_plan(ssp, s)
+        try:
+            alone.append(ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps))
+        finally:
+            ssp.ssp_plan_destroy(pl)
+    plans = [make_plan(ssp, s) for s in solves]
+    try:
+        for pl, s in zip(plans, solves):
+            ssp.ssp_set_field(pl, s.starter(), s.nz)
+        st, fl, tl, stats = ssp.ssp_march_batch(plans, [s.nz for s in solves], 6)
+    finally:
+        for pl in plans:
+            ssp.ssp_plan_destroy(pl)
+    for (st1, f1, t1, s1), f2, t2, s2 in zip(alone, fl, tl, stats):
+        assert s1 == s2
+        assert np.array_equal(f1, f2) and np.array_equal(t1, t2)
+
+
 def test_device_batch_matches_host_march(ssp, gpu):
     torch = gpu
     B = 5
