@@ -261,6 +261,56 @@ def run_broadband(args, ssp, torch, stream, dev):
     return updates, wall, roof, config, sorted(statuses), plain, None
 
 
+PEAK_FP16_MFMA = 2.5e15   # MI355X dense fp16/bf16 matrix peak (FLOP/s)
+
+
+def transform_rooflines(ssp, torch, stream, dev, reps=20):
+    """Stand-alone batched transforms, each timed with events on its stream:
+    the chirp-z DST (FFT path, HBM-bound: 16 B per point read + written) at Nz = 4096 and
+    the dense DST on the matrix cores at Nz = 2048 (three fp16 products of 2 Nz^2 flops per
+    real column)."""
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    nz, B = 4096, 4096
+    pl = ssp.ssp_plan_create(nz, 5000.0, 50.0, 1500.0, 25.0, 6, 48, 1e-10)
+    ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
+    x = torch.randn((B, nz), dtype=torch.complex64, device=dev)
+    y = torch.empty_like(x)
+    t = timed(lambda: ssp.ssp_dst_device(pl, B, x.data_ptr(), y.data_ptr()))
+    ssp.ssp_plan_destroy(pl)
+    gbs = 16.0 * nz * B / t
+    out["dst_fft"] = {"kernel": f"k_transform<{_fft_len(nz)}>", "nz": nz, "vectors": B,
+                      "bound": "hbm", "achieved": gbs / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                      "frac": gbs / PEAK_HBM, "ms_per_call": 1e3 * t}
+    nz, B = 2048, 1024
+    pl = ssp.ssp_plan_create(nz, 5000.0, 50.0, 1500.0, 25.0, 6, 48, 1e-10)
+    ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
+    x = torch.randn((B, nz), dtype=torch.complex64, device=dev)
+    y = torch.empty_like(x)
+    t = timed(lambda: ssp.ssp_dst_dense_device(pl, B, x.data_ptr(), y.data_ptr()))
+    ssp.ssp_plan_destroy(pl)
+    alg = 2.0 * nz * nz * 2 * B
+    out["dst_dense"] = {"kernel": "k_dense_split + k_dense_gemm", "nz": nz, "vectors": B,
+                        "bound": "mfma", "achieved": 3 * alg / t / 1e12,
+                        "peak": PEAK_FP16_MFMA / 1e12, "unit": "TFLOP/s",
+                        "frac": 3 * alg / t / PEAK_FP16_MFMA,
+                        "algorithmic_tflops": alg / t / 1e12, "ms_per_call": 1e3 * t,
+                        "dtype": "fp16x3 (FP32 accumulate)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +325,8 @@ def main():
                     help="range steps of the plain-form comparison (0: skip)")
     ap.add_argument("--graph", type=int, default=1, help="replay recorded launches (HIP graph)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-transforms", action="store_true",
+                    help="skip the stand-alone transform measurements")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -298,6 +350,8 @@ def main():
     updates, wall, roof, config, statuses, plain, nz = runner(args, ssp, torch, stream, dev)
     value = updates / wall
 
+    transforms = None if args.no_transforms else transform_rooflines(ssp, torch, stream, dev)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.workload, nz, args.cpu_seconds)
@@ -319,6 +373,7 @@ def main():
         "roofline": roof,
         "status": statuses,
         "plain_form": plain,
+        "transforms": transforms,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -176,6 +176,17 @@ ssp_status ssp_from_sine(ssp_plan *plan, int B, const void *d_sine, const void *
  * device in/out (may alias), asynchronous on the plan's stream. */
 ssp_status ssp_dst_device(ssp_plan *plan, int B, const void *d_in, void *d_out);
 
+/* The same transform as a dense matrix product Y = S X on the matrix cores (Sec. 3.1: S is
+ * the orthonormal DST-I matrix, symmetric and its own inverse).  Each complex vector is two
+ * real columns of X; the product runs in fp16 MFMA with FP32 accumulation, every operand
+ * split into high and low fp16 parts (three partial products) after exact power-of-two
+ * scaling of S and of each column, so the relative error is about 2^-22 (a few 1e-7).
+ * Device in/out [B][Nz] complex64 (may alias); asynchronous on the plan's stream.  The
+ * plan builds S (2 x 2 bytes per entry, Nz rounded up to 128) and scratch for the split
+ * operands on first use.  Nz > ssp_max_dense_nz() -> SSP_E_UNIMPL. */
+ssp_status ssp_dst_dense_device(ssp_plan *plan, int B, const void *d_in, void *d_out);
+int ssp_max_dense_nz(void);
+
 const char *ssp_status_string(ssp_status s);
 const char *ssp_last_error(void); /* thread-local detail of the last error */
 

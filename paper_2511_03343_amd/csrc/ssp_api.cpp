@@ -13,6 +13,7 @@
 
 #include "ssp_device.h"
 #include "ssp_plan.h"
+#include "ssp_dense.h"
 
 namespace {
 
@@ -100,6 +101,12 @@ struct ssp_plan {
     float2 *d_out_fld = nullptr;
     float *d_out_tl = nullptr;
     size_t out_cap = 0;
+    // dense DST (matrix cores): S parts and split-operand scratch
+    _Float16 *d_dense_sh = nullptr, *d_dense_sl = nullptr;
+    int dense_kpad = 0;
+    _Float16 *d_dense_xh = nullptr, *d_dense_xl = nullptr;
+    int *d_dense_expo = nullptr;
+    int dense_cols_cap = 0;
     // plain-form work buffers
     float2 *d_plain = nullptr;
     void *d_plain_flags = nullptr;      // plain-form series state
@@ -381,6 +388,11 @@ void ssp_plan_destroy(ssp_plan *pl) {
     dev_free(pl->d_out_fld);
     dev_free(pl->d_out_tl);
     dev_free(pl->d_plain);
+    dev_free(pl->d_dense_sh);
+    dev_free(pl->d_dense_sl);
+    dev_free(pl->d_dense_xh);
+    dev_free(pl->d_dense_xl);
+    dev_free(pl->d_dense_expo);
     if (pl->d_plain_flags) (void)hipFree(pl->d_plain_flags);
     delete pl;
 }
@@ -800,6 +812,42 @@ ssp_status ssp_dst_device(ssp_plan *pl, int B, const void *d_in, void *d_out) {
     HIP_TRY(hipMemcpyAsync(pl->d_desc, &d, sizeof(d), hipMemcpyHostToDevice, pl->stream));
     HIP_TRY(ssp::launch_transform(pl->P, 0, pl->d_desc, B, static_cast<const float2 *>(d_in),
                                   static_cast<float2 *>(d_out), nullptr, pl->stream));
+    return SSP_OK;
+}
+
+int ssp_max_dense_nz(void) { return ssp::kMaxDenseNz; }
+
+ssp_status ssp_dst_dense_device(ssp_plan *pl, int B, const void *d_in, void *d_out) {
+    if (!pl || B <= 0 || !d_in || !d_out) return fail(SSP_E_INVAL, "bad argument");
+    if (pl->N > ssp::kMaxDenseNz) return fail(SSP_E_UNIMPL, "Nz above ssp_max_dense_nz()");
+    if (B > (1 << 20)) return fail(SSP_E_INVAL, "B too large");
+    if (!pl->d_dense_sh) {
+        std::vector<uint16_t> sh, sl;
+        int kpad = 0;
+        ssp::build_dense_tables(pl->N, kpad, sh, sl);
+        HIP_TRY(dev_alloc(&pl->d_dense_sh, sh.size()));
+        HIP_TRY(dev_alloc(&pl->d_dense_sl, sl.size()));
+        HIP_TRY(hipMemcpy(pl->d_dense_sh, sh.data(), sh.size() * 2, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(pl->d_dense_sl, sl.data(), sl.size() * 2, hipMemcpyHostToDevice));
+        pl->dense_kpad = kpad;
+    }
+    if (pl->dense_cols_cap < 2 * B) {
+        dev_free(pl->d_dense_xh);
+        dev_free(pl->d_dense_xl);
+        dev_free(pl->d_dense_expo);
+        pl->dense_cols_cap = 0;
+        HIP_TRY(dev_alloc(&pl->d_dense_xh, static_cast<size_t>(2 * B) * pl->dense_kpad));
+        HIP_TRY(dev_alloc(&pl->d_dense_xl, static_cast<size_t>(2 * B) * pl->dense_kpad));
+        HIP_TRY(dev_alloc(&pl->d_dense_expo, static_cast<size_t>(2 * B)));
+        pl->dense_cols_cap = 2 * B;
+    }
+    ssp::DenseTables t;
+    t.sh = pl->d_dense_sh;
+    t.sl = pl->d_dense_sl;
+    t.n = pl->N;
+    t.kpad = pl->dense_kpad;
+    HIP_TRY(ssp::launch_dense_dst(t, B, static_cast<const float2 *>(d_in), static_cast<float2 *>(d_out),
+                                  pl->d_dense_xh, pl->d_dense_xl, pl->d_dense_expo, pl->stream));
     return SSP_OK;
 }
 

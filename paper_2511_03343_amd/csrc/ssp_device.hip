@@ -815,7 +815,7 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_transform(const SolveDesc *__res
     constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
     SSP_LDS_DECL(eng_len<P>());
     const SolveDesc &d = *desc;
-    const int N = d.N, tid = threadIdx.x;
+    const int N = d.N;
     Twiddles<eng_len<P>()> tw;
     init_twiddles<eng_len<P>()>(tw, L.th, L.tl, d.tw);
     const float2 *vin = in + static_cast<size_t>(blockIdx.x) * N;

@@ -6,6 +6,7 @@
 // it runs in x87 extended precision (64-bit mantissa); the roots are found with the
 // Aberth-Ehrlich simultaneous iteration and polished by Newton steps.
 #include "ssp_plan.h"
+#include "ssp_dense.h"
 
 #include <algorithm>
 #include <cmath>
@@ -367,6 +368,33 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, DeviceTabl
         split_df(al.imag(), t.alpha[4 * j + 1], t.alpha[4 * j + 3]);
         split_df(be.real(), t.beta[4 * j], t.beta[4 * j + 2]);
         split_df(be.imag(), t.beta[4 * j + 1], t.beta[4 * j + 3]);
+    }
+}
+
+}  // namespace ssp
+
+// ------------------------------------------------------------------------------ dense DST
+namespace ssp {
+
+void build_dense_tables(int n, int &kpad, std::vector<uint16_t> &sh, std::vector<uint16_t> &sl) {
+    kpad = (n + 127) / 128 * 128;
+    sh.assign(static_cast<size_t>(kpad) * kpad, 0);
+    sl.assign(static_cast<size_t>(kpad) * kpad, 0);
+    const long long M = n + 1;
+    const long double amp = std::sqrt(2.0L / M) * 4096.0L;  // S scaled by 2^12
+    for (int k = 1; k <= n; ++k) {
+        for (int j = 1; j <= n; ++j) {
+            // sin(pi k j / M) with the argument reduced exactly: k j mod 2M
+            const long long r = (static_cast<long long>(k) * j) % (2 * M);
+            const double v = static_cast<double>(amp * std::sin(kPi * static_cast<long double>(r) / M));
+            const _Float16 h = static_cast<_Float16>(v);
+            const _Float16 l = static_cast<_Float16>(v - static_cast<double>(h));
+            uint16_t hb, lb;
+            std::memcpy(&hb, &h, 2);
+            std::memcpy(&lb, &l, 2);
+            sh[static_cast<size_t>(k - 1) * kpad + (j - 1)] = hb;
+            sl[static_cast<size_t>(k - 1) * kpad + (j - 1)] = lb;
+        }
     }
 }
 

@@ -95,6 +95,8 @@ def lib() -> C.CDLL:
             "ssp_to_sine": (S, [_VP, C.c_int, _VP, _VP]),
             "ssp_from_sine": (S, [_VP, C.c_int, _VP, _VP, _VP]),
             "ssp_dst_device": (S, [_VP, C.c_int, _VP, _VP]),
+            "ssp_dst_dense_device": (S, [_VP, C.c_int, _VP, _VP]),
+            "ssp_max_dense_nz": (C.c_int, []),
             "ssp_status_string": (C.c_char_p, [C.c_int]),
             "ssp_last_error": (C.c_char_p, []),
         }
@@ -246,6 +248,14 @@ def ssp_from_sine(plan, B, d_sine, d_step, d_phys):
 
 def ssp_dst_device(plan, B, d_in, d_out):
     return _check(lib().ssp_dst_device(plan, int(B), d_in, d_out))
+
+
+def ssp_dst_dense_device(plan, B, d_in, d_out):
+    return _check(lib().ssp_dst_dense_device(plan, int(B), d_in, d_out))
+
+
+def ssp_max_dense_nz():
+    return lib().ssp_max_dense_nz()
 
 
 def ssp_status_string(s):

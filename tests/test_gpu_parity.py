@@ -82,6 +82,52 @@ def test_dst_parity(ssp, gpu, nz):
     assert err.max() < 2e-6
 
 
+# dense product on the matrix cores: fp16 high/low parts of S and of each scaled column
+# (three partial products, FP32 accumulation) leave ~2^-22 of the result plus the FP32
+# accumulation over Nz terms; the bar is the one of the FFT transform
+@pytest.mark.parametrize("nz,B", [(2, 1), (3, 5), (100, 3), (127, 64), (128, 2), (129, 65), (1000, 7),
+                                  (2047, 3), (2048, 100)])
+def test_dense_dst_parity(ssp, gpu, nz, B):
+    torch = gpu
+    pl = ssp.ssp_plan_create(nz, 1000.0, 50.0, 1500.0, 10.0, 2, 0, 1e-10)
+    try:
+        x = np.stack([W.random_field(nz, 300 + b) for b in range(B)])
+        # columns of very different magnitude, and a zero vector
+        x[0] *= 1e-30
+        if B > 2:
+            x[1] *= 1e30
+            x[2] = 0.0
+        d_in = torch.from_numpy(x.astype(np.complex64)).cuda()
+        d_out = torch.empty_like(d_in)
+        ssp.ssp_dst_dense_device(pl, B, d_in.data_ptr(), d_out.data_ptr())
+        ssp.ssp_dst_dense_device(pl, B, d_in.data_ptr(), d_in.data_ptr())  # in place
+        torch.cuda.synchronize()
+        got = d_out.cpu().numpy().astype(np.complex128)
+        got_inplace = d_in.cpu().numpy().astype(np.complex128)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    x32 = x.astype(np.complex64).astype(np.complex128)
+    ref = np.stack([odst(v) for v in x32])
+    nrm = np.linalg.norm(ref, axis=1)
+    live = nrm > 0
+    err = np.linalg.norm(got - ref, axis=1)[live] / nrm[live]
+    _report("dense dst", nz=nz, B=B, relL2=f"{err.max():.2e}")
+    assert err.max() < 2e-6
+    assert np.all(got[~live] == 0)
+    assert np.array_equal(got, got_inplace)
+
+
+def test_dense_dst_rejects_large_grid(ssp, gpu):
+    nz = ssp.ssp_max_dense_nz() + 1
+    pl = ssp.ssp_plan_create(nz, 1000.0, 50.0, 1500.0, 10.0, 2, 0, 1e-10)
+    try:
+        with pytest.raises(ssp.SspError) as e:
+            ssp.ssp_dst_dense_device(pl, 1, 1, 1)
+        assert e.value.status == ssp.SSP_E_UNIMPL
+    finally:
+        ssp.ssp_plan_destroy(pl)
+
+
 def test_sine_roundtrip_and_carrier(ssp, gpu):
     torch = gpu
     s = W.munk_deep(nz=1000)
