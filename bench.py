@@ -52,6 +52,8 @@ def _solve(workload, nz=None, nsteps=None, zs=None, index=None):
         s = W.munk_deep(nz=nz or 4096)
     elif workload == "eddy16384":
         s = W.munk_eddy(nz=nz or 16384)
+    elif workload == "serving":
+        s = W.serving_requests(duration=0.2)[index].solve
     else:
         s = W.broadband()[index]
     if nsteps is not None:
@@ -75,7 +77,14 @@ def _oracle_worker(args):
 def cpu_baseline(workload, nz, seconds_target=20.0):
     """The FP64 oracle on the host cores: one solve per process, a bounded number of steps."""
     cores = max(1, min(16, os.cpu_count() or 1))
-    if workload == "broadband":
+    if workload == "serving":
+        reqs = W.serving_requests(duration=0.2)[:cores]
+        jobs = [("serving", None, None, None, i) for i in range(len(reqs))]
+        upd, dt = _oracle_worker(("serving", None, 1, None, 0))
+        steps = max(1, int(seconds_target / max(dt, 1e-3)))
+        jobs = [(w, n, steps, z, i) for (w, n, _, z, i) in jobs]
+        what = f"the first {len(jobs)} requests of the stream x {steps} range steps each"
+    elif workload == "broadband":
         # every 16th frequency (uneven Nz), the same bounded step count each
         jobs = [(workload, None, 1, None, i) for i in range(0, 256, 256 // cores)][:cores]
         upd, dt = _oracle_worker(jobs[len(jobs) // 2])
@@ -101,6 +110,7 @@ DEFAULTS = {  # batch, timed steps, warmup steps, steps per launch
     "munk4096": (512, 400, 20, 100),
     "eddy16384": (256, 100, 10, 50),
     "broadband": (256, 200, 40, 200),
+    "serving": (1024, 0, 0, 50),
 }
 DESCRIPTIONS = {
     "munk4096": "deep Munk waveguide, Nz=4096, [6/6] Pade, dr=25 m, 50 Hz, Neumann tol 1e-10 "
@@ -109,6 +119,9 @@ DESCRIPTIONS = {
                  "(cap 12), potential on device every step, TL every 5 steps",
     "broadband": "256 frequencies 50..300 Hz, Munk, Nz=2667..16000 (16 pts/wavelength), [6/6] Pade, "
                  "dr=25 m, Neumann tol 1e-10 (cap 48), TL every 40 steps to host",
+    "serving": "Poisson request stream: f ~ U[25, 400] Hz, Nz a power of two 512..16384 (>= 4 pts/"
+               "wavelength), range U[10, 100] km, Munk or Munk + eddy, [6/6], dr = max(25 m, 5/k0), "
+               "continuous batching, TL rows to host every tick",
 }
 
 
@@ -311,6 +324,40 @@ def transform_rooflines(ssp, torch, stream, dev, reps=20):
     return out
 
 
+def run_serving(args, ssp, torch, stream, dev):
+    """Poisson request stream through the continuous-batching server (the whole stream, plan
+    creation included, is the timed region)."""
+    from paper_2511_03343_amd.serve import LibBackend, Server, from_solve, latency_summary
+    stream_reqs = W.serving_requests(rate=args.rate, duration=args.duration)
+    reqs = []
+    for i, q in enumerate(stream_reqs):
+        s = q.solve
+        c = W.munk(W.depth_grid(s.nz, s.depth)) if s.env == "munk" else None
+        reqs.append(from_solve(q.arrival, s, c_table=c, rid=i))
+    srv = Server(LibBackend(stream.cuda_stream), max_active=args.batch, steps_per_tick=args.chunk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    updates = sum(r.nz * res[r.rid].steps_done for r in reqs)
+    flops = sum(algorithmic_flops(r.nz, r.pade_order, res[r.rid].neumann_terms, res[r.rid].steps_done,
+                                  res[r.rid].steps_done // r.out_every) for r in reqs)
+    nzs = [r.nz for r in reqs]
+    roof = {"bound": "alu", "achieved": flops / wall / 1e12, "peak": PEAK_FP32 / 1e12,
+            "unit": "TFLOP/s", "frac": flops / wall / PEAK_FP32, "traffic": None,
+            "kernel": "k_march family + per-length launches, whole stream",
+            "neumann_terms_per_solve_step": sum(res[r.rid].neumann_terms for r in reqs) /
+                                            max(1, sum(res[r.rid].steps_done for r in reqs))}
+    config = {"requests": len(reqs), "arrival_rate_per_s": args.rate, "arrival_window_s": args.duration,
+              "nz_min": min(nzs), "nz_max": max(nzs), "steps_per_tick": args.chunk,
+              "max_active": args.batch, "ticks": srv.ticks, "peak_active": srv.peak_active,
+              "host_plan_creation_s": srv.t_create, "march_calls_s": srv.t_march,
+              "latency": latency_summary(res)}
+    statuses = sorted({res[r.rid].status for r in reqs})
+    return updates, wall, roof, config, statuses, None, None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,6 +371,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=8,
                     help="range steps of the plain-form comparison (0: skip)")
     ap.add_argument("--graph", type=int, default=1, help="replay recorded launches (HIP graph)")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
+    ap.add_argument("--duration", type=float, default=2.0, help="serving: arrival window (s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-transforms", action="store_true",
                     help="skip the stand-alone transform measurements")
@@ -346,9 +395,10 @@ def main():
     stream = torch.cuda.Stream(dev)           # default priority
     torch.cuda.set_stream(stream)
 
-    runner = run_broadband if args.workload == "broadband" else run_device_batch
+    runner = {"broadband": run_broadband, "serving": run_serving}.get(args.workload, run_device_batch)
     updates, wall, roof, config, statuses, plain, nz = runner(args, ssp, torch, stream, dev)
     value = updates / wall
+    timed_steps = args.steps or config.get("ticks") or 1   # serving: a step is one tick
 
     transforms = None if args.no_transforms else transform_rooflines(ssp, torch, stream, dev)
 
@@ -361,9 +411,9 @@ def main():
         "value": value,
         "unit": "field updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": timed_steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step": 1e3 * wall / timed_steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -155,6 +155,12 @@ int ssp_count_outputs(const ssp_plan *plan, int nsteps);
 ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *const *field_out,
                            float *const *tl_out, ssp_stats *stats);
 
+/* ssp_march_batch with its own step count per plan (nsteps [n], each >= 0; a plan with 0
+ * steps is left unchanged): the batch of a continuous-batching server, whose requests end
+ * at different ranges.  Outputs, stats and the returned status as in ssp_march_batch. */
+ssp_status ssp_march_batch_steps(ssp_plan *const *plans, int n, const int *nsteps,
+                                 double *const *field_out, float *const *tl_out, ssp_stats *stats);
+
 /* Device-resident batch for serving and benchmarking (no host copies in the hot path):
  * B solves of one plan's grid and coefficients, each with its own state.  d_psi is a device
  * array [B][Nz] complex64 holding each solve's field in the library's sine-basis

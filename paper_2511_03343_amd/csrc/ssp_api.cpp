@@ -107,6 +107,9 @@ struct ssp_plan {
     _Float16 *d_dense_xh = nullptr, *d_dense_xl = nullptr;
     int *d_dense_expo = nullptr;
     int dense_cols_cap = 0;
+    // side streams of a batch whose launch groups run concurrently (default priority)
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     // plain-form work buffers
     float2 *d_plain = nullptr;
     void *d_plain_flags = nullptr;      // plain-form series state
@@ -119,6 +122,30 @@ void drop_graph(ssp_plan *pl) {
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
     pl->graph_exec = nullptr;
     pl->graph = nullptr;
+}
+
+constexpr int kSideStreams = 3;
+
+hipError_t ensure_side_streams(ssp_plan *pl) {
+    if (pl->fork) return hipSuccess;
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < kSideStreams && e == hipSuccess; ++j) {
+        e = hipStreamCreateWithFlags(&pl->side[j], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->join[j], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming);
+    return e;
+}
+
+void free_side_streams(ssp_plan *pl) {
+    for (int j = 0; j < kSideStreams; ++j) {
+        if (pl->side[j]) (void)hipStreamDestroy(pl->side[j]);
+        if (pl->join[j]) (void)hipEventDestroy(pl->join[j]);
+        pl->side[j] = nullptr;
+        pl->join[j] = nullptr;
+    }
+    if (pl->fork) (void)hipEventDestroy(pl->fork);
+    pl->fork = nullptr;
 }
 
 void free_tables(ssp_plan *pl) {
@@ -374,6 +401,7 @@ void ssp_plan_destroy(ssp_plan *pl) {
     if (pl->stream) (void)hipStreamSynchronize(pl->stream);
     else (void)hipDeviceSynchronize();
     drop_graph(pl);
+    free_side_streams(pl);
     free_tables(pl);
     dev_free(pl->d_v);
     dev_free(pl->d_field);
@@ -584,16 +612,23 @@ ssp_status ssp_march(ssp_plan *pl, const double *psi0, int nsteps, double *field
     return ssp_march_batch(plans, 1, nsteps, fo, to, stats);
 }
 
-ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *const *field_out,
-                           float *const *tl_out, ssp_stats *stats) {
+}  // extern "C"
+
+namespace {
+
+// Shared body of ssp_march_batch and ssp_march_batch_steps: plan i marches steps[i] steps.
+ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, double *const *field_out,
+                            float *const *tl_out, ssp_stats *stats) {
     if (!plans || n <= 0) return fail(SSP_E_INVAL, "no plans");
-    if (nsteps < 0) return fail(SSP_E_INVAL, "nsteps must be >= 0");
+    int nsteps = 0;  // the largest step count
     for (int i = 0; i < n; ++i) {
+        if (steps[i] < 0) return fail(SSP_E_INVAL, "nsteps must be >= 0");
+        nsteps = std::max(nsteps, steps[i]);
         if (!plans[i]) return fail(SSP_E_INVAL, "NULL plan in batch");
         if (!plans[i]->has_field) return fail(SSP_E_STATE, "plan without a field in batch");
         for (int k = 0; k < i; ++k)
             if (plans[k] == plans[i]) return fail(SSP_E_INVAL, "plan repeated in batch");
-        ssp_status st = check_profile_range(plans[i], plans[i]->step_index, nsteps);
+        ssp_status st = check_profile_range(plans[i], plans[i]->step_index, steps[i]);
         if (st != SSP_OK) return st;
     }
     hipStream_t stream = plans[0]->stream;
@@ -602,7 +637,7 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
     std::vector<ssp::SolveDesc> descs(n);
     for (int i = 0; i < n; ++i) {
         ssp_plan *pl = plans[i];
-        nout[i] = count_outputs(pl->step_index, nsteps, pl->out_every);
+        nout[i] = count_outputs(pl->step_index, steps[i], pl->out_every);
         ssp_status st = ensure_out(pl, static_cast<size_t>(nout[i]) * pl->N);
         if (st != SSP_OK) return st;
         ssp::SolveDesc d = base_desc(pl);
@@ -610,6 +645,7 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
         ssp::set_work(d, pl->d_work);
         d.step = pl->d_step;
         d.nout = nout[i];
+        d.nsteps = steps[i];
         d.stats = pl->d_stats;
         // snapshots go to the field staging rows and are converted there in place
         d.fld_out = (field_out && field_out[i] && nout[i] > 0) ? pl->d_out_fld : nullptr;
@@ -630,7 +666,9 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
     // dispatched first
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return descs[x].P > descs[y].P; });
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return descs[x].P != descs[y].P ? descs[x].P > descs[y].P : descs[x].nsteps > descs[y].nsteps;
+    });
     std::vector<ssp::SolveDesc> sorted(n);
     for (int i = 0; i < n; ++i) sorted[i] = descs[order[i]];
     HIP_TRY(hipMemcpyAsync(owner->d_descs, sorted.data(), n * sizeof(ssp::SolveDesc),
@@ -651,28 +689,50 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
             HIP_TRY(ssp::plain_march(sorted[0], owner->d_descs, nsteps, pl->d_plain, pl->d_plain_flags, stream));
             if (sorted[0].snap) HIP_TRY(ssp::launch_output(sorted[0].P, owner->d_descs, 1, sorted[0].nout, stream));
         } else {
-        // marches: one launch for the 1024-thread lengths together, one per other length
-        int fam = 0;
-        while (fam < n && ssp::march_family_member(sorted[fam].P)) ++fam;
-        if (fam > 0 && sorted[0].P != sorted[fam - 1].P)
-            HIP_TRY(ssp::launch_march_family(owner->d_descs, fam, nsteps, stream));
-        else
-            fam = 0;
-        for (int start = fam; start < n;) {
-            int end = start;
-            while (end < n && sorted[end].P == sorted[start].P) ++end;
-            HIP_TRY(ssp::launch_march(sorted[start].P, owner->d_descs + start, end - start, nsteps, stream));
-            start = end;
-        }
-        // outputs: one launch per length
-        for (int start = 0; start < n;) {
-            int end = start;
-            while (end < n && sorted[end].P == sorted[start].P) ++end;
-            int rows = 0;
-            for (int k = start; k < end; ++k) rows = std::max(rows, sorted[k].snap ? sorted[k].nout : 0);
-            HIP_TRY(ssp::launch_output(sorted[start].P, owner->d_descs + start, end - start, rows, stream));
-            start = end;
-        }
+            // launch groups: the 1024-thread lengths together (one launch), then one per other
+            // length; each group's march is followed by its output launches (one per length)
+            struct Group { int start, end; bool family; };
+            std::vector<Group> groups;
+            int fam = 0;
+            while (fam < n && ssp::march_family_member(sorted[fam].P)) ++fam;
+            if (fam > 0 && sorted[0].P != sorted[fam - 1].P) groups.push_back({0, fam, true});
+            else fam = 0;
+            for (int start = fam; start < n;) {
+                int end = start;
+                while (end < n && sorted[end].P == sorted[start].P) ++end;
+                groups.push_back({start, end, false});
+                start = end;
+            }
+            // groups run concurrently: the first on the caller's stream, the others on the
+            // plan's side streams, forked from and joined back into the caller's stream
+            const int ng = static_cast<int>(groups.size());
+            if (ng > 1) {
+                HIP_TRY(ensure_side_streams(owner));
+                HIP_TRY(hipEventRecord(owner->fork, stream));
+            }
+            for (int g = 0; g < ng; ++g) {
+                hipStream_t gs = g == 0 ? stream : owner->side[(g - 1) % kSideStreams];
+                if (g > 0) HIP_TRY(hipStreamWaitEvent(gs, owner->fork, 0));
+                const Group &G = groups[g];
+                int gmax = 0;
+                for (int k = G.start; k < G.end; ++k) gmax = std::max(gmax, sorted[k].nsteps);
+                if (G.family)
+                    HIP_TRY(ssp::launch_march_family(owner->d_descs + G.start, G.end - G.start, gmax, gs));
+                else
+                    HIP_TRY(ssp::launch_march(sorted[G.start].P, owner->d_descs + G.start, G.end - G.start, gmax, gs));
+                for (int start = G.start; start < G.end;) {
+                    int end = start;
+                    while (end < G.end && sorted[end].P == sorted[start].P) ++end;
+                    int rows = 0;
+                    for (int k = start; k < end; ++k) rows = std::max(rows, sorted[k].snap ? sorted[k].nout : 0);
+                    HIP_TRY(ssp::launch_output(sorted[start].P, owner->d_descs + start, end - start, rows, gs));
+                    start = end;
+                }
+            }
+            for (int j = 0; j < std::min(ng - 1, kSideStreams); ++j) {
+                HIP_TRY(hipEventRecord(owner->join[j], owner->side[j]));
+                HIP_TRY(hipStreamWaitEvent(stream, owner->join[j], 0));
+            }
         }
     }
     ssp_status worst = SSP_OK;
@@ -683,7 +743,7 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
     for (int i = 0; i < n; ++i) {
         ssp_plan *pl = plans[i];
         ssp::DevStats st = hs[i];
-        if (nsteps == 0) {
+        if (steps[i] == 0) {
             st = ssp::DevStats{};
             st.step_index = pl->step_index;
         }
@@ -705,6 +765,23 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
     }
     if (worst == SSP_E_DIVERGED) g_last_error = "Neumann series diverged";
     return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *const *field_out,
+                           float *const *tl_out, ssp_stats *stats) {
+    if (n <= 0 || n > (1 << 24)) return fail(SSP_E_INVAL, "no plans");
+    std::vector<int> steps(n, nsteps);
+    return march_batch_impl(plans, n, steps.data(), field_out, tl_out, stats);
+}
+
+ssp_status ssp_march_batch_steps(ssp_plan *const *plans, int n, const int *nsteps, double *const *field_out,
+                                 float *const *tl_out, ssp_stats *stats) {
+    if (!nsteps) return fail(SSP_E_INVAL, "nsteps is NULL");
+    return march_batch_impl(plans, n, nsteps, field_out, tl_out, stats);
 }
 
 ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int nsteps, void *d_tl,
@@ -753,6 +830,7 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
         d.field = static_cast<float2 *>(d_psi) + static_cast<size_t>(b) * pl->N;
         ssp::set_work(d, pl->d_bwork + ssp::kWorkPerSolve * static_cast<size_t>(b) * pl->N);
         d.nout = nout;
+        d.nsteps = nsteps;
         d.step = static_cast<long long *>(d_step) + b;
         d.stats = (d_stats ? static_cast<ssp::DevStats *>(d_stats) : pl->d_bstats) + b;
         d.tl_out = d_tl ? static_cast<float *>(d_tl) + static_cast<size_t>(b) * nout * pl->N : nullptr;

@@ -50,10 +50,12 @@ struct SolveDesc {
     float2 *fld_out;            // [nout][N] or null (complex64, carrier included)
     int out_every;
     int nout;                   // output rows available in snap / tl_out / fld_out
+    int nsteps;                 // range steps of this solve in the launch
 };
 
 // Launch the fused persistent march: one workgroup per descriptor, all with the same FFT
-// length P.  Returns hipSuccess or the launch error.
+// length P, each marching its own descriptor's nsteps (nsteps here: the largest, 0 = no
+// launch).  Returns hipSuccess or the launch error.
 // Scratch elements (complex) per solve behind SolveDesc::work: work, pot, wacc, xs.
 constexpr int kWorkPerSolve = 5;
 inline void set_work(SolveDesc &d, float2 *base) {

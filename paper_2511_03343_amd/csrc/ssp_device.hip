@@ -781,12 +781,13 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     }
 }
 
-// One solve per workgroup (descriptor blockIdx.x), all with convolution length P.
+// One solve per workgroup (descriptor blockIdx.x, its own step count), all with
+// convolution length P.  The launch argument is the largest step count.
 template <int P>
 __global__ __launch_bounds__(ECfg<P>::T) void k_march(const SolveDesc *__restrict__ descs, int nsteps) {
     __shared__ float2 lds_raw[lds_words<eng_len<P>()>()];
     __shared__ double red[2 * (ECfg<P>::T / 64)];
-    march_body<P>(descs[blockIdx.x], nsteps, lds_raw, red);
+    march_body<P>(descs[blockIdx.x], descs[blockIdx.x].nsteps, lds_raw, red);
 }
 
 // Solves of uneven length in one launch: every length that runs with 1024-thread workgroups
@@ -800,9 +801,9 @@ __global__ __launch_bounds__(kFamilyT) void k_march_family(const SolveDesc *__re
     __shared__ double red[2 * (kFamilyT / 64)];
     const SolveDesc &d = descs[blockIdx.x];
     switch (d.P) {  // uniform over the workgroup
-        case 8192: march_body<8192>(d, nsteps, lds_raw, red); break;
-        case 16384: march_body<16384>(d, nsteps, lds_raw, red); break;
-        case 32768: march_body<32768>(d, nsteps, lds_raw, red); break;
+        case 8192: march_body<8192>(d, d.nsteps, lds_raw, red); break;
+        case 16384: march_body<16384>(d, d.nsteps, lds_raw, red); break;
+        case 32768: march_body<32768>(d, d.nsteps, lds_raw, red); break;
         default: break;
     }
 }

@@ -30,6 +30,7 @@ uint16_t bf16_round(float f) {
 }
 
 const long double kPi = 3.141592653589793238462643383279502884L;
+const double kPiD = 3.141592653589793238462643383279502884;
 
 cld expj(long double t) { return cld(std::cos(t), std::sin(t)); }
 
@@ -234,34 +235,30 @@ cd pade_eval(const PadeSet &ps, cd x) {
 }
 
 // ------------------------------------------------------------------------------ host FFT
-namespace {
-void fft_rec(cd *x, int n, int stride, cd *out, int sign) {
-    if (n == 1) {
-        out[0] = x[0];
-        return;
-    }
-    int r = (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : 5;
-    int m = n / r;
-    std::vector<cd> sub(n);
-    for (int k = 0; k < r; ++k) fft_rec(x + k * stride, m, stride * r, sub.data() + k * m, sign);
-    for (int q = 0; q < m; ++q) {
-        for (int s = 0; s < r; ++s) {
-            cd acc(0);
-            for (int k = 0; k < r; ++k) {
-                long double ang = sign * 2 * kPi * static_cast<long double>(k) * (q + s * m) / n;
-                cd w(static_cast<double>(std::cos(ang)), static_cast<double>(std::sin(ang)));
-                acc += w * sub[k * m + q];
-            }
-            out[q + s * m] = acc;
-        }
-    }
-}
-}  // namespace
-
 void host_fft(std::vector<cd> &x, int sign) {
-    std::vector<cd> out(x.size());
-    fft_rec(x.data(), static_cast<int>(x.size()), 1, out.data(), sign);
-    x.swap(out);
+    // iterative radix-2 (the chirp lengths are powers of two): bit reversal, then log2 n
+    // passes of butterflies with twiddles from a table computed once
+    const int n = static_cast<int>(x.size());
+    std::vector<cd> w(n / 2 > 0 ? n / 2 : 1);
+    for (int j = 0; j < n / 2; ++j) {
+        const double ang = sign * 2 * kPiD * static_cast<double>(j) / n;
+        w[j] = cd(std::cos(ang), std::sin(ang));
+    }
+    for (int i = 1, j = 0; i < n; ++i) {
+        int bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(x[i], x[j]);
+    }
+    for (int len = 2; len <= n; len <<= 1) {
+        const int half = len / 2, step = n / len;
+        for (int i = 0; i < n; i += len)
+            for (int k = 0; k < half; ++k) {
+                const cd t = w[static_cast<size_t>(k) * step] * x[i + k + half];
+                x[i + k + half] = x[i + k] - t;
+                x[i + k] += t;
+            }
+    }
 }
 
 int chirp_fft_length(int n_min) {
@@ -275,12 +272,15 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, DeviceTabl
     const int N = nz, M = nz + 1, P = chirp_fft_length(2 * nz - 1);
     t.nz = N;
     t.P = P;
-    // chirp c_d = exp(i pi d^2 / (2M)), argument reduced exactly with d^2 mod 4M
-    auto chirp = [&](long long d) {
-        long long r = (d * d) % (4LL * M);
-        long double ang = kPi * static_cast<long double>(r) / (2.0L * M);
-        return cd(static_cast<double>(std::cos(ang)), static_cast<double>(std::sin(ang)));
-    };
+    // chirp c_d = exp(i pi d^2 / (2M)) for d = 0..2N (even in d), the argument reduced
+    // exactly with d^2 mod 4M
+    std::vector<cd> ch(2 * static_cast<size_t>(N) + 1);
+    for (long long d = 0; d <= 2LL * N; ++d) {
+        const long long r = (d * d) % (4LL * M);
+        const double ang = kPiD * static_cast<double>(r) / (2.0 * M);
+        ch[d] = cd(std::cos(ang), std::sin(ang));
+    }
+    auto chirp = [&](long long d) { return ch[d < 0 ? -d : d]; };
     std::vector<cd> K1(P, 0.0), K2(P, 0.0);
     // element n (1..N) at position n-1: Toeplitz window c_{k-n}, Hankel window c_{(k-1)+(n-1)+2}
     for (long long d = 1 - N; d <= N - 1; ++d) K1[((d % P) + P) % P] = chirp(d);
@@ -302,9 +302,9 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, DeviceTabl
     if (split) {
         t.twist.resize(4 * static_cast<size_t>(PE));
         for (int n = 0; n < PE; ++n) {
-            long double ang = -2 * kPi * static_cast<long double>(n) / P;
-            split_df(static_cast<double>(std::cos(ang)), t.twist[4 * n], t.twist[4 * n + 2]);
-            split_df(static_cast<double>(std::sin(ang)), t.twist[4 * n + 1], t.twist[4 * n + 3]);
+            const double ang = -2 * kPiD * static_cast<double>(n) / P;
+            split_df(std::cos(ang), t.twist[4 * n], t.twist[4 * n + 2]);
+            split_df(std::sin(ang), t.twist[4 * n + 1], t.twist[4 * n + 3]);
         }
     }
     const double scale = 0.5 * std::sqrt(2.0 / M) / P;  // (i/2) sqrt(2/M) / P, i applied below
@@ -327,8 +327,8 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, DeviceTabl
     const int O = PE / 8;
     t.twiddle.resize(3 * static_cast<size_t>(O + 1));
     for (int e = 0; e <= O; ++e) {
-        long double ang = -2 * kPi * static_cast<long double>(e) / PE;
-        double re = static_cast<double>(std::cos(ang)), im = static_cast<double>(std::sin(ang));
+        const double ang = -2 * kPiD * static_cast<double>(e) / PE;
+        const double re = std::cos(ang), im = std::sin(ang);
         float hr, lr, hi, li;
         split_df(re, hr, lr);
         split_df(im, hi, li);

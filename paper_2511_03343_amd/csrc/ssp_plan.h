@@ -34,7 +34,7 @@ bool pade_coefficients(double sigma, int p, double alpha, PadeSet &out, std::str
 // R(x) = C prod (1 + a_j x)/(1 + b_j x)
 cd pade_eval(const PadeSet &ps, cd x);
 
-// In-place complex FFT of length n (a power of two times 3^a 5^b), sign -1 forward.
+// In-place complex FFT of length n (a power of two), sign -1 forward.
 void host_fft(std::vector<cd> &x, int sign);
 
 // Smallest FFT length accepted by the device engine that is >= n_min.

@@ -91,6 +91,8 @@ def lib() -> C.CDLL:
             "ssp_count_outputs": (C.c_int, [_VP, C.c_int]),
             "ssp_march_batch": (S, [C.POINTER(_VP), C.c_int, C.c_int, C.POINTER(_DP),
                                     C.POINTER(_FP), C.POINTER(ssp_stats)]),
+            "ssp_march_batch_steps": (S, [C.POINTER(_VP), C.c_int, C.POINTER(C.c_int), C.POINTER(_DP),
+                                          C.POINTER(_FP), C.POINTER(ssp_stats)]),
             "ssp_march_device": (S, [_VP, C.c_int, _VP, _VP, C.c_int, _VP, _VP]),
             "ssp_to_sine": (S, [_VP, C.c_int, _VP, _VP]),
             "ssp_from_sine": (S, [_VP, C.c_int, _VP, _VP, _VP]),
@@ -230,6 +232,22 @@ def ssp_march_batch(plans, nzs, nsteps, want_field=True, want_tl=True):
     tptr = (_FP * n)(*[None if t is None else _fp(t) for t in tl])
     stats = (ssp_stats * n)()
     status = _check(lib().ssp_march_batch(arr, n, int(nsteps), fptr, tptr, stats))
+    return status, fl, tl, [s.as_dict() for s in stats]
+
+
+def ssp_march_batch_steps(plans, nzs, nsteps, want_field=True, want_tl=True):
+    """Like ssp_march_batch with a step count per plan (nsteps: sequence of n ints)."""
+    n = len(plans)
+    arr = (_VP * n)(*plans)
+    ns = (C.c_int * n)(*[int(k) for k in nsteps])
+    fl = [np.zeros((ssp_count_outputs(pl, k), nz), dtype=np.complex128) if want_field else None
+          for pl, nz, k in zip(plans, nzs, nsteps)]
+    tl = [np.zeros((ssp_count_outputs(pl, k), nz), dtype=np.float32) if want_tl else None
+          for pl, nz, k in zip(plans, nzs, nsteps)]
+    fptr = (_DP * n)(*[None if f is None else _dp(f.view(np.float64)) for f in fl])
+    tptr = (_FP * n)(*[None if t is None else _fp(t) for t in tl])
+    stats = (ssp_stats * n)()
+    status = _check(lib().ssp_march_batch_steps(arr, n, ns, fptr, tptr, stats))
     return status, fl, tl, [s.as_dict() for s in stats]
 
 
