@@ -373,6 +373,8 @@ def main():
     ap.add_argument("--graph", type=int, default=1, help="replay recorded launches (HIP graph)")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--duration", type=float, default=2.0, help="serving: arrival window (s)")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="MiB of a plain device copy run first (counter calibration)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-transforms", action="store_true",
                     help="skip the stand-alone transform measurements")
@@ -394,6 +396,17 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(dev)           # default priority
     torch.cuda.set_stream(stream)
+
+    if args.copy_calibration > 0:
+        # a plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
+        # scale between those counters and bytes moved
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     runner = {"broadband": run_broadband, "serving": run_serving}.get(args.workload, run_device_batch)
     updates, wall, roof, config, statuses, plain, nz = runner(args, ssp, torch, stream, dev)

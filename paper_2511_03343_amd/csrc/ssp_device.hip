@@ -80,6 +80,12 @@ __device__ __forceinline__ float2 ld2(const float2 *p, int i) {
     auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc(p), i * 8, 0, 0);
     return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
 }
+// element v + s with s uniform over the workgroup (the constant or uniform part goes to the
+// scalar offset of the access)
+__device__ __forceinline__ float2 ld2s(const float2 *p, int v, int s) {
+    auto r = __builtin_amdgcn_raw_buffer_load_b64(rsrc(p), v * 8, s * 8, 0);
+    return make_float2(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
 __device__ __forceinline__ float4 ld4(const float4 *p, int i) {
     auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc(p), i * 16, 0, 0);
     return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
@@ -183,8 +189,11 @@ __device__ __forceinline__ int opaque_tid() {
 // Because T is a multiple of every middle stride Ns, a thread's k is t mod Ns in every
 // pass, so its twiddles are the same in every transform of a launch: they are computed
 // once per launch and held in registers (double-float: FP32 value + bf16 pair remainder).
-// LDS: padded index (one slot per 16 elements, spreads power-of-two strides over the
-// banks); two data buffers when they fit (one barrier per exchange), else one.
+// LDS: padded index lp(i) = i + i/16 (one slot per 16 elements, spreads power-of-two strides
+// over the banks); two data buffers when they fit (one barrier per exchange), else one.
+// Every padded index of a pass is a per-thread base plus a compile-time offset (the
+// offsets that are added are multiples of 16, or keep within one 16-block), so exchanges
+// cost no index arithmetic beyond one base per pass.
 template <int P>
 struct Cfg {
     static constexpr int T = P <= 512 ? 64 : (P == 1024 ? 128 : (P <= 4096 ? 256 : 1024));
@@ -193,11 +202,13 @@ struct Cfg {
     static constexpr int DLEN = P + (P >> PADSH);
     static constexpr int O = P / 8;
     static constexpr int LOG2O = __builtin_ctz(P / 8);
-    static constexpr bool PINGPONG = (2 * DLEN * 8 + 12 * T + 1024) <= 160 * 1024;
+    static constexpr bool PINGPONG = (2 * DLEN * 8 + 16 * T + 1024) <= 160 * 1024;
 };
 
 template <int P>
 __device__ __forceinline__ int lp(int i) { return i + (i >> Cfg<P>::PADSH); }
+// the same at compile time
+constexpr int lpc(int i) { return i + (i >> 4); }
 
 // radix of the middle pass at stride Ns
 template <int P, int Ns>
@@ -266,7 +277,7 @@ __device__ __forceinline__ void fetch_twiddle(const uint32_t *tab, int e, float2
 // Middle-pass table in LDS: pass at stride Ns holds w_{Ns R}^{r k} at
 // offset(Ns) + (r - 1) Ns + k, so lanes with consecutive k read consecutive entries.
 template <int P, int Ns>
-__device__ __forceinline__ void init_mid_table(float2 *th, uint32_t *tl, const uint32_t *tab) {
+__device__ __forceinline__ void init_mid_table(float4 *t4, const uint32_t *tab) {
     if constexpr (Ns < Cfg<P>::T) {
         constexpr int R = mid_radix<P, Ns>();
         constexpr int OFF = mid_tab_offset<P, Ns>();
@@ -276,21 +287,20 @@ __device__ __forceinline__ void init_mid_table(float2 *th, uint32_t *tl, const u
             float2 h;
             uint32_t l;
             fetch_twiddle<P>(tab, r * k * STRIDE, h, l);
-            th[OFF + idx] = h;
-            tl[OFF + idx] = l;
+            t4[OFF + idx] = make_float4(h.x, h.y, __uint_as_float(l & 0xffff0000u), __uint_as_float(l << 16));
         }
-        init_mid_table<P, Ns * R>(th, tl, tab);
+        init_mid_table<P, Ns * R>(t4, tab);
     }
 }
 
 // All twiddles of a launch: the middle-pass table (LDS, ends with a barrier) and the
 // thread's last-pass twiddles (registers).
 template <int P>
-__device__ __forceinline__ void init_twiddles(Twiddles<P> &tw, float2 *th, uint32_t *tl, const uint32_t *tab) {
+__device__ __forceinline__ void init_twiddles(Twiddles<P> &tw, float4 *t4, const uint32_t *tab) {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int r = 1; r < Cfg<P>::RT; ++r) fetch_twiddle<P>(tab, r * tid, tw.h[r - 1], tw.l[r - 1]);
-    init_mid_table<P, Cfg<P>::RT>(th, tl, tab);
+    init_mid_table<P, Cfg<P>::RT>(t4, tab);
     __syncthreads();
 }
 
@@ -304,8 +314,7 @@ __device__ __forceinline__ float2 twmul(float2 x, float2 h, uint32_t l) {
 // uses buffer k mod 2 (buffer 0 only when two do not fit), chosen at compile time.
 struct LdsBufs {
     float2 *b0, *b1;
-    float2 *th;   // middle-pass twiddle table
-    uint32_t *tl;
+    float4 *tw4;  // middle-pass twiddle table: hi.re, hi.im, lo.re, lo.im
 };
 
 template <int P, int PH>
@@ -328,28 +337,49 @@ __device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBuf
         constexpr int PER = RT / R;
         constexpr int NB = P / R;
         constexpr int OFF = mid_tab_offset<P, Ns>();
+        // constant-offset addressing applies when every added offset keeps the padding
+        // count exact (see the engine notes); otherwise the index is padded per access
+        constexpr bool FAST = (T % 16 == 0) && (NB % 16 == 0) &&
+                              ((Ns % 16 == 0) || (16 % Ns == 0 && (Ns * R) % 16 == 0));
         const int tid = opaque_tid();
         const float2 *in = phase_buf<P, PH>(L);
+        if constexpr (FAST) {
+            const float2 *rb = in + lp<P>(tid);
 #pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int j = tid + i * T;
+            for (int i = 0; i < PER; ++i)
 #pragma unroll
-            for (int r = 0; r < R; ++r) x[i * R + r] = in[lp<P>(j + r * NB)];
+                for (int r = 0; r < R; ++r) x[i * R + r] = rb[i * lpc(T) + r * lpc(NB)];
+        } else {
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int j = tid + i * T;
+#pragma unroll
+                for (int r = 0; r < R; ++r) x[i * R + r] = in[lp<P>(j + r * NB)];
+            }
         }
         before_write<P>();
         float2 *out = phase_buf<P, PH + 1>(L);
+        const int t2 = opaque_tid();
+        const int k = t2 & (Ns - 1);  // T is a multiple of Ns: the same k for every i
+        const float4 *wt = L.tw4 + OFF + k;
+        float2 *wb = out + lp<P>((t2 - k) * R + k);
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-            const int j = tid + i * T;
-            const int k = j & (Ns - 1);
             float2 *v = &x[i * R];
 #pragma unroll
-            for (int r = 1; r < R; ++r)
-                v[r] = twmul<INV>(v[r], L.th[OFF + (r - 1) * Ns + k], L.tl[OFF + (r - 1) * Ns + k]);
+            for (int r = 1; r < R; ++r) {
+                const float4 w = wt[(r - 1) * Ns];
+                v[r] = INV ? cmul_df_conj(v[r], w) : cmul_df(v[r], w);
+            }
             Dft<R, INV>::run(v);
-            const int base = (j - k) * R + k;
+            if constexpr (FAST) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) out[lp<P>(base + r * Ns)] = v[r];
+                for (int r = 0; r < R; ++r) wb[i * lpc(T * R) + lpc(r * Ns)] = v[r];
+            } else {
+                const int base = (t2 + i * T - k) * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) out[lp<P>(base + r * Ns)] = v[r];
+            }
         }
         __syncthreads();
         mid_passes<P, INV, Ns * R, PH + 1>(x, L, tw);
@@ -366,18 +396,18 @@ __device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, c
     Dft<RT, INV>::run(x);
     before_write<P>();
     {
-        float2 *out = phase_buf<P, PH>(L);
+        // tid RT + r stays within one 16-block of the padded index (RT <= 16)
+        float2 *out = phase_buf<P, PH>(L) + lp<P>(tid * RT);
 #pragma unroll
-        for (int r = 0; r < RT; ++r) out[lp<P>(tid * RT + r)] = x[r];
+        for (int r = 0; r < RT; ++r) out[r] = x[r];
     }
     __syncthreads();
     mid_passes<P, INV, RT, PH>(x, L, tw);
     // last pass: Ns = T, butterfly j = t, twiddles w_P^{r t}, outputs at t + r T
     {
-        const float2 *in = phase_buf<P, PH + fft_phases<P>() - 1>(L);
-        const int t2 = opaque_tid();
+        const float2 *in = phase_buf<P, PH + fft_phases<P>() - 1>(L) + lp<P>(opaque_tid());
 #pragma unroll
-        for (int r = 0; r < RT; ++r) x[r] = in[lp<P>(t2 + r * T)];
+        for (int r = 0; r < RT; ++r) x[r] = in[r * lpc(T)];
 #pragma unroll
         for (int r = 1; r < RT; ++r)
             x[r] = twmul<INV>(x[r], tw.h[r - 1], tw.l[r - 1]);
@@ -395,16 +425,25 @@ __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const Lds
     const int tid = opaque_tid();
     before_write<P>();
     float2 *buf = phase_buf<P, PH>(L);
+    {
+        float2 *wb = buf + lp<P>(tid);
 #pragma unroll
-    for (int i = 0; i < RT; ++i) buf[lp<P>(tid + i * T)] = x[i];
+        for (int i = 0; i < RT; ++i) wb[i * lpc(T)] = x[i];
+    }
     __syncthreads();
     const int t2 = opaque_tid();
+    // reflected position of q = t2 + i T:  even: -q mod P = u + (RT - 1 - i + c) T with
+    // u = -t2 mod T, c = (t2 == 0) (position 0 itself for i = 0, c = 1);
+    // odd: P - 1 - q = (T - 1 - t2) + (RT - 1 - i) T
+    const int u = ODD ? (T - 1 - t2) : ((T - t2) & (T - 1));
+    const int c = ODD ? 0 : (t2 == 0 ? 1 : 0);
+    const float2 *rb = buf + lp<P>(u) + c * lpc(T);
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-        const int q = t2 + i * T;
-        const int qr = ODD ? (P - 1 - q) : ((P - q) & (P - 1));
-        const float2 yr = buf[lp<P>(qr)];
-        x[i] = csub(cmul(x[i], ld2(k1, q)), cmul(yr, ld2(k2, q)));
+        float2 yr;
+        if (!ODD && i == 0) yr = c ? buf[0] : rb[(RT - 1) * lpc(T)];
+        else yr = rb[(RT - 1 - i) * lpc(T)];
+        x[i] = csub(cmul(x[i], ld2s(k1, t2, i * T)), cmul(yr, ld2s(k2, t2, i * T)));
     }
 }
 
@@ -485,17 +524,17 @@ __device__ __forceinline__ void dst_core(float2 (&x)[ECfg<P>::RT], const LdsBufs
 // LDS of one workgroup for engine length PE, carved from one array: the data buffer(s),
 // then the middle-pass twiddle table (FP32 values, then the bf16 remainders).
 template <int PE>
-constexpr int lds_words() {  // in float2 units
-    return (Cfg<PE>::PINGPONG ? 2 : 1) * Cfg<PE>::DLEN + (mid_tab_len<PE>() + 1) + (mid_tab_len<PE>() + 2) / 2;
+constexpr int lds_words() {  // in float4 units (16-byte aligned storage)
+    return ((Cfg<PE>::PINGPONG ? 2 : 1) * Cfg<PE>::DLEN + 1) / 2 + mid_tab_len<PE>() + 1;
 }
 template <int PE>
-__device__ __forceinline__ LdsBufs carve_lds(float2 *raw) {
-    float2 *th = raw + (Cfg<PE>::PINGPONG ? 2 : 1) * Cfg<PE>::DLEN;
-    return LdsBufs{raw, Cfg<PE>::PINGPONG ? raw + Cfg<PE>::DLEN : raw, th,
-                   reinterpret_cast<uint32_t *>(th + mid_tab_len<PE>() + 1)};
+__device__ __forceinline__ LdsBufs carve_lds(float4 *raw4) {
+    float2 *raw = reinterpret_cast<float2 *>(raw4);
+    constexpr int NB = (Cfg<PE>::PINGPONG ? 2 : 1) * Cfg<PE>::DLEN;
+    return LdsBufs{raw, Cfg<PE>::PINGPONG ? raw + Cfg<PE>::DLEN : raw, raw4 + (NB + 1) / 2};
 }
 #define SSP_LDS_DECL(PE)                          \
-    __shared__ float2 lds_raw[lds_words<PE>()];   \
+    __shared__ float4 lds_raw[lds_words<PE>()];   \
     const LdsBufs L = carve_lds<PE>(lds_raw)
 
 // Sum two doubles over the workgroup in a fixed order (wave butterfly, then waves in
@@ -604,7 +643,7 @@ __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, 
 // ----------------------------------------------------------------------------- march
 // One workgroup marches one solve through nsteps range steps.
 template <int P>
-__device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float2 *lds_raw, double *red) {
+__device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float4 *lds_raw, double *red) {
     constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
     // the Neumann multiplier stays in registers for up to 8 elements per thread
     constexpr bool kBInRegs = (RT <= 8) && (T < 1024);
@@ -622,7 +661,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     const int tid = threadIdx.x;
     const int N = d.N, p = d.p, nmax = d.nmax;
     Twiddles<eng_len<P>()> tw;
-    init_twiddles<eng_len<P>()>(tw, L.th, L.tl, d.tw);
+    init_twiddles<eng_len<P>()>(tw, L.tw4, d.tw);
 
     // The state u is not held in registers: d.field holds the state at the start of the
     // step (the recovery point if the step diverges) and d.work the state between Pade
@@ -785,7 +824,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
 // convolution length P.  The launch argument is the largest step count.
 template <int P>
 __global__ __launch_bounds__(ECfg<P>::T) void k_march(const SolveDesc *__restrict__ descs, int nsteps) {
-    __shared__ float2 lds_raw[lds_words<eng_len<P>()>()];
+    __shared__ float4 lds_raw[lds_words<eng_len<P>()>()];
     __shared__ double red[2 * (ECfg<P>::T / 64)];
     march_body<P>(descs[blockIdx.x], descs[blockIdx.x].nsteps, lds_raw, red);
 }
@@ -797,7 +836,7 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int kFamilyLds = cmax(lds_words<8192>(), lds_words<16384>());
 static_assert(Cfg<8192>::T == kFamilyT && Cfg<16384>::T == kFamilyT, "family thread count");
 __global__ __launch_bounds__(kFamilyT) void k_march_family(const SolveDesc *__restrict__ descs, int nsteps) {
-    __shared__ float2 lds_raw[kFamilyLds];
+    __shared__ float4 lds_raw[kFamilyLds];
     __shared__ double red[2 * (kFamilyT / 64)];
     const SolveDesc &d = descs[blockIdx.x];
     switch (d.P) {  // uniform over the workgroup
@@ -818,7 +857,7 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_transform(const SolveDesc *__res
     const SolveDesc &d = *desc;
     const int N = d.N;
     Twiddles<eng_len<P>()> tw;
-    init_twiddles<eng_len<P>()>(tw, L.th, L.tl, d.tw);
+    init_twiddles<eng_len<P>()>(tw, L.tw4, d.tw);
     const float2 *vin = in + static_cast<size_t>(blockIdx.x) * N;
     float2 *vout = out + static_cast<size_t>(blockIdx.x) * N;
     float2 x[RT];
@@ -858,7 +897,7 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_output(const SolveDesc *__restri
     if (row >= d.nout || !d.snap || !d.stats || d.out_every <= 0) return;  // uniform
     const int N = d.N, tid = threadIdx.x;
     Twiddles<eng_len<P>()> tw;
-    init_twiddles<eng_len<P>()>(tw, L.th, L.tl, d.tw);
+    init_twiddles<eng_len<P>()>(tw, L.tw4, d.tw);
     // the march that wrote the snapshots started at step step_index - steps_done
     const long long n0 = d.stats->step_index - d.stats->steps_done;
     const long long n = (n0 / d.out_every + 1) * d.out_every + static_cast<long long>(row) * d.out_every;
@@ -936,7 +975,7 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_plain_half(const SolveDesc *__re
     const SolveDesc &d = *desc;
     if (ps->halt || ps->done) return;  // uniform: the series has stopped
     Twiddles<eng_len<P>()> tw;
-    init_twiddles<eng_len<P>()>(tw, L.th, L.tl, d.tw);
+    init_twiddles<eng_len<P>()>(tw, L.tw4, d.tw);
     const int N = d.N;
     float2 x[RT];
 #pragma unroll
