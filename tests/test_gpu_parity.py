@@ -449,6 +449,73 @@ def test_graph_replays_match_plain_launches(ssp, gpu):
     assert results[0][-1][2] == [chunk * nchunks] * B
 
 
+def _device_batch_vs_oracle(ssp, torch, s, B, nsteps, samples, profile):
+    """The benchmark's launch configuration: B solves of one plan on a dedicated stream,
+    graph-recorded launches, TL rows on the device; sampled solves against the oracle."""
+    stream = torch.cuda.Stream()
+    pl = make_plan(ssp, s, profile=profile)
+    zs = W.source_depths(B, 50.0, 2000.0)
+    try:
+        ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_GRAPH, 1)
+        psi = np.stack([W.gaussian_starter(s.nz, s.depth, s.freq, s.c0, z) for z in zs])
+        with torch.cuda.stream(stream):
+            d_psi = torch.from_numpy(psi.astype(np.complex64)).cuda()
+            steps = torch.zeros(B, dtype=torch.int64, device="cuda")
+            nout = nsteps // s.out_every + 1
+            d_tl = torch.zeros((B, nout, s.nz), dtype=torch.float32, device="cuda")
+            out = torch.empty_like(d_psi)
+        stream.synchronize()
+        ssp.ssp_to_sine(pl, B, d_psi.data_ptr(), d_psi.data_ptr())
+        ssp.ssp_march_device(pl, B, d_psi.data_ptr(), steps.data_ptr(), nsteps, d_tl.data_ptr())
+        ssp.ssp_from_sine(pl, B, d_psi.data_ptr(), steps.data_ptr(), out.data_ptr())
+        stream.synchronize()
+        tl = d_tl.cpu().numpy()
+        fld = out.cpu().numpy().astype(np.complex128)
+        assert steps.cpu().tolist() == [nsteps] * B
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    for b in samples:
+        s1 = W.Solve(**{**s.__dict__, "zs": float(zs[b]), "nsteps": nsteps})
+        ref = oracle_march(s1)
+        rows = ref.tl.shape[0]
+        mask = ref.tl < 120.0
+        dtl = np.abs(tl[b, :rows].astype(np.float64) - ref.tl)[mask]
+        err = np.linalg.norm(fld[b] - ref.final) / np.linalg.norm(ref.final)
+        _report(f"bench config b={b}", nz=s.nz, relL2=f"{err:.3e}", max_dTL=f"{dtl.max():.3e}")
+        assert err <= REL_L2 and dtl.max() <= DTL
+
+
+def test_munk_bench_launch_configuration_sampled(ssp, gpu):
+    # 512 solves of the deep Munk waveguide at Nz = 4096, as bench.py times them
+    s = W.munk_deep()
+    _device_batch_vs_oracle(ssp, gpu, s, 512, 24, [0, 255, 511], "table")
+
+
+def test_eddy_bench_launch_configuration_sampled(ssp, gpu):
+    # 256 Munk + eddy solves at Nz = 16384 (split transforms), potential on the device
+    s = W.munk_eddy()
+    _device_batch_vs_oracle(ssp, gpu, s, 256, 10, [0, 255], "analytic")
+
+
+def test_broadband_one_launch_sampled(ssp, gpu):
+    # frequencies of the broadband set with lengths 8192, 16384 and 32768 in one batched call
+    solves = [W.broadband()[i] for i in (0, 100, 255)]
+    nsteps = 8
+    plans = [make_plan(ssp, s) for s in solves]
+    try:
+        for pl, s in zip(plans, solves):
+            ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_OUT_EVERY, 4)
+            ssp.ssp_set_field(pl, s.starter(), s.nz)
+        st, fl, tl, stats = ssp.ssp_march_batch(plans, [s.nz for s in solves], nsteps)
+    finally:
+        for pl in plans:
+            ssp.ssp_plan_destroy(pl)
+    for s, f, t in zip(solves, fl, tl):
+        s.out_every = 4
+        compare(f"broadband f={s.freq:.1f} nz={s.nz}", f, t, oracle_march(s, nsteps=nsteps))
+
+
 def test_munk_full_size_full_range_vs_stored_oracle(ssp, gpu):
     # the benchmark workload at its full size and range (Nz = 4096, 4000 steps, 100 km)
     # against the oracle's field every 10 km (tests/golden/make_golden.py munk4096)
