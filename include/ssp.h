@@ -63,10 +63,15 @@ enum {
                               Use ssp_plan_set_stream to pass a pointer exactly. */
     SSP_OPT_ENGINE = 4,    /* 0 = fused persistent kernel (default); 1 = plain form: one
                               kernel per transform / pointwise step, host-driven loop */
-    SSP_OPT_GRAPH = 5      /* 1: ssp_march_device records its launches (march + outputs) in
+    SSP_OPT_GRAPH = 5,     /* 1: ssp_march_device records its launches (march + outputs) in
                               a HIP graph on the first call and replays the graph on later
                               calls with the same arguments; needs a non-null stream.
                               0 (default): plain launches */
+    SSP_OPT_VARIANT = 6    /* engine layout of the fused march kernel: -1 (default) = the
+                              layout the autotuner chose for this FFT length; 0 or 1 = that
+                              layout (1 falls back to 0 where no second layout exists).
+                              Layouts differ in rounding only; a solve's results do not
+                              depend on what it is batched with. */
 };
 
 /* Analytic range-dependent environment evaluated on the device every step at the step's

@@ -1,0 +1,121 @@
+"""Autotuner for the engine layout of the fused march kernel, per FFT length.
+
+The march kernel of an FFT length P can run in two layouts (SSP_OPT_VARIANT): different
+thread counts, i.e. different elements per thread and radix of the first and last FFT
+passes, with different register / LDS residency (which of the series sum, potential and
+multipliers stay in registers follows from the layout).  For every length with two
+layouts this script marches a full device batch of a representative solve (deep Munk
+waveguide at 50 Hz, [6/6], dr = 25 m, Nz = P/2) in each layout, times the launches with
+HIP events on their stream, checks that the layouts agree to rounding, and writes the
+faster one into csrc/ssp_tuned.h.  Rebuild the library afterwards.
+
+    python -m paper_2511_03343_amd.autotune [--write]
+
+The synthetic inputs come from workloads/ (seeded); nothing here computes the method.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+HEADER = os.path.join(HERE, "csrc", "ssp_tuned.h")
+LENGTHS = [128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768]
+
+
+def _engine_threads(P: int, v: int) -> int:
+    """Thread counts of the two layouts (the same rule as the kernels)."""
+    PE = P // 2 if P > 16384 else P
+    t0 = 64 if PE <= 512 else (128 if PE == 1024 else (256 if PE <= 4096 else 1024))
+    t1 = {1024: 64, 2048: 128, 4096: 512, 8192: 512}.get(PE, t0)
+    return t1 if v else t0
+
+
+def time_layout(ssp, torch, P: int, variant: int, batch: int, steps: int, reps: int):
+    sys.path.insert(0, ROOT)
+    import workloads as W
+    nz = P // 2
+    s = W.munk_deep(nz=nz)
+    stream = torch.cuda.Stream()
+    pl = ssp.ssp_plan_create(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol)
+    try:
+        ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, variant)
+        ssp.ssp_set_profile(pl, 0, -1, s.profile()[0])
+        zs = W.source_depths(batch, 50.0, 2000.0)
+        psi = np.stack([W.gaussian_starter(s.nz, s.depth, s.freq, s.c0, z) for z in zs])
+        with torch.cuda.stream(stream):
+            d_psi = torch.from_numpy(psi.astype(np.complex64)).cuda()
+            d_step = torch.zeros(batch, dtype=torch.int64, device="cuda")
+        stream.synchronize()
+        ssp.ssp_to_sine(pl, batch, d_psi.data_ptr(), d_psi.data_ptr())
+        ssp.ssp_march_device(pl, batch, d_psi.data_ptr(), d_step.data_ptr(), 2)  # warm-up
+        stream.synchronize()
+        best = math.inf
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ssp.ssp_march_device(pl, batch, d_psi.data_ptr(), d_step.data_ptr(), steps)
+            e1.record(stream)
+            stream.synchronize()
+            best = min(best, e0.elapsed_time(e1) / 1e3)
+        out = d_psi.cpu().numpy()
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    return best, out
+
+
+def write_header(choice: dict) -> None:
+    vals = ", ".join(str(choice.get(P, 0)) for P in LENGTHS)
+    with open(HEADER, "w") as f:
+        f.write("// ssp_tuned.h - engine layout of the fused march kernel per FFT length, chosen by\n"
+                "// paper_2511_03343_amd/autotune.py (written by that script; do not edit by hand).\n"
+                "#pragma once\n\n"
+                "namespace ssp {\n"
+                "// kTunedVariant[log2(P) - 7] for P = 128 ... 32768\n"
+                f"constexpr int kTunedVariant[9] = {{{vals}}};\n"
+                "}  // namespace ssp\n")
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--write", action="store_true", help="write csrc/ssp_tuned.h")
+    ap.add_argument("--steps", type=int, default=12)
+    ap.add_argument("--reps", type=int, default=2)
+    args = ap.parse_args()
+    import torch
+    sys.path.insert(0, ROOT)
+    from paper_2511_03343_amd import ssp
+    assert torch.cuda.is_available(), "the autotuner times kernels on the GPU"
+    choice, report = {}, []
+    for P in LENGTHS:
+        if _engine_threads(P, 1) == _engine_threads(P, 0):
+            choice[P] = 0
+            continue
+        # enough solves for several workgroups per compute unit at every layout
+        batch = 512 if P >= 8192 else 1024
+        t0, f0 = time_layout(ssp, torch, P, 0, batch, args.steps, args.reps)
+        t1, f1 = time_layout(ssp, torch, P, 1, batch, args.steps, args.reps)
+        diff = float(np.linalg.norm(f1 - f0) / np.linalg.norm(f0))
+        assert diff < 1e-5, f"layouts of P={P} disagree beyond rounding ({diff:.2e})"
+        choice[P] = 1 if t1 < t0 else 0
+        row = {"P": P, "nz": P // 2, "batch": batch, "steps": args.steps,
+               "threads": [_engine_threads(P, 0), _engine_threads(P, 1)],
+               "ms": [round(1e3 * t0, 3), round(1e3 * t1, 3)], "chosen": choice[P],
+               "layout_difference_relL2": diff}
+        report.append(row)
+        print(json.dumps(row), flush=True)
+    if args.write:
+        write_header(choice)
+        print(f"wrote {HEADER}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

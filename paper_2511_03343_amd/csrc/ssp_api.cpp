@@ -14,6 +14,7 @@
 #include "ssp_device.h"
 #include "ssp_plan.h"
 #include "ssp_dense.h"
+#include "ssp_tuned.h"
 
 namespace {
 
@@ -54,6 +55,7 @@ struct ssp_plan {
     int N = 0, P = 0, p = 0, nmax = 0;
     double H = 0, f = 0, c0 = 0, dr = 0, tol = 0, k0 = 0, sigma = 0, alpha = 0;
     int out_every = 1, engine = 0;
+    int variant_opt = -1;               // SSP_OPT_VARIANT
     hipStream_t stream = nullptr;
     ssp::PadeSet ps;
     ssp::DeviceTables tab;
@@ -208,6 +210,16 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     return SSP_OK;
 }
 
+// Engine layout of the plan's march: the option if set, else the autotuned choice.
+int effective_variant(const ssp_plan *pl) {
+    if (!ssp::engine_has_variant(pl->P)) return 0;
+    if (pl->variant_opt >= 0) return pl->variant_opt;
+    int lg = 0;
+    while ((1 << lg) < pl->P) ++lg;
+    const int idx = lg - 7;
+    return (idx >= 0 && idx < 9) ? ssp::kTunedVariant[idx] : 0;
+}
+
 ssp::SolveDesc base_desc(const ssp_plan *pl) {
     ssp::SolveDesc d{};
     d.k1 = pl->d_k1;
@@ -236,6 +248,7 @@ ssp::SolveDesc base_desc(const ssp_plan *pl) {
     d.v = pl->d_v;
     for (int i = 0; i < 8; ++i) d.env[i] = pl->env[i];
     d.out_every = pl->out_every;
+    d.variant = effective_variant(pl);
     return d;
 }
 
@@ -467,6 +480,10 @@ ssp_status ssp_plan_set_option(ssp_plan *pl, int key, double value) {
             if (value != 0 && value != 1) return fail(SSP_E_INVAL, "engine must be 0 or 1");
             pl->engine = static_cast<int>(value);
             return SSP_OK;
+        case SSP_OPT_VARIANT:
+            if (value != -1 && value != 0 && value != 1) return fail(SSP_E_INVAL, "variant must be -1, 0 or 1");
+            pl->variant_opt = static_cast<int>(value);
+            return SSP_OK;
         default:
             return fail(SSP_E_INVAL, "unknown option key");
     }
@@ -666,8 +683,14 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
     // dispatched first
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
+    // (the family: lengths of the 1024-thread kernel in their default layout)
+    auto fam = [](const ssp::SolveDesc &d) { return ssp::march_family_member(d.P) && d.variant == 0; };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        return descs[x].P != descs[y].P ? descs[x].P > descs[y].P : descs[x].nsteps > descs[y].nsteps;
+        const ssp::SolveDesc &a = descs[x], &b = descs[y];
+        if (fam(a) != fam(b)) return fam(a);
+        if (a.P != b.P) return a.P > b.P;
+        if (a.variant != b.variant) return a.variant < b.variant;
+        return a.nsteps > b.nsteps;
     });
     std::vector<ssp::SolveDesc> sorted(n);
     for (int i = 0; i < n; ++i) sorted[i] = descs[order[i]];
@@ -693,13 +716,14 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
             // length; each group's march is followed by its output launches (one per length)
             struct Group { int start, end; bool family; };
             std::vector<Group> groups;
-            int fam = 0;
-            while (fam < n && ssp::march_family_member(sorted[fam].P)) ++fam;
-            if (fam > 0 && sorted[0].P != sorted[fam - 1].P) groups.push_back({0, fam, true});
-            else fam = 0;
-            for (int start = fam; start < n;) {
+            int nf = 0;
+            while (nf < n && fam(sorted[nf])) ++nf;
+            if (nf > 0 && sorted[0].P != sorted[nf - 1].P) groups.push_back({0, nf, true});
+            else nf = 0;
+            for (int start = nf; start < n;) {
                 int end = start;
-                while (end < n && sorted[end].P == sorted[start].P) ++end;
+                while (end < n && sorted[end].P == sorted[start].P && sorted[end].variant == sorted[start].variant)
+                    ++end;
                 groups.push_back({start, end, false});
                 start = end;
             }
@@ -719,7 +743,8 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
                 if (G.family)
                     HIP_TRY(ssp::launch_march_family(owner->d_descs + G.start, G.end - G.start, gmax, gs));
                 else
-                    HIP_TRY(ssp::launch_march(sorted[G.start].P, owner->d_descs + G.start, G.end - G.start, gmax, gs));
+                    HIP_TRY(ssp::launch_march(sorted[G.start].P, sorted[G.start].variant, owner->d_descs + G.start,
+                                              G.end - G.start, gmax, gs));
                 for (int start = G.start; start < G.end;) {
                     int end = start;
                     while (end < G.end && sorted[end].P == sorted[start].P) ++end;
@@ -845,7 +870,7 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
         // record the launches once; the descriptors above stay valid for later replays
         drop_graph(pl);
         HIP_TRY(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = ssp::launch_march(pl->P, pl->d_descs, B, nsteps, pl->stream);
+        hipError_t e = ssp::launch_march(pl->P, effective_variant(pl), pl->d_descs, B, nsteps, pl->stream);
         if (e == hipSuccess && d_tl && nout > 0) e = ssp::launch_output(pl->P, pl->d_descs, B, nout, pl->stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(pl->stream, &g);
@@ -858,7 +883,7 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
         pl->graph_key = key;
         HIP_TRY(hipGraphLaunch(pl->graph_exec, pl->stream));
     } else {
-        HIP_TRY(ssp::launch_march(pl->P, pl->d_descs, B, nsteps, pl->stream));
+        HIP_TRY(ssp::launch_march(pl->P, effective_variant(pl), pl->d_descs, B, nsteps, pl->stream));
         if (d_tl && nout > 0) HIP_TRY(ssp::launch_output(pl->P, pl->d_descs, B, nout, pl->stream));
     }
     pl->step_index += nsteps;

@@ -51,6 +51,7 @@ struct SolveDesc {
     int out_every;
     int nout;                   // output rows available in snap / tl_out / fld_out
     int nsteps;                 // range steps of this solve in the launch
+    int variant;                // engine layout of the march (host-side grouping only)
 };
 
 // Launch the fused persistent march: one workgroup per descriptor, all with the same FFT
@@ -65,11 +66,17 @@ inline void set_work(SolveDesc &d, float2 *base) {
     d.xs = base + 3 * static_cast<size_t>(d.N);
 }
 
-hipError_t launch_march(int P, const SolveDesc *d_descs, int nsolves, int nsteps,
+hipError_t launch_march(int P, int variant, const SolveDesc *d_descs, int nsolves, int nsteps,
                         hipStream_t stream);
 
+// Engine layouts of the march kernel: variant 0 is the default; variant 1 (where it exists)
+// uses another thread count, i.e. another radix for the first and last FFT passes.  Results
+// of the two differ in rounding only.
+bool engine_has_variant(int P);
+int engine_threads(int P, int variant);
+
 // One launch for solves of different FFT lengths, all members of the 1024-thread family
-// (march_family_member): each workgroup runs the code of its own descriptor's P.
+// (march_family_member, variant 0): each workgroup runs the code of its own descriptor's P.
 bool march_family_member(int P);
 hipError_t launch_march_family(const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream);
 

@@ -194,9 +194,24 @@ __device__ __forceinline__ int opaque_tid() {
 // Every padded index of a pass is a per-thread base plus a compile-time offset (the
 // offsets that are added are multiples of 16, or keep within one 16-block), so exchanges
 // cost no index arithmetic beyond one base per pass.
-template <int P>
+// Engine configurations.  A template argument K names one: the FFT length (low bits) and a
+// variant (high bits) that selects the thread count, i.e. the radix of the first and last
+// passes (elements per thread).  Variant 0 is the default layout; variant 1 exists where a
+// second layout fits the register and LDS budgets, and the autotuner picks per length.
+constexpr int kVarShift = 20;
+constexpr int key_len(int K) { return K & ((1 << kVarShift) - 1); }
+constexpr int key_var(int K) { return K >> kVarShift; }
+constexpr int threads_v0(int P) { return P <= 512 ? 64 : (P == 1024 ? 128 : (P <= 4096 ? 256 : 1024)); }
+constexpr int threads_v1(int P) {
+    return P == 1024 ? 64 : (P == 2048 ? 128 : (P == 4096 ? 512 : (P == 8192 ? 512 : threads_v0(P))));
+}
+constexpr int threads_for(int P, int V) { return V ? threads_v1(P) : threads_v0(P); }
+constexpr bool has_variant(int P) { return threads_v1(P) != threads_v0(P); }
+
+template <int K>
 struct Cfg {
-    static constexpr int T = P <= 512 ? 64 : (P == 1024 ? 128 : (P <= 4096 ? 256 : 1024));
+    static constexpr int P = key_len(K);
+    static constexpr int T = threads_for(P, key_var(K));
     static constexpr int RT = P / T;
     static constexpr int PADSH = 4;
     static constexpr int DLEN = P + (P >> PADSH);
@@ -281,7 +296,7 @@ __device__ __forceinline__ void init_mid_table(float4 *t4, const uint32_t *tab) 
     if constexpr (Ns < Cfg<P>::T) {
         constexpr int R = mid_radix<P, Ns>();
         constexpr int OFF = mid_tab_offset<P, Ns>();
-        constexpr int STRIDE = P / (Ns * R);
+        constexpr int STRIDE = Cfg<P>::P / (Ns * R);
         for (int idx = threadIdx.x; idx < Ns * (R - 1); idx += Cfg<P>::T) {
             const int r = idx / Ns + 1, k = idx & (Ns - 1);
             float2 h;
@@ -335,7 +350,7 @@ __device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBuf
     if constexpr (Ns < T) {
         constexpr int R = mid_radix<P, Ns>();
         constexpr int PER = RT / R;
-        constexpr int NB = P / R;
+        constexpr int NB = Cfg<P>::P / R;
         constexpr int OFF = mid_tab_offset<P, Ns>();
         // constant-offset addressing applies when every added offset keeps the padding
         // count exact (see the engine notes); otherwise the index is padded per access
@@ -460,27 +475,32 @@ __device__ __forceinline__ void chirp_core(float2 (&x)[Cfg<P>::RT], const LdsBuf
     fft<P, true, F + 1>(x, L, tw);
 }
 
-// Largest FFT held by one workgroup, and the engine length of a convolution length P.
+// Largest FFT held by one workgroup, and the engine (length and variant) of a convolution
+// length P.
 constexpr int kMaxEngine = 16384;
 template <int P>
 constexpr int eng_len() { return P > kMaxEngine ? P / 2 : P; }
-template <int P>
-using ECfg = Cfg<eng_len<P>()>;
+template <int P, int V>
+constexpr int eng_key() {
+    return eng_len<P>() | ((V && has_variant(eng_len<P>()) ? 1 : 0) << kVarShift);
+}
+template <int P, int V>
+using ECfg = Cfg<eng_key<P, V>()>;
 
 // One DST core for convolution length P (positions 0 .. eng_len-1 distributed as in the
 // engine).  For P above kMaxEngine the odd-frequency half needs the input again after the
 // even half has overwritten x: KEEP_GLOBAL keeps it (and the even result) in the solve's
 // scratch keep[0 .. 2N), else in registers.  Both give identical results.  Positions >= N
 // of the result are zero.
-template <int P, bool KEEP_GLOBAL>
-__device__ __forceinline__ void dst_core(float2 (&x)[ECfg<P>::RT], const LdsBufs &L,
-                                         const Twiddles<eng_len<P>()> &tw, const SolveDesc &d,
-                                         float2 *keep) {
+template <int P, int V, bool KEEP_GLOBAL, int EKEY = eng_key<P, V>()>
+__device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBufs &L,
+                                         const Twiddles<EKEY> &tw, const SolveDesc &d, float2 *keep) {
     constexpr int H = eng_len<P>();
+    constexpr int EK = eng_key<P, V>();
     if constexpr (H == P) {
-        chirp_core<P, false>(x, L, tw, d.k1, d.k2);
+        chirp_core<EK, false>(x, L, tw, d.k1, d.k2);
     } else {
-        constexpr int T = Cfg<H>::T, RT = Cfg<H>::RT;
+        constexpr int T = Cfg<EK>::T, RT = Cfg<EK>::RT;
         const int N = d.N;
         float2 y[KEEP_GLOBAL ? 1 : RT];
         // odd-frequency input y = x (.) w_P^n
@@ -495,7 +515,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[ECfg<P>::RT], const LdsBufs
                 y[i] = v;
             }
         }
-        chirp_core<H, false>(x, L, tw, d.k1, d.k2);
+        chirp_core<EK, false>(x, L, tw, d.k1, d.k2);
         if constexpr (KEEP_GLOBAL) {
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
@@ -503,7 +523,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[ECfg<P>::RT], const LdsBufs
                 if (pos < N) st2(keep + N, pos, x[i]);
                 x[i] = pos < N ? ld2(keep, pos) : make_float2(0.f, 0.f);
             }
-            chirp_core<H, true>(x, L, tw, d.k1 + H, d.k2 + H);
+            chirp_core<EK, true>(x, L, tw, d.k1 + H, d.k2 + H);
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T;
@@ -511,7 +531,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[ECfg<P>::RT], const LdsBufs
                                : make_float2(0.f, 0.f);
             }
         } else {
-            chirp_core<H, true>(y, L, tw, d.k1 + H, d.k2 + H);
+            chirp_core<EK, true>(y, L, tw, d.k1 + H, d.k2 + H);
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T;
@@ -613,9 +633,9 @@ __device__ __forceinline__ float eddy_correction(const SolveDesc &d, float vm, f
 
 // A = v (.) dmod at the thread's positions (zero at positions >= N); v of global step n.
 // Written to registers (A) when the kernel keeps it there, else to the solve's pot array.
-template <int P, bool IN_REGS>
+template <int P, int V, bool IN_REGS>
 __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, float2 *A) {
-    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
+    constexpr int T = ECfg<P, V>::T, RT = ECfg<P, V>::RT;
     const int N = d.N;
     long long row = 0;
     if (d.prof_mode == PROF_TABLE_STEPS) {
@@ -642,9 +662,10 @@ __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, 
 
 // ----------------------------------------------------------------------------- march
 // One workgroup marches one solve through nsteps range steps.
-template <int P>
+template <int P, int V>
 __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float4 *lds_raw, double *red) {
-    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
+    constexpr int T = ECfg<P, V>::T, RT = ECfg<P, V>::RT;
+    constexpr int EK = eng_key<P, V>();
     // the Neumann multiplier stays in registers for up to 8 elements per thread
     constexpr bool kBInRegs = (RT <= 8) && (T < 1024);
     constexpr int EB = kBInRegs ? RT : 1;
@@ -657,11 +678,11 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     constexpr int EW = kWInRegs ? RT : 1;
     // split transforms keep their second input in the solve's scratch (fewer spills)
     constexpr bool kKeepGlobal = true;
-    const LdsBufs L = carve_lds<eng_len<P>()>(lds_raw);
+    const LdsBufs L = carve_lds<EK>(lds_raw);
     const int tid = threadIdx.x;
     const int N = d.N, p = d.p, nmax = d.nmax;
-    Twiddles<eng_len<P>()> tw;
-    init_twiddles<eng_len<P>()>(tw, L.tw4, d.tw);
+    Twiddles<EK> tw;
+    init_twiddles<EK>(tw, L.tw4, d.tw);
 
     // The state u is not held in registers: d.field holds the state at the start of the
     // step (the recovery point if the step diverges) and d.work the state between Pade
@@ -672,7 +693,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     long long n = *d.step;
     // outputs of this launch: steps out_base, out_base + out_every, ... (row = slot)
     const long long out_base = d.out_every > 0 ? (n / d.out_every + 1) * d.out_every : 0;
-    if (d.prof_mode == PROF_TABLE_FIXED) load_potential<P, kAInRegs>(d, n + 1, A);
+    if (d.prof_mode == PROF_TABLE_FIXED) load_potential<P, V, kAInRegs>(d, n + 1, A);
 
     long long terms = 0, done = 0;
     int max_used = 0, notconv = 0, status = kOK;
@@ -680,7 +701,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
 
     for (int s = 0; s < nsteps; ++s) {
         const long long nn = n + 1;
-        if (d.prof_mode != PROF_TABLE_FIXED) load_potential<P, kAInRegs>(d, nn, A);
+        if (d.prof_mode != PROF_TABLE_FIXED) load_potential<P, V, kAInRegs>(d, nn, A);
         bool bad = false;
         for (int j = 0; j < p; ++j) {
             const float2 *cur = (j == 0) ? d.field : d.work;
@@ -709,7 +730,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
             // half-iteration h: even -> a = A (.) S a (multiply by v); odd -> a = B_j (.) S a
             // (diagonal solve) and the term is accumulated; one transform site per loop
             for (int h = 0; h < 2 * nmax; ++h) {
-                dst_core<P, kKeepGlobal>(a, L, tw, d, d.xs);
+                dst_core<P, V, kKeepGlobal>(a, L, tw, d, d.xs);
                 if ((h & 1) == 0) {
 #pragma unroll
                     for (int i = 0; i < RT; ++i) {
@@ -822,42 +843,43 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
 
 // One solve per workgroup (descriptor blockIdx.x, its own step count), all with
 // convolution length P.  The launch argument is the largest step count.
-template <int P>
-__global__ __launch_bounds__(ECfg<P>::T) void k_march(const SolveDesc *__restrict__ descs, int nsteps) {
-    __shared__ float4 lds_raw[lds_words<eng_len<P>()>()];
-    __shared__ double red[2 * (ECfg<P>::T / 64)];
-    march_body<P>(descs[blockIdx.x], descs[blockIdx.x].nsteps, lds_raw, red);
+template <int P, int V>
+__global__ __launch_bounds__((ECfg<P, V>::T)) void k_march(const SolveDesc *__restrict__ descs, int nsteps) {
+    __shared__ float4 lds_raw[lds_words<eng_key<P, V>()>()];
+    __shared__ double red[2 * (ECfg<P, V>::T / 64)];
+    march_body<P, V>(descs[blockIdx.x], descs[blockIdx.x].nsteps, lds_raw, red);
 }
 
 // Solves of uneven length in one launch: every length that runs with 1024-thread workgroups
 // (P = 8192, 16384, 32768); each workgroup takes the code path of its own descriptor's P.
 constexpr int kFamilyT = 1024;
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int kFamilyLds = cmax(lds_words<8192>(), lds_words<16384>());
-static_assert(Cfg<8192>::T == kFamilyT && Cfg<16384>::T == kFamilyT, "family thread count");
+constexpr int kFamilyLds = cmax(lds_words<eng_key<8192, 0>()>(), lds_words<eng_key<16384, 0>()>());
+static_assert(ECfg<8192, 0>::T == kFamilyT && ECfg<16384, 0>::T == kFamilyT &&
+              ECfg<32768, 0>::T == kFamilyT, "family thread count");
 __global__ __launch_bounds__(kFamilyT) void k_march_family(const SolveDesc *__restrict__ descs, int nsteps) {
     __shared__ float4 lds_raw[kFamilyLds];
     __shared__ double red[2 * (kFamilyT / 64)];
     const SolveDesc &d = descs[blockIdx.x];
     switch (d.P) {  // uniform over the workgroup
-        case 8192: march_body<8192>(d, d.nsteps, lds_raw, red); break;
-        case 16384: march_body<16384>(d, d.nsteps, lds_raw, red); break;
-        case 32768: march_body<32768>(d, d.nsteps, lds_raw, red); break;
+        case 8192: march_body<8192, 0>(d, d.nsteps, lds_raw, red); break;
+        case 16384: march_body<16384, 0>(d, d.nsteps, lds_raw, red); break;
+        case 32768: march_body<32768, 0>(d, d.nsteps, lds_raw, red); break;
         default: break;
     }
 }
 
 // ----------------------------------------------------------------------------- transforms
 template <int P>
-__global__ __launch_bounds__(ECfg<P>::T) void k_transform(const SolveDesc *__restrict__ desc, int mode,
+__global__ __launch_bounds__((ECfg<P, 0>::T)) void k_transform(const SolveDesc *__restrict__ desc, int mode,
                                                          const float2 *__restrict__ in, float2 *out,
                                                          const long long *__restrict__ step) {
-    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
-    SSP_LDS_DECL(eng_len<P>());
+    constexpr int T = ECfg<P, 0>::T, RT = ECfg<P, 0>::RT;
+    SSP_LDS_DECL((eng_key<P, 0>()));
     const SolveDesc &d = *desc;
     const int N = d.N;
-    Twiddles<eng_len<P>()> tw;
-    init_twiddles<eng_len<P>()>(tw, L.tw4, d.tw);
+    Twiddles<eng_key<P, 0>()> tw;
+    init_twiddles<eng_key<P, 0>()>(tw, L.tw4, d.tw);
     const float2 *vin = in + static_cast<size_t>(blockIdx.x) * N;
     float2 *vout = out + static_cast<size_t>(blockIdx.x) * N;
     float2 x[RT];
@@ -871,7 +893,7 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_transform(const SolveDesc *__res
         }
         x[i] = v;
     }
-    dst_core<P, false>(x, L, tw, d, nullptr);
+    dst_core<P, 0, false>(x, L, tw, d, nullptr);
     float2 car = make_float2(1.f, 0.f);
     if (mode == 2) car = carrier(d.sigma, step[blockIdx.x]);
 #pragma unroll
@@ -889,15 +911,15 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_transform(const SolveDesc *__res
 // with the carrier of its step -> field row (complex64, in place over the snapshot when
 // fld_out == snap) and TL row.
 template <int P>
-__global__ __launch_bounds__(ECfg<P>::T) void k_output(const SolveDesc *__restrict__ descs, int nout) {
-    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
-    SSP_LDS_DECL(eng_len<P>());
+__global__ __launch_bounds__((ECfg<P, 0>::T)) void k_output(const SolveDesc *__restrict__ descs, int nout) {
+    constexpr int T = ECfg<P, 0>::T, RT = ECfg<P, 0>::RT;
+    SSP_LDS_DECL((eng_key<P, 0>()));
     const int b = blockIdx.x / nout, row = blockIdx.x % nout;
     const SolveDesc &d = descs[b];
     if (row >= d.nout || !d.snap || !d.stats || d.out_every <= 0) return;  // uniform
     const int N = d.N, tid = threadIdx.x;
-    Twiddles<eng_len<P>()> tw;
-    init_twiddles<eng_len<P>()>(tw, L.tw4, d.tw);
+    Twiddles<eng_key<P, 0>()> tw;
+    init_twiddles<eng_key<P, 0>()>(tw, L.tw4, d.tw);
     // the march that wrote the snapshots started at step step_index - steps_done
     const long long n0 = d.stats->step_index - d.stats->steps_done;
     const long long n = (n0 / d.out_every + 1) * d.out_every + static_cast<long long>(row) * d.out_every;
@@ -909,7 +931,7 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_output(const SolveDesc *__restri
         const int pos = tid + i * T;
         x[i] = (pos < N) ? ld2(src, pos) : make_float2(0.f, 0.f);
     }
-    dst_core<P, false>(x, L, tw, d, nullptr);
+    dst_core<P, 0, false>(x, L, tw, d, nullptr);
     const float2 car = carrier(d.sigma, n);
     const float lr = log10f(static_cast<float>(static_cast<double>(n) * d.dr));
 #pragma unroll
@@ -935,9 +957,9 @@ struct PlainState {
 };
 
 template <int P>
-__global__ __launch_bounds__(ECfg<P>::T) void k_plain_start(const SolveDesc *__restrict__ desc, float2 *a, float2 *w,
+__global__ __launch_bounds__((ECfg<P, 0>::T)) void k_plain_start(const SolveDesc *__restrict__ desc, float2 *a, float2 *w,
                                                              PlainState *ps, int j) {
-    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
+    constexpr int T = ECfg<P, 0>::T, RT = ECfg<P, 0>::RT;
     __shared__ double red[2 * (T / 64)];
     const SolveDesc &d = *desc;
     if (ps->halt) return;
@@ -967,15 +989,15 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_plain_start(const SolveDesc *__r
 }
 
 template <int P>
-__global__ __launch_bounds__(ECfg<P>::T) void k_plain_half(const SolveDesc *__restrict__ desc, float2 *a, float2 *w,
+__global__ __launch_bounds__((ECfg<P, 0>::T)) void k_plain_half(const SolveDesc *__restrict__ desc, float2 *a, float2 *w,
                                                             PlainState *ps, int j, int h, long long n) {
-    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
-    SSP_LDS_DECL(eng_len<P>());
+    constexpr int T = ECfg<P, 0>::T, RT = ECfg<P, 0>::RT;
+    SSP_LDS_DECL((eng_key<P, 0>()));
     __shared__ double red[2 * (T / 64)];
     const SolveDesc &d = *desc;
     if (ps->halt || ps->done) return;  // uniform: the series has stopped
-    Twiddles<eng_len<P>()> tw;
-    init_twiddles<eng_len<P>()>(tw, L.tw4, d.tw);
+    Twiddles<eng_key<P, 0>()> tw;
+    init_twiddles<eng_key<P, 0>()>(tw, L.tw4, d.tw);
     const int N = d.N;
     float2 x[RT];
 #pragma unroll
@@ -983,10 +1005,10 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_plain_half(const SolveDesc *__re
         const int pos = opaque_tid() + i * T;
         x[i] = (pos < N) ? ld2(a, pos) : make_float2(0.f, 0.f);
     }
-    dst_core<P, false>(x, L, tw, d, nullptr);
+    dst_core<P, 0, false>(x, L, tw, d, nullptr);
     if ((h & 1) == 0) {
         float2 A[RT];
-        load_potential<P, true>(d, n, A);
+        load_potential<P, 0, true>(d, n, A);
 #pragma unroll
         for (int i = 0; i < RT; ++i) {
             const int pos = opaque_tid() + i * T;
@@ -1024,9 +1046,9 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_plain_half(const SolveDesc *__re
 
 // End of a Pade factor: statistics, divergence test, product-form combine into d.work.
 template <int P>
-__global__ __launch_bounds__(ECfg<P>::T) void k_plain_finish(const SolveDesc *__restrict__ desc, const float2 *w,
+__global__ __launch_bounds__((ECfg<P, 0>::T)) void k_plain_finish(const SolveDesc *__restrict__ desc, const float2 *w,
                                                               PlainState *ps, int j) {
-    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
+    constexpr int T = ECfg<P, 0>::T, RT = ECfg<P, 0>::RT;
     const SolveDesc &d = *desc;
     if (ps->halt) return;
     const bool conv = ps->done && !ps->bad;
@@ -1061,8 +1083,8 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_plain_finish(const SolveDesc *__
 
 // End of a step: commit, counters, output snapshot.
 template <int P>
-__global__ __launch_bounds__(ECfg<P>::T) void k_plain_commit(const SolveDesc *__restrict__ desc, PlainState *ps) {
-    constexpr int T = ECfg<P>::T, RT = ECfg<P>::RT;
+__global__ __launch_bounds__((ECfg<P, 0>::T)) void k_plain_commit(const SolveDesc *__restrict__ desc, PlainState *ps) {
+    constexpr int T = ECfg<P, 0>::T, RT = ECfg<P, 0>::RT;
     const SolveDesc &d = *desc;
     if (ps->halt) return;
     const int N = d.N;
@@ -1091,7 +1113,7 @@ __global__ __launch_bounds__(ECfg<P>::T) void k_plain_commit(const SolveDesc *__
 template <int P>
 hipError_t plain_march_P(const SolveDesc &hd, const SolveDesc *dd, int nsteps, float2 *work,
                          void *state, hipStream_t stream) {
-    constexpr int T = ECfg<P>::T;
+    constexpr int T = ECfg<P, 0>::T;
     float2 *a = work, *w = work + hd.N;
     PlainState *ps = static_cast<PlainState *>(state);
     long long n0 = 0;
@@ -1115,26 +1137,42 @@ hipError_t plain_march_P(const SolveDesc &hd, const SolveDesc *dd, int nsteps, f
 
 template <int P>
 hipError_t launch_output_P(const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream) {
-    hipLaunchKernelGGL((k_output<P>), dim3(nsolves * nout), dim3(ECfg<P>::T), 0, stream, d_descs, nout);
+    hipLaunchKernelGGL((k_output<P>), dim3(nsolves * nout), dim3(ECfg<P, 0>::T), 0, stream, d_descs, nout);
     return hipGetLastError();
 }
 
-template <int P>
+template <int P, int V>
 hipError_t launch_march_P(const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
-    hipLaunchKernelGGL((k_march<P>), dim3(nsolves), dim3(ECfg<P>::T), 0, stream, d_descs, nsteps);
+    hipLaunchKernelGGL((k_march<P, V>), dim3(nsolves), dim3(ECfg<P, V>::T), 0, stream, d_descs, nsteps);
     return hipGetLastError();
+}
+
+// variant 1 only where it differs from variant 0 (no duplicate instantiations)
+template <int P>
+hipError_t launch_march_PV(bool v1, const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
+    if constexpr (has_variant(eng_len<P>())) {
+        if (v1) return launch_march_P<P, 1>(d_descs, nsolves, nsteps, stream);
+    }
+    return launch_march_P<P, 0>(d_descs, nsolves, nsteps, stream);
 }
 
 template <int P>
 hipError_t launch_transform_P(int mode, const SolveDesc *d_desc, int B, const float2 *in,
                               float2 *out, const long long *step, hipStream_t stream) {
-    hipLaunchKernelGGL((k_transform<P>), dim3(B), dim3(ECfg<P>::T), 0, stream, d_desc, mode, in, out, step);
+    hipLaunchKernelGGL((k_transform<P>), dim3(B), dim3(ECfg<P, 0>::T), 0, stream, d_desc, mode, in, out, step);
     return hipGetLastError();
 }
 
 }  // namespace
 
 bool march_family_member(int P) { return P == 8192 || P == 16384 || P == 32768; }
+
+bool engine_has_variant(int P) { return has_variant(P > kMaxEngine ? P / 2 : P); }
+
+int engine_threads(int P, int variant) {
+    const int PE = P > kMaxEngine ? P / 2 : P;
+    return threads_for(PE, variant != 0 && has_variant(PE) ? 1 : 0);
+}
 
 hipError_t launch_march_family(const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
     if (nsolves <= 0 || nsteps <= 0) return hipSuccess;
@@ -1161,9 +1199,11 @@ bool fft_length_supported(int P) {
         default: return hipErrorInvalidValue; \
     }
 
-hipError_t launch_march(int P, const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
+hipError_t launch_march(int P, int variant, const SolveDesc *d_descs, int nsolves, int nsteps,
+                        hipStream_t stream) {
     if (nsolves <= 0 || nsteps <= 0) return hipSuccess;
-#define CALL_M(PP) launch_march_P<PP>(d_descs, nsolves, nsteps, stream)
+    const bool v1 = variant != 0 && engine_has_variant(P);
+#define CALL_M(PP) launch_march_PV<PP>(v1, d_descs, nsolves, nsteps, stream)
     SSP_DISPATCH_P(P, CALL_M)
 #undef CALL_M
 }

@@ -30,6 +30,7 @@ SSP_OPT_OUT_EVERY = 2
 SSP_OPT_STREAM = 3
 SSP_OPT_ENGINE = 4
 SSP_OPT_GRAPH = 5
+SSP_OPT_VARIANT = 6
 
 
 class ssp_stats(C.Structure):

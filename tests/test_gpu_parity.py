@@ -388,12 +388,30 @@ def test_plain_form_equals_fused_bitwise(ssp, gpu, nz, env):
         pl = make_plan(ssp, s, profile="analytic" if env != "munk" else "table")
         try:
             ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_ENGINE, engine)
+            ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, 0)  # the plain kernels' layout
             out.append(ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps))
         finally:
             ssp.ssp_plan_destroy(pl)
     (st0, f0, t0, s0), (st1, f1, t1, s1) = out
     assert st0 == st1 and s0 == s1
     assert np.array_equal(f0, f1) and np.array_equal(t0, t1)
+
+
+# both engine layouts of the lengths that have two (FFT lengths 1024 ... 8192)
+@pytest.mark.parametrize("nz", [511, 1000, 2047, 4096])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_engine_layouts_vs_oracle(ssp, gpu, nz, variant):
+    s = W.munk_deep(nsteps=16, nz=nz)
+    s.out_every = 4
+    pl = make_plan(ssp, s)
+    try:
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, variant)
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert st == ref.status == OK
+    compare(f"layout {variant} nz={nz}", fld, tl, ref)
 
 
 def test_plain_form_reports_divergence(ssp, gpu):
