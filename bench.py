@@ -37,6 +37,33 @@ import workloads as W  # noqa: E402
 PEAK_FP32 = 157.3e12   # MI355X published FP32 vector peak (FLOP/s)
 PEAK_HBM = 8.0e12      # MI355X HBM3E (B/s)
 
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc passes (FETCH_SIZE,
+# WRITE_SIZE) of `bench.py --steps 100 --warmup 10 --roof-launches 2 --copy-calibration 1024`,
+# each scaled by the counter's reading for a plain 1 GiB device copy in the same run
+# (FETCH_SIZE reads 0.5x the bytes moved, WRITE_SIZE 1.0x).  Keyed by the workload's launch
+# shape and a fingerprint of the kernel sources and layout table: any change to them makes
+# the figure stale, and it is then reported as null.
+TRAFFIC = {
+    ("munk4096", 512, 100): {"fingerprint": "c504238869213089", "fetch": 1199649734.0,
+                             "write": 11166548432.0},
+}
+
+
+def source_fingerprint():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ssp_device.hip", "ssp_device.h", "ssp_tuned.h"):
+        with open(os.path.join(ROOT, "paper_2511_03343_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, batch, chunk):
+    t = TRAFFIC.get((workload, batch, chunk))
+    if t is None or t["fingerprint"] != source_fingerprint():
+        return None
+    return t["fetch"] + t["write"]
+
 
 def algorithmic_flops(nz, pade_order, terms, steps, outputs):
     """Algorithmic FP32 work of the range step: every Neumann term costs two DSTs
@@ -161,6 +188,7 @@ def run_device_batch(args, ssp, torch, stream, dev):
     pl = make_plan(ssp, s)
     ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
     ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_GRAPH, 1 if args.graph else 0)
+    layout, threads, P = ssp.ssp_plan_engine(pl)
 
     zs = W.source_depths(B, 50.0, 2000.0)
     psi = np.stack([W.gaussian_starter(s.nz, s.depth, s.freq, s.c0, z) for z in zs])
@@ -210,8 +238,10 @@ def run_device_batch(args, ssp, torch, stream, dev):
     stats = _stats(d_stats)
     ssp.ssp_plan_destroy(pl)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
-            "kernel": f"k_march<{_fft_len(s.nz)}>",
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+            "traffic": measured_traffic(args.workload, B, args.chunk),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": f"k_march<{P}, {layout}> ({threads} threads per workgroup)",
             "avg_launch_ms": 1e3 * sum(launch_s) / len(launch_s),
             "steps_per_launch": args.chunk,
             "neumann_terms_per_solve_step": stats["terms"] / B / args.chunk}

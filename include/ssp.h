@@ -120,6 +120,10 @@ ssp_status ssp_plan_info(const ssp_plan *plan, double *sigma, double *k0, double
                          double *g, double *C, double *d0, double *d);
 int ssp_max_nz(void);
 
+/* Engine of the plan's fused march: layout actually used (0 or 1, see SSP_OPT_VARIANT),
+ * threads per workgroup and the chirp-z FFT length P (either pointer may be NULL). */
+ssp_status ssp_plan_engine(const ssp_plan *plan, int *variant, int *threads, int *fft_length);
+
 /* Host-only Pade coefficients (Sec. 2; Alg. 1 first step) for sigma = k0 dr, order p and
  * rotation alpha, in the library's factor order: b[2p], g[2p] (product-form weights
  * g_j = a_j/b_j), C[2], d0[2], d[2p] as (re, im) pairs; any output may be NULL.  Touches no

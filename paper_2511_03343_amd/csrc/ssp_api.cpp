@@ -325,6 +325,15 @@ const char *ssp_last_error(void) { return g_last_error.c_str(); }
 
 int ssp_max_nz(void) { return kMaxP / 2; }
 
+ssp_status ssp_plan_engine(const ssp_plan *pl, int *variant, int *threads, int *fft_length) {
+    if (!pl) return fail(SSP_E_INVAL, "plan is NULL");
+    const int v = effective_variant(pl);
+    if (variant) *variant = v;
+    if (threads) *threads = ssp::engine_threads(pl->P, v);
+    if (fft_length) *fft_length = pl->P;
+    return SSP_OK;
+}
+
 ssp_status ssp_pade_coefficients(double sigma, int pade_order, double alpha, double *b, double *g,
                                  double *C, double *d0, double *d) {
     if (!std::isfinite(sigma) || !(sigma > 0) || !std::isfinite(alpha))

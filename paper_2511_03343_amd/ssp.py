@@ -83,6 +83,7 @@ def lib() -> C.CDLL:
             "ssp_plan_set_stream": (S, [_VP, _VP]),
             "ssp_plan_info": (S, [_VP, _DP, _DP, _DP, _DP, _DP, _DP, _DP]),
             "ssp_max_nz": (C.c_int, []),
+            "ssp_plan_engine": (S, [_VP, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
             "ssp_pade_coefficients": (S, [C.c_double, C.c_int, C.c_double, _DP, _DP, _DP, _DP, _DP]),
             "ssp_set_profile": (S, [_VP, C.c_int, C.c_int, _DP]),
             "ssp_set_profile_analytic": (S, [_VP, C.POINTER(ssp_env)]),
@@ -155,6 +156,13 @@ def ssp_plan_set_stream(plan, stream_ptr):
 
 def ssp_max_nz():
     return lib().ssp_max_nz()
+
+
+def ssp_plan_engine(plan):
+    """(layout, threads per workgroup, FFT length) of the plan's fused march."""
+    v, t, p = C.c_int(), C.c_int(), C.c_int()
+    _check(lib().ssp_plan_engine(plan, C.byref(v), C.byref(t), C.byref(p)))
+    return v.value, t.value, p.value
 
 
 def ssp_pade_coefficients(sigma, pade_order, alpha=0.0):
