@@ -77,6 +77,8 @@ def _solve(workload, nz=None, nsteps=None, zs=None, index=None):
     """The Solve of one job of a workload (index: frequency index of the broadband set)."""
     if workload == "munk4096":
         s = W.munk_deep(nz=nz or 4096)
+    elif workload == "homogeneous":
+        s = W.homogeneous_waveguide()
     elif workload == "eddy16384":
         s = W.munk_eddy(nz=nz or 16384)
     elif workload == "serving":
@@ -95,7 +97,8 @@ def _oracle_worker(args):
     import scipy.fft  # noqa: F401
     from oracle import Plan
     s = _solve(workload, nz, nsteps, zs, index)
-    pl = Plan(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol)
+    pl = Plan(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol,
+              rotation=s.rotation)
     t = time.perf_counter()
     pl.march(s.starter(), nsteps, s.profile(), out_every=s.out_every)
     return s.nz * nsteps, time.perf_counter() - t
@@ -119,9 +122,10 @@ def cpu_baseline(workload, nz, seconds_target=20.0):
         jobs = [(w, n, steps, z, i) for (w, n, _, z, i) in jobs]
         what = f"{len(jobs)} of the 256 frequencies (every {256 // cores}th) x {steps} range steps"
     else:
-        upd, dt = _oracle_worker((workload, nz, 1, 1000.0, None))
+        lo, hi = (20.0, 180.0) if workload == "homogeneous" else (50.0, 2000.0)
+        upd, dt = _oracle_worker((workload, nz, 1, 0.5 * (lo + hi), None))
         steps = max(1, int(seconds_target / max(dt, 1e-3)))
-        zs = W.source_depths(cores, 50.0, 2000.0)
+        zs = W.source_depths(cores, lo, hi)
         jobs = [(workload, nz, steps, float(z), None) for z in zs]
         what = f"{cores} solves x {steps} range steps of the Nz={nz} {workload} workload"
     t = time.perf_counter()
@@ -135,11 +139,14 @@ def cpu_baseline(workload, nz, seconds_target=20.0):
 
 DEFAULTS = {  # batch, timed steps, warmup steps, steps per launch
     "munk4096": (512, 400, 20, 100),
+    "homogeneous": (1024, 1000, 20, 200),
     "eddy16384": (256, 100, 10, 50),
     "broadband": (256, 200, 40, 200),
     "serving": (1024, 0, 0, 50),
 }
 DESCRIPTIONS = {
+    "homogeneous": "homogeneous Dirichlet waveguide, H=200 m, c=1500 m/s, 100 Hz, Nz=256, rotated [4/4] "
+                   "Pade (alpha=pi/16), dr=5 m, V=0 (no Neumann terms), TL every 10 steps",
     "munk4096": "deep Munk waveguide, Nz=4096, [6/6] Pade, dr=25 m, 50 Hz, Neumann tol 1e-10 "
                 "(cap 48), TL every 4 steps",
     "eddy16384": "Munk + Gaussian eddy, Nz=16384, [8/8] Pade, dr=20 m, 200 Hz, Neumann tol 1e-10 "
@@ -154,6 +161,8 @@ DESCRIPTIONS = {
 
 def make_plan(ssp, s):
     pl = ssp.ssp_plan_create(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol)
+    if s.rotation:
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_ROTATION, s.rotation)
     ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_OUT_EVERY, s.out_every)
     if s.env == "munk+eddy":
         e = s.eddy or W.Eddy()
@@ -190,7 +199,8 @@ def run_device_batch(args, ssp, torch, stream, dev):
     ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_GRAPH, 1 if args.graph else 0)
     layout, threads, P = ssp.ssp_plan_engine(pl)
 
-    zs = W.source_depths(B, 50.0, 2000.0)
+    zs = (W.source_depths(B, 20.0, 180.0) if args.workload == "homogeneous"
+          else W.source_depths(B, 50.0, 2000.0))
     psi = np.stack([W.gaussian_starter(s.nz, s.depth, s.freq, s.c0, z) for z in zs])
     d_psi = torch.from_numpy(psi.astype(np.complex64)).to(dev)
     d_step = torch.zeros(B, dtype=torch.int64, device=dev)

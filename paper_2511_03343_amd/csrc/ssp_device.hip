@@ -169,6 +169,48 @@ struct Dft<1, INV> {
     __device__ __forceinline__ static void run(float2 *) {}
 };
 
+// DFT of x[0..R) whose upper half x[R/2..R) is zero (never read): decimation in frequency,
+// X_{2k} = DFT_{R/2}(x)_k and X_{2k+1} = DFT_{R/2}(x_i w_R^i)_k, natural order out.
+template <int R, bool INV>
+struct DftHalfIn {
+    __device__ __forceinline__ static void run(float2 *x) {
+        float2 e[R / 2], o[R / 2];
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) {
+            e[i] = x[i];
+            o[i] = mulw<R, INV>(x[i], i);
+        }
+        Dft<R / 2, INV>::run(e);
+        Dft<R / 2, INV>::run(o);
+#pragma unroll
+        for (int k = 0; k < R / 2; ++k) {
+            x[2 * k] = e[k];
+            x[2 * k + 1] = o[k];
+        }
+    }
+};
+
+// DFT of x[0..R) of which only X[0..R/2) is needed (the upper half is set to zero):
+// decimation in time without the subtraction half of the last stage.
+template <int R, bool INV>
+struct DftHalfOut {
+    __device__ __forceinline__ static void run(float2 *x) {
+        float2 e[R / 2], o[R / 2];
+#pragma unroll
+        for (int k = 0; k < R / 2; ++k) {
+            e[k] = x[2 * k];
+            o[k] = x[2 * k + 1];
+        }
+        Dft<R / 2, INV>::run(e);
+        Dft<R / 2, INV>::run(o);
+#pragma unroll
+        for (int k = 0; k < R / 2; ++k) {
+            x[k] = cadd(e[k], mulw<R, INV>(o[k], k));
+            x[k + R / 2] = make_float2(0.f, 0.f);
+        }
+    }
+};
+
 // Thread index laundered through an empty asm: index arithmetic derived from it is
 // recomputed where it is used instead of being hoisted out of the range-step loops, which
 // would keep dozens of loop-invariant addresses alive in vector registers.
@@ -402,13 +444,15 @@ __device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBuf
 }
 
 // Full FFT of the distributed vector x (registers in, registers out); its first exchange
-// uses phase PH.
-template <int P, bool INV, int PH>
+// uses phase PH.  HALF_IN: positions >= P/2 of the input are zero (the thread's upper half);
+// HALF_OUT: only positions < P/2 of the output are needed (the upper half is returned zero).
+template <int P, bool INV, int PH, bool HALF_IN = false, bool HALF_OUT = false>
 __device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, const Twiddles<P> &tw) {
     constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
     const int tid = opaque_tid();
     // first pass: Ns = 1, butterfly j = t on positions t + r T
-    Dft<RT, INV>::run(x);
+    if constexpr (HALF_IN && RT >= 2) DftHalfIn<RT, INV>::run(x);
+    else Dft<RT, INV>::run(x);
     before_write<P>();
     {
         // tid RT + r stays within one 16-block of the padded index (RT <= 16)
@@ -426,7 +470,8 @@ __device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, c
 #pragma unroll
         for (int r = 1; r < RT; ++r)
             x[r] = twmul<INV>(x[r], tw.h[r - 1], tw.l[r - 1]);
-        Dft<RT, INV>::run(x);
+        if constexpr (HALF_OUT && RT >= 2) DftHalfOut<RT, INV>::run(x);
+        else Dft<RT, INV>::run(x);
     }
 }
 
@@ -465,14 +510,16 @@ __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const Lds
 // The chirp-z core of one DST on P positions: x <- IFFT(comb(FFT(x))) (unnormalised), x
 // distributed by position; positions >= N must hold zeros on entry.  Phases 0 .. 2F
 // (F = passes - 1); the opening barrier separates them from the previous core's last reads.
-template <int P, bool ODD>
+// HALF: the vector length N is at most P/2 (every unsplit length), so the input's upper
+// half is zero and the output's upper half is not needed; it is returned zero.
+template <int P, bool ODD, bool HALF = false>
 __device__ __forceinline__ void chirp_core(float2 (&x)[Cfg<P>::RT], const LdsBufs &L,
                                            const Twiddles<P> &tw, const float2 *k1, const float2 *k2) {
     constexpr int F = fft_phases<P>();
     __syncthreads();
-    fft<P, false, 0>(x, L, tw);
+    fft<P, false, 0, HALF, false>(x, L, tw);
     chirp_combine<P, F, ODD>(x, L, k1, k2);
-    fft<P, true, F + 1>(x, L, tw);
+    fft<P, true, F + 1, false, HALF>(x, L, tw);
 }
 
 // Largest FFT held by one workgroup, and the engine (length and variant) of a convolution
@@ -487,18 +534,24 @@ constexpr int eng_key() {
 template <int P, int V>
 using ECfg = Cfg<eng_key<P, V>()>;
 
+// Elements i of a thread that can hold data of a vector of length N <= P/2: all for split
+// lengths, the lower half otherwise (positions t + i T >= P/2 are always beyond N).
+template <int P, int V>
+constexpr int live_elems() { return eng_len<P>() == P ? ECfg<P, V>::RT / 2 : ECfg<P, V>::RT; }
+
 // One DST core for convolution length P (positions 0 .. eng_len-1 distributed as in the
 // engine).  For P above kMaxEngine the odd-frequency half needs the input again after the
 // even half has overwritten x: KEEP_GLOBAL keeps it (and the even result) in the solve's
 // scratch keep[0 .. 2N), else in registers.  Both give identical results.  Positions >= N
-// of the result are zero.
+// of the input must be zero.  Output: split lengths return zero at positions >= N; unsplit
+// lengths return zero at positions >= P/2 and values without meaning in [N, P/2).
 template <int P, int V, bool KEEP_GLOBAL, int EKEY = eng_key<P, V>()>
 __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBufs &L,
                                          const Twiddles<EKEY> &tw, const SolveDesc &d, float2 *keep) {
     constexpr int H = eng_len<P>();
     constexpr int EK = eng_key<P, V>();
     if constexpr (H == P) {
-        chirp_core<EK, false>(x, L, tw, d.k1, d.k2);
+        chirp_core<EK, false, true>(x, L, tw, d.k1, d.k2);
     } else {
         constexpr int T = Cfg<EK>::T, RT = Cfg<EK>::RT;
         const int N = d.N;
@@ -635,7 +688,7 @@ __device__ __forceinline__ float eddy_correction(const SolveDesc &d, float vm, f
 // Written to registers (A) when the kernel keeps it there, else to the solve's pot array.
 template <int P, int V, bool IN_REGS>
 __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, float2 *A) {
-    constexpr int T = ECfg<P, V>::T, RT = ECfg<P, V>::RT;
+    constexpr int T = ECfg<P, V>::T, RL = live_elems<P, V>();
     const int N = d.N;
     long long row = 0;
     if (d.prof_mode == PROF_TABLE_STEPS) {
@@ -645,7 +698,7 @@ __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, 
     const float *vrow = d.v + row * N;
     const float r = static_cast<float>((static_cast<double>(n) - 0.5) * d.dr);
 #pragma unroll
-    for (int i = 0; i < RT; ++i) {
+    for (int i = 0; i < RL; ++i) {
         const int pos = opaque_tid() + i * T, m = pos;
         float2 val = make_float2(0.f, 0.f);
         if (pos < N) {
@@ -666,16 +719,18 @@ template <int P, int V>
 __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float4 *lds_raw, double *red) {
     constexpr int T = ECfg<P, V>::T, RT = ECfg<P, V>::RT;
     constexpr int EK = eng_key<P, V>();
+    // elements that can hold data (the lower half for unsplit lengths); the others stay zero
+    constexpr int RL = live_elems<P, V>();
     // the Neumann multiplier stays in registers for up to 8 elements per thread
     constexpr bool kBInRegs = (RT <= 8) && (T < 1024);
-    constexpr int EB = kBInRegs ? RT : 1;
+    constexpr int EB = kBInRegs ? RL : 1;
     // ... and so does the potential A = v (.) dmod; otherwise both come from L2
     constexpr bool kAInRegs = kBInRegs;
-    constexpr int EA = kAInRegs ? RT : 1;
+    constexpr int EA = kAInRegs ? RL : 1;
     // the series sum w_j stays in registers up to 8 elements per thread or below 1024
     // threads (else in d.wacc)
     constexpr bool kWInRegs = T < 1024 || RT <= 8;
-    constexpr int EW = kWInRegs ? RT : 1;
+    constexpr int EW = kWInRegs ? RL : 1;
     // split transforms keep their second input in the solve's scratch (fewer spills)
     constexpr bool kKeepGlobal = true;
     const LdsBufs L = carve_lds<EK>(lds_raw);
@@ -709,7 +764,9 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
             // in FP64
             float t0f = 0.f;
 #pragma unroll
-            for (int i = 0; i < RT; ++i) {
+            for (int i = RL; i < RT; ++i) a[i] = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int i = 0; i < RL; ++i) {
                 const int pos = opaque_tid() + i * T, m = pos;
                 if (pos < N) {
                     a[i] = cmul_df(ld2(cur, m), ld4(d.s, j * N + m));
@@ -733,7 +790,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                 dst_core<P, V, kKeepGlobal>(a, L, tw, d, d.xs);
                 if ((h & 1) == 0) {
 #pragma unroll
-                    for (int i = 0; i < RT; ++i) {
+                    for (int i = 0; i < RL; ++i) {
                         if constexpr (kAInRegs) {
                             a[i] = cmul(A[i], a[i]);
                         } else {
@@ -745,7 +802,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                 }
                 float tnf = 0.f, wnf = 0.f;
 #pragma unroll
-                for (int i = 0; i < RT; ++i) {
+                for (int i = 0; i < RL; ++i) {
                     const int pos = opaque_tid() + i * T;
                     float4 bm;
                     if constexpr (kBInRegs) bm = Bm[i];
@@ -792,7 +849,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
             // product-form factor: u <- g_j u + (1 - g_j) w_j  (alpha, beta double-float)
             const float4 al = ld4(d.alpha, j), be = ld4(d.beta, j);
 #pragma unroll
-            for (int i = 0; i < RT; ++i) {
+            for (int i = 0; i < RL; ++i) {
                 const int pos = opaque_tid() + i * T, m = pos;
                 if (pos < N) {
                     const float2 ws = kWInRegs ? w[i] : ld2(d.wacc, m);
@@ -806,7 +863,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
         }
         // commit the step
 #pragma unroll
-        for (int i = 0; i < RT; ++i) {
+        for (int i = 0; i < RL; ++i) {
             const int pos = opaque_tid() + i * T, m = pos;
             if (pos < N) st2(d.field, m, ld2(d.work, m));
         }
@@ -818,7 +875,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
             const long long slot = (n - out_base) / d.out_every;
             if (n >= out_base && slot < d.nout) {
 #pragma unroll
-                for (int i = 0; i < RT; ++i) {
+                for (int i = 0; i < RL; ++i) {
                     const int pos = opaque_tid() + i * T, m = pos;
                     if (pos < N) st2(d.snap + slot * N, m, ld2(d.field, m));
                 }
