@@ -12,7 +12,8 @@
 //
 // Kernels: k_dense_split (one workgroup per vector: scales and fp16 planes of its two
 // columns) and k_dense_gemm (128 x 128 output tile per workgroup, 4 waves of 64 x 64, K in
-// chunks of 32 through LDS, epilogue staged through LDS so that stores are coalesced).
+// chunks of 32 through double-buffered LDS (one barrier per chunk), epilogue staged through
+// LDS so that stores are coalesced).
 #include "ssp_dense.h"
 
 namespace ssp {
@@ -96,7 +97,7 @@ struct alignas(16) GemmLds {
         struct {
             _Float16 ah[kTile][kLdsRow], al[kTile][kLdsRow];  // S rows x K chunk
             _Float16 bh[kTile][kLdsRow], bl[kTile][kLdsRow];  // X columns x K chunk
-        } op;
+        } op[2];                                              // double buffer
         float out[kTile][kTile + 1];                          // result tile [column][row]
     };
 };
@@ -137,31 +138,40 @@ __global__ __launch_bounds__(kThreads) void k_dense_gemm(const _Float16 *__restr
         pb[1][0] = *reinterpret_cast<const half8 *>(xl + static_cast<size_t>(colrow(ra)) * kpad + k0 + ka);
         pb[1][1] = *reinterpret_cast<const half8 *>(xl + static_cast<size_t>(colrow(rb)) * kpad + k0 + kb);
     };
+    auto store = [&](int buf) {
+        auto &o = L.op[buf];
+        *reinterpret_cast<half8 *>(&o.ah[ra][ka]) = pa[0][0];
+        *reinterpret_cast<half8 *>(&o.ah[rb][kb]) = pa[0][1];
+        *reinterpret_cast<half8 *>(&o.al[ra][ka]) = pa[1][0];
+        *reinterpret_cast<half8 *>(&o.al[rb][kb]) = pa[1][1];
+        *reinterpret_cast<half8 *>(&o.bh[ra][ka]) = pb[0][0];
+        *reinterpret_cast<half8 *>(&o.bh[rb][kb]) = pb[0][1];
+        *reinterpret_cast<half8 *>(&o.bl[ra][ka]) = pb[1][0];
+        *reinterpret_cast<half8 *>(&o.bl[rb][kb]) = pb[1][1];
+    };
+    // double-buffered K loop: chunk k is read from buffer k mod 2 while chunk k+1 goes from
+    // registers (loaded during chunk k's products) into the other buffer; one barrier per
+    // chunk separates the two
     fetch(0);
-    for (int k0 = 0; k0 < kpad; k0 += kKc) {
-        __syncthreads();  // previous chunk fully read
-        *reinterpret_cast<half8 *>(&L.op.ah[ra][ka]) = pa[0][0];
-        *reinterpret_cast<half8 *>(&L.op.ah[rb][kb]) = pa[0][1];
-        *reinterpret_cast<half8 *>(&L.op.al[ra][ka]) = pa[1][0];
-        *reinterpret_cast<half8 *>(&L.op.al[rb][kb]) = pa[1][1];
-        *reinterpret_cast<half8 *>(&L.op.bh[ra][ka]) = pb[0][0];
-        *reinterpret_cast<half8 *>(&L.op.bh[rb][kb]) = pb[0][1];
-        *reinterpret_cast<half8 *>(&L.op.bl[ra][ka]) = pb[1][0];
-        *reinterpret_cast<half8 *>(&L.op.bl[rb][kb]) = pb[1][1];
-        __syncthreads();
-        if (k0 + kKc < kpad) fetch(k0 + kKc);
+    store(0);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < kpad; k0 += kKc, cur ^= 1) {
+        const bool more = k0 + kKc < kpad;
+        if (more) fetch(k0 + kKc);
+        const auto &o = L.op[cur];
         // MFMA operands: row (column) = lane mod 16, 8 consecutive k from 8 (lane / 16)
         const int rr = lane & 15, kk = (lane >> 4) * 8;
         half8 bh[4], bl[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            bh[j] = *reinterpret_cast<const half8 *>(&L.op.bh[wn * 64 + j * 16 + rr][kk]);
-            bl[j] = *reinterpret_cast<const half8 *>(&L.op.bl[wn * 64 + j * 16 + rr][kk]);
+            bh[j] = *reinterpret_cast<const half8 *>(&o.bh[wn * 64 + j * 16 + rr][kk]);
+            bl[j] = *reinterpret_cast<const half8 *>(&o.bl[wn * 64 + j * 16 + rr][kk]);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const half8 ah = *reinterpret_cast<const half8 *>(&L.op.ah[wm * 64 + i * 16 + rr][kk]);
-            const half8 al = *reinterpret_cast<const half8 *>(&L.op.al[wm * 64 + i * 16 + rr][kk]);
+            const half8 ah = *reinterpret_cast<const half8 *>(&o.ah[wm * 64 + i * 16 + rr][kk]);
+            const half8 al = *reinterpret_cast<const half8 *>(&o.al[wm * 64 + i * 16 + rr][kk]);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[j], acc[i][j], 0, 0, 0);
@@ -169,8 +179,10 @@ __global__ __launch_bounds__(kThreads) void k_dense_gemm(const _Float16 *__restr
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[j], acc[i][j], 0, 0, 0);
             }
         }
+        if (more) store(cur ^ 1);
+        __syncthreads();
     }
-    __syncthreads();  // operand tiles no longer read: the LDS becomes the result tile
+    // (the loop's last barrier: operand tiles no longer read, the LDS becomes the result tile)
     // accumulator layout: lane holds rows 4 (lane / 16) + q of column lane mod 16
 #pragma unroll
     for (int i = 0; i < 4; ++i)
