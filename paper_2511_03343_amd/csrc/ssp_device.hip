@@ -231,11 +231,11 @@ __device__ __forceinline__ int opaque_tid() {
 // Because T is a multiple of every middle stride Ns, a thread's k is t mod Ns in every
 // pass, so its twiddles are the same in every transform of a launch: they are computed
 // once per launch and held in registers (double-float: FP32 value + bf16 pair remainder).
-// LDS: padded index lp(i) = i + i/16 (one slot per 16 elements, spreads power-of-two strides
-// over the banks); two data buffers when they fit (one barrier per exchange), else one.
-// Every padded index of a pass is a per-thread base plus a compile-time offset (the
-// offsets that are added are multiples of 16, or keep within one 16-block), so exchanges
-// cost no index arithmetic beyond one base per pass.
+// LDS: each exchange has its own padding (see lps); two data buffers when they fit (one
+// barrier per exchange), else one.  Every padded index of a pass is a per-thread base plus
+// a compile-time offset (the offsets that are added are multiples of the padding period,
+// or keep within one period), so exchanges cost no index arithmetic beyond one base per
+// pass.
 // Engine configurations.  A template argument K names one: the FFT length (low bits) and a
 // variant (high bits) that selects the thread count, i.e. the radix of the first and last
 // passes (elements per thread).  Variant 0 is the default layout; variant 1 exists where a
@@ -255,17 +255,23 @@ struct Cfg {
     static constexpr int P = key_len(K);
     static constexpr int T = threads_for(P, key_var(K));
     static constexpr int RT = P / T;
-    static constexpr int PADSH = 4;
-    static constexpr int DLEN = P + (P >> PADSH);
+    static constexpr int DLEN = P + (P >> 4);  // room for the densest padding (1 per 16)
     static constexpr int O = P / 8;
     static constexpr int LOG2O = __builtin_ctz(P / 8);
     static constexpr bool PINGPONG = (2 * DLEN * 8 + 16 * T + 1024) <= 160 * 1024;
 };
 
-template <int P>
-__device__ __forceinline__ int lp(int i) { return i + (i >> Cfg<P>::PADSH); }
-// the same at compile time
-constexpr int lpc(int i) { return i + (i >> 4); }
+// Padded LDS index with one slot per 2^SH elements (SH = 0: none), and the same at compile
+// time.  Each exchange (a pass's writes and the next pass's reads) has its own padding,
+// chosen by the writer so that both access patterns spread over the 64 banks: the first
+// pass writes RT consecutive elements per thread (one slot per 32), a middle pass at stride
+// Ns < 16 writes R-strided groups (one per 16); later middle passes and the combine write
+// unit-stride runs, which padding would only shift across the bank boundary (none).
+template <int SH>
+__device__ __forceinline__ int lps(int i) { return SH ? i + (i >> SH) : i; }
+constexpr int lpcs(int SH, int v) { return SH ? v + (v >> SH) : v; }
+constexpr int kShFirst = 5;
+constexpr int mid_shift(int Ns) { return Ns < 16 ? 4 : 0; }
 
 // radix of the middle pass at stride Ns
 template <int P, int Ns>
@@ -384,8 +390,9 @@ __device__ __forceinline__ void before_write() {
     if constexpr (!Cfg<P>::PINGPONG) __syncthreads();
 }
 
-// middle passes: read phase PH, write phase PH + 1; Ns = current stride until it reaches T
-template <int P, bool INV, int Ns, int PH>
+// middle passes: read phase PH (padding SHR), write phase PH + 1 (padding mid_shift(Ns));
+// Ns = current stride until it reaches T
+template <int P, bool INV, int Ns, int PH, int SHR>
 __device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBufs &L,
                                            const Twiddles<P> &tw) {
     constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
@@ -394,24 +401,27 @@ __device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBuf
         constexpr int PER = RT / R;
         constexpr int NB = Cfg<P>::P / R;
         constexpr int OFF = mid_tab_offset<P, Ns>();
+        constexpr int SHW = mid_shift(Ns);
+        constexpr int QR = 1 << SHR, QW = 1 << SHW;
         // constant-offset addressing applies when every added offset keeps the padding
         // count exact (see the engine notes); otherwise the index is padded per access
-        constexpr bool FAST = (T % 16 == 0) && (NB % 16 == 0) &&
-                              ((Ns % 16 == 0) || (16 % Ns == 0 && (Ns * R) % 16 == 0));
+        constexpr bool FAST_R = SHR == 0 || ((T % QR == 0) && (NB % QR == 0));
+        constexpr bool FAST_W = SHW == 0 || (((T * R) % QW == 0) &&
+                                             ((Ns % QW == 0) || (QW % Ns == 0 && (Ns * R) % QW == 0)));
         const int tid = opaque_tid();
         const float2 *in = phase_buf<P, PH>(L);
-        if constexpr (FAST) {
-            const float2 *rb = in + lp<P>(tid);
+        if constexpr (FAST_R) {
+            const float2 *rb = in + lps<SHR>(tid);
 #pragma unroll
             for (int i = 0; i < PER; ++i)
 #pragma unroll
-                for (int r = 0; r < R; ++r) x[i * R + r] = rb[i * lpc(T) + r * lpc(NB)];
+                for (int r = 0; r < R; ++r) x[i * R + r] = rb[i * lpcs(SHR, T) + r * lpcs(SHR, NB)];
         } else {
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
                 const int j = tid + i * T;
 #pragma unroll
-                for (int r = 0; r < R; ++r) x[i * R + r] = in[lp<P>(j + r * NB)];
+                for (int r = 0; r < R; ++r) x[i * R + r] = in[lps<SHR>(j + r * NB)];
             }
         }
         before_write<P>();
@@ -419,7 +429,7 @@ __device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBuf
         const int t2 = opaque_tid();
         const int k = t2 & (Ns - 1);  // T is a multiple of Ns: the same k for every i
         const float4 *wt = L.tw4 + OFF + k;
-        float2 *wb = out + lp<P>((t2 - k) * R + k);
+        float2 *wb = out + lps<SHW>((t2 - k) * R + k);
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             float2 *v = &x[i * R];
@@ -429,17 +439,28 @@ __device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBuf
                 v[r] = INV ? cmul_df_conj(v[r], w) : cmul_df(v[r], w);
             }
             Dft<R, INV>::run(v);
-            if constexpr (FAST) {
+            if constexpr (FAST_W) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) wb[i * lpc(T * R) + lpc(r * Ns)] = v[r];
+                for (int r = 0; r < R; ++r) wb[i * lpcs(SHW, T * R) + lpcs(SHW, r * Ns)] = v[r];
             } else {
                 const int base = (t2 + i * T - k) * R + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) out[lp<P>(base + r * Ns)] = v[r];
+                for (int r = 0; r < R; ++r) out[lps<SHW>(base + r * Ns)] = v[r];
             }
         }
         __syncthreads();
-        mid_passes<P, INV, Ns * R, PH + 1>(x, L, tw);
+        mid_passes<P, INV, Ns * R, PH + 1, SHW>(x, L, tw);
+    }
+}
+
+// padding of the exchange the last pass reads (written by the last middle pass, or by the
+// first pass when there is none)
+template <int P, int Ns, int SH>
+constexpr int last_shift_from() {
+    if constexpr (Ns >= Cfg<P>::T) {
+        return SH;
+    } else {
+        return last_shift_from<P, Ns * mid_radix<P, Ns>(), mid_shift(Ns)>();
     }
 }
 
@@ -455,18 +476,20 @@ __device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, c
     else Dft<RT, INV>::run(x);
     before_write<P>();
     {
-        // tid RT + r stays within one 16-block of the padded index (RT <= 16)
-        float2 *out = phase_buf<P, PH>(L) + lp<P>(tid * RT);
+        // tid RT + r stays within one 32-block of the padded index (RT divides 32)
+        static_assert(32 % RT == 0, "first-pass radix must divide 32");
+        float2 *out = phase_buf<P, PH>(L) + lps<kShFirst>(tid * RT);
 #pragma unroll
         for (int r = 0; r < RT; ++r) out[r] = x[r];
     }
     __syncthreads();
-    mid_passes<P, INV, RT, PH>(x, L, tw);
+    mid_passes<P, INV, RT, PH, kShFirst>(x, L, tw);
     // last pass: Ns = T, butterfly j = t, twiddles w_P^{r t}, outputs at t + r T
     {
-        const float2 *in = phase_buf<P, PH + fft_phases<P>() - 1>(L) + lp<P>(opaque_tid());
+        constexpr int SHL = last_shift_from<P, RT, kShFirst>();
+        const float2 *in = phase_buf<P, PH + fft_phases<P>() - 1>(L) + lps<SHL>(opaque_tid());
 #pragma unroll
-        for (int r = 0; r < RT; ++r) x[r] = in[r * lpc(T)];
+        for (int r = 0; r < RT; ++r) x[r] = in[r * lpcs(SHL, T)];
 #pragma unroll
         for (int r = 1; r < RT; ++r)
             x[r] = twmul<INV>(x[r], tw.h[r - 1], tw.l[r - 1]);
@@ -485,10 +508,11 @@ __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const Lds
     const int tid = opaque_tid();
     before_write<P>();
     float2 *buf = phase_buf<P, PH>(L);
+    // unit-stride exchange: no padding
     {
-        float2 *wb = buf + lp<P>(tid);
+        float2 *wb = buf + tid;
 #pragma unroll
-        for (int i = 0; i < RT; ++i) wb[i * lpc(T)] = x[i];
+        for (int i = 0; i < RT; ++i) wb[i * T] = x[i];
     }
     __syncthreads();
     const int t2 = opaque_tid();
@@ -497,12 +521,12 @@ __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const Lds
     // odd: P - 1 - q = (T - 1 - t2) + (RT - 1 - i) T
     const int u = ODD ? (T - 1 - t2) : ((T - t2) & (T - 1));
     const int c = ODD ? 0 : (t2 == 0 ? 1 : 0);
-    const float2 *rb = buf + lp<P>(u) + c * lpc(T);
+    const float2 *rb = buf + u + c * T;
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
         float2 yr;
-        if (!ODD && i == 0) yr = c ? buf[0] : rb[(RT - 1) * lpc(T)];
-        else yr = rb[(RT - 1 - i) * lpc(T)];
+        if (!ODD && i == 0) yr = c ? buf[0] : rb[(RT - 1) * T];
+        else yr = rb[(RT - 1 - i) * T];
         x[i] = csub(cmul(x[i], ld2s(k1, t2, i * T)), cmul(yr, ld2s(k2, t2, i * T)));
     }
 }
