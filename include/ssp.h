@@ -68,8 +68,8 @@ enum {
                               calls with the same arguments; needs a non-null stream.
                               0 (default): plain launches */
     SSP_OPT_VARIANT = 6    /* engine layout of the fused march kernel: -1 (default) = the
-                              layout the autotuner chose for this FFT length; 0 or 1 = that
-                              layout (1 falls back to 0 where no second layout exists).
+                              layout the autotuner chose for this FFT length; 0, 1 or 2 = that
+                              layout (falls back to 0 where the length has no such layout).
                               Layouts differ in rounding only; a solve's results do not
                               depend on what it is batched with. */
 };

@@ -1,13 +1,14 @@
 """Autotuner for the engine layout of the fused march kernel, per FFT length.
 
-The march kernel of an FFT length P can run in two layouts (SSP_OPT_VARIANT): different
-thread counts, i.e. different elements per thread and radix of the first and last FFT
-passes, with different register / LDS residency (which of the series sum, potential and
-multipliers stay in registers follows from the layout).  For every length with two
-layouts this script marches a full device batch of a representative solve (deep Munk
+The march kernel of an FFT length P can run in up to three layouts (SSP_OPT_VARIANT):
+different thread counts, i.e. different elements per thread and radix of the first and
+last FFT passes, with different register / LDS residency (which of the series sum,
+potential and multipliers stay in registers follows from the layout; layout 2 uses one LDS
+buffer so that two workgroups share a compute unit).  For every length with more than one
+layout this script marches a full device batch of a representative solve (deep Munk
 waveguide at 50 Hz, [6/6], dr = 25 m, Nz = P/2) in each layout, times the launches with
 HIP events on their stream, checks that the layouts agree to rounding, and writes the
-faster one into csrc/ssp_tuned.h.  Rebuild the library afterwards.
+fastest into csrc/ssp_tuned.h.  Rebuild the library afterwards.
 
     python -m paper_2511_03343_amd.autotune [--write]
 
@@ -30,11 +31,12 @@ LENGTHS = [128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768]
 
 
 def _engine_threads(P: int, v: int) -> int:
-    """Thread counts of the two layouts (the same rule as the kernels)."""
+    """Thread counts of the layouts (the same rule as the kernels)."""
     PE = P // 2 if P > 16384 else P
     t0 = 64 if PE <= 512 else (128 if PE == 1024 else (256 if PE <= 4096 else 1024))
     t1 = {1024: 64, 2048: 128, 4096: 512, 8192: 512}.get(PE, t0)
-    return t1 if v else t0
+    t2 = {4096: 128, 8192: 256}.get(PE, t0)
+    return (t0, t1, t2)[v]
 
 
 def time_layout(ssp, torch, P: int, variant: int, batch: int, steps: int, reps: int):
@@ -96,20 +98,24 @@ def main() -> None:
     assert torch.cuda.is_available(), "the autotuner times kernels on the GPU"
     choice, report = {}, []
     for P in LENGTHS:
-        if _engine_threads(P, 1) == _engine_threads(P, 0):
+        layouts = [v for v in range(3) if v == 0 or _engine_threads(P, v) != _engine_threads(P, 0)]
+        if len(layouts) == 1:
             choice[P] = 0
             continue
         # enough solves for several workgroups per compute unit at every layout
         batch = 512 if P >= 8192 else 1024
-        t0, f0 = time_layout(ssp, torch, P, 0, batch, args.steps, args.reps)
-        t1, f1 = time_layout(ssp, torch, P, 1, batch, args.steps, args.reps)
-        diff = float(np.linalg.norm(f1 - f0) / np.linalg.norm(f0))
-        assert diff < 1e-5, f"layouts of P={P} disagree beyond rounding ({diff:.2e})"
-        choice[P] = 1 if t1 < t0 else 0
-        row = {"P": P, "nz": P // 2, "batch": batch, "steps": args.steps,
-               "threads": [_engine_threads(P, 0), _engine_threads(P, 1)],
-               "ms": [round(1e3 * t0, 3), round(1e3 * t1, 3)], "chosen": choice[P],
-               "layout_difference_relL2": diff}
+        times, fields = [], []
+        for v in layouts:
+            t, f = time_layout(ssp, torch, P, v, batch, args.steps, args.reps)
+            times.append(t)
+            fields.append(f)
+        diffs = [float(np.linalg.norm(f - fields[0]) / np.linalg.norm(fields[0])) for f in fields]
+        assert max(diffs) < 1e-5, f"layouts of P={P} disagree beyond rounding ({max(diffs):.2e})"
+        choice[P] = layouts[int(np.argmin(times))]
+        row = {"P": P, "nz": P // 2, "batch": batch, "steps": args.steps, "layouts": layouts,
+               "threads": [_engine_threads(P, v) for v in layouts],
+               "ms": [round(1e3 * t, 3) for t in times], "chosen": choice[P],
+               "layout_difference_relL2": max(diffs)}
         report.append(row)
         print(json.dumps(row), flush=True)
     if args.write:

@@ -212,12 +212,14 @@ ssp_status build_plan_tables(ssp_plan *pl) {
 
 // Engine layout of the plan's march: the option if set, else the autotuned choice.
 int effective_variant(const ssp_plan *pl) {
-    if (!ssp::engine_has_variant(pl->P)) return 0;
-    if (pl->variant_opt >= 0) return pl->variant_opt;
-    int lg = 0;
-    while ((1 << lg) < pl->P) ++lg;
-    const int idx = lg - 7;
-    return (idx >= 0 && idx < 9) ? ssp::kTunedVariant[idx] : 0;
+    int v = pl->variant_opt;
+    if (v < 0) {
+        int lg = 0;
+        while ((1 << lg) < pl->P) ++lg;
+        const int idx = lg - 7;
+        v = (idx >= 0 && idx < 9) ? ssp::kTunedVariant[idx] : 0;
+    }
+    return ssp::engine_variant_exists(pl->P, v) ? v : 0;
 }
 
 ssp::SolveDesc base_desc(const ssp_plan *pl) {
@@ -490,7 +492,8 @@ ssp_status ssp_plan_set_option(ssp_plan *pl, int key, double value) {
             pl->engine = static_cast<int>(value);
             return SSP_OK;
         case SSP_OPT_VARIANT:
-            if (value != -1 && value != 0 && value != 1) return fail(SSP_E_INVAL, "variant must be -1, 0 or 1");
+            if (value != -1 && value != 0 && value != 1 && value != 2)
+                return fail(SSP_E_INVAL, "variant must be -1, 0, 1 or 2");
             pl->variant_opt = static_cast<int>(value);
             return SSP_OK;
         default:

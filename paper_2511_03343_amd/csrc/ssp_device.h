@@ -69,10 +69,11 @@ inline void set_work(SolveDesc &d, float2 *base) {
 hipError_t launch_march(int P, int variant, const SolveDesc *d_descs, int nsolves, int nsteps,
                         hipStream_t stream);
 
-// Engine layouts of the march kernel: variant 0 is the default; variant 1 (where it exists)
-// uses another thread count, i.e. another radix for the first and last FFT passes.  Results
-// of the two differ in rounding only.
-bool engine_has_variant(int P);
+// Engine layouts of the march kernel: variant 0 is the default; variants 1 and 2 (where they
+// exist) use other thread counts, i.e. other radices for the first and last FFT passes
+// (variant 2 with one LDS buffer, two workgroups per compute unit).  Results differ in
+// rounding only.
+bool engine_variant_exists(int P, int variant);
 int engine_threads(int P, int variant);
 
 // One launch for solves of different FFT lengths, all members of the 1024-thread family

@@ -107,22 +107,27 @@ __device__ __forceinline__ void stf(float *p, int i, float v) {
 }
 
 // ----------------------------------------------------------------------------- radix-R DFT
-// cos(2 pi i/16), i = 0..15
-__device__ constexpr double kCos16[16] = {
-    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
-    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
-    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
-    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+// cos(2 pi i/32), i = 0..31
+__device__ constexpr double kCos32[32] = {
+    1.0, 9.80785280403230449126e-1, 9.23879532511286756128e-1, 8.31469612302545237079e-1,
+    7.07106781186547524401e-1, 5.55570233019602224743e-1, 3.82683432365089771728e-1, 1.95090322016128267848e-1,
+    0.0, -1.95090322016128267848e-1, -3.82683432365089771728e-1, -5.55570233019602224743e-1,
+    -7.07106781186547524401e-1, -8.31469612302545237079e-1, -9.23879532511286756128e-1, -9.80785280403230449126e-1,
+    -1.0, -9.80785280403230449126e-1, -9.23879532511286756128e-1, -8.31469612302545237079e-1,
+    -7.07106781186547524401e-1, -5.55570233019602224743e-1, -3.82683432365089771728e-1, -1.95090322016128267848e-1,
+    0.0, 1.95090322016128267848e-1, 3.82683432365089771728e-1, 5.55570233019602224743e-1,
+    7.07106781186547524401e-1, 8.31469612302545237079e-1, 9.23879532511286756128e-1, 9.80785280403230449126e-1};
 
-// x * exp(-+ 2 pi i k / R) (minus for the forward transform), R <= 16
+// x * exp(-+ 2 pi i k / R) (minus for the forward transform), R <= 32
 template <int R, bool INV>
 __device__ __forceinline__ float2 mulw(float2 x, int k) {
-    const int i16 = (k * (16 / R)) & 15;
-    if (i16 == 0) return x;
-    if (i16 == 8) return make_float2(-x.x, -x.y);
-    if (i16 == 4) return INV ? make_float2(-x.y, x.x) : make_float2(x.y, -x.x);
-    if (i16 == 12) return INV ? make_float2(x.y, -x.x) : make_float2(-x.y, x.x);
-    const double c = kCos16[i16], s = kCos16[(i16 + 12) & 15];
+    static_assert(R <= 32 && 32 % R == 0, "radix must divide 32");
+    const int i32 = (k * (32 / R)) & 31;
+    if (i32 == 0) return x;
+    if (i32 == 16) return make_float2(-x.x, -x.y);
+    if (i32 == 8) return INV ? make_float2(-x.y, x.x) : make_float2(x.y, -x.x);
+    if (i32 == 24) return INV ? make_float2(x.y, -x.x) : make_float2(-x.y, x.x);
+    const double c = kCos32[i32], s = kCos32[(i32 + 24) & 31];
     const float ch = static_cast<float>(c), cl = static_cast<float>(c - static_cast<double>(ch));
     const float sh = static_cast<float>(s), sl = static_cast<float>(s - static_cast<double>(sh));
     // forward: x (c - i s); inverse: x (c + i s)
@@ -247,8 +252,16 @@ constexpr int threads_v0(int P) { return P <= 512 ? 64 : (P == 1024 ? 128 : (P <
 constexpr int threads_v1(int P) {
     return P == 1024 ? 64 : (P == 2048 ? 128 : (P == 4096 ? 512 : (P == 8192 ? 512 : threads_v0(P))));
 }
-constexpr int threads_for(int P, int V) { return V ? threads_v1(P) : threads_v0(P); }
-constexpr bool has_variant(int P) { return threads_v1(P) != threads_v0(P); }
+// variant 2: 32 elements per thread with a single LDS buffer, so that two workgroups share
+// a compute unit and cover each other's barriers
+constexpr int threads_v2(int P) { return P == 4096 ? 128 : (P == 8192 ? 256 : threads_v0(P)); }
+constexpr int threads_for(int P, int V) {
+    return V == 2 ? threads_v2(P) : (V == 1 ? threads_v1(P) : threads_v0(P));
+}
+constexpr bool variant_exists(int P, int V) {
+    return V == 0 || (V == 1 && threads_v1(P) != threads_v0(P)) || (V == 2 && threads_v2(P) != threads_v0(P));
+}
+constexpr bool has_variant(int P) { return variant_exists(P, 1) || variant_exists(P, 2); }
 
 template <int K>
 struct Cfg {
@@ -258,7 +271,9 @@ struct Cfg {
     static constexpr int DLEN = P + (P >> 4);  // room for the densest padding (1 per 16)
     static constexpr int O = P / 8;
     static constexpr int LOG2O = __builtin_ctz(P / 8);
-    static constexpr bool PINGPONG = (2 * DLEN * 8 + 16 * T + 1024) <= 160 * 1024;
+    static constexpr bool SINGLE = key_var(K) == 2;  // one data buffer, two workgroups per CU
+    static constexpr bool PINGPONG = !SINGLE && (2 * DLEN * 8 + 16 * T + 1024) <= 160 * 1024;
+    static constexpr int MINW = SINGLE ? 2 : 1;       // waves per SIMD the kernel must allow
 };
 
 // Padded LDS index with one slot per 2^SH elements (SH = 0: none), and the same at compile
@@ -553,7 +568,7 @@ template <int P>
 constexpr int eng_len() { return P > kMaxEngine ? P / 2 : P; }
 template <int P, int V>
 constexpr int eng_key() {
-    return eng_len<P>() | ((V && has_variant(eng_len<P>()) ? 1 : 0) << kVarShift);
+    return eng_len<P>() | ((variant_exists(eng_len<P>(), V) ? V : 0) << kVarShift);
 }
 template <int P, int V>
 using ECfg = Cfg<eng_key<P, V>()>;
@@ -925,7 +940,8 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
 // One solve per workgroup (descriptor blockIdx.x, its own step count), all with
 // convolution length P.  The launch argument is the largest step count.
 template <int P, int V>
-__global__ __launch_bounds__((ECfg<P, V>::T)) void k_march(const SolveDesc *__restrict__ descs, int nsteps) {
+__global__ __launch_bounds__((ECfg<P, V>::T), (ECfg<P, V>::MINW)) void k_march(const SolveDesc *__restrict__ descs,
+                                                                               int nsteps) {
     __shared__ float4 lds_raw[lds_words<eng_key<P, V>()>()];
     __shared__ double red[2 * (ECfg<P, V>::T / 64)];
     march_body<P, V>(descs[blockIdx.x], descs[blockIdx.x].nsteps, lds_raw, red);
@@ -1228,11 +1244,14 @@ hipError_t launch_march_P(const SolveDesc *d_descs, int nsolves, int nsteps, hip
     return hipGetLastError();
 }
 
-// variant 1 only where it differs from variant 0 (no duplicate instantiations)
+// variants 1 and 2 only where they differ from variant 0 (no duplicate instantiations)
 template <int P>
-hipError_t launch_march_PV(bool v1, const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
-    if constexpr (has_variant(eng_len<P>())) {
-        if (v1) return launch_march_P<P, 1>(d_descs, nsolves, nsteps, stream);
+hipError_t launch_march_PV(int v, const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
+    if constexpr (variant_exists(eng_len<P>(), 1)) {
+        if (v == 1) return launch_march_P<P, 1>(d_descs, nsolves, nsteps, stream);
+    }
+    if constexpr (variant_exists(eng_len<P>(), 2)) {
+        if (v == 2) return launch_march_P<P, 2>(d_descs, nsolves, nsteps, stream);
     }
     return launch_march_P<P, 0>(d_descs, nsolves, nsteps, stream);
 }
@@ -1248,11 +1267,13 @@ hipError_t launch_transform_P(int mode, const SolveDesc *d_desc, int B, const fl
 
 bool march_family_member(int P) { return P == 8192 || P == 16384 || P == 32768; }
 
-bool engine_has_variant(int P) { return has_variant(P > kMaxEngine ? P / 2 : P); }
+bool engine_variant_exists(int P, int variant) {
+    return variant >= 0 && variant <= 2 && variant_exists(P > kMaxEngine ? P / 2 : P, variant);
+}
 
 int engine_threads(int P, int variant) {
     const int PE = P > kMaxEngine ? P / 2 : P;
-    return threads_for(PE, variant != 0 && has_variant(PE) ? 1 : 0);
+    return threads_for(PE, engine_variant_exists(P, variant) ? variant : 0);
 }
 
 hipError_t launch_march_family(const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
@@ -1283,8 +1304,8 @@ bool fft_length_supported(int P) {
 hipError_t launch_march(int P, int variant, const SolveDesc *d_descs, int nsolves, int nsteps,
                         hipStream_t stream) {
     if (nsolves <= 0 || nsteps <= 0) return hipSuccess;
-    const bool v1 = variant != 0 && engine_has_variant(P);
-#define CALL_M(PP) launch_march_PV<PP>(v1, d_descs, nsolves, nsteps, stream)
+    const int v = engine_variant_exists(P, variant) ? variant : 0;
+#define CALL_M(PP) launch_march_PV<PP>(v, d_descs, nsolves, nsteps, stream)
     SSP_DISPATCH_P(P, CALL_M)
 #undef CALL_M
 }

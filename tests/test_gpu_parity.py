@@ -397,9 +397,10 @@ def test_plain_form_equals_fused_bitwise(ssp, gpu, nz, env):
     assert np.array_equal(f0, f1) and np.array_equal(t0, t1)
 
 
-# both engine layouts of the lengths that have two (FFT lengths 1024 ... 8192)
+# every engine layout of the lengths that have several (FFT lengths 1024 ... 8192; a layout
+# a length does not have falls back to layout 0)
 @pytest.mark.parametrize("nz", [511, 1000, 2047, 4096])
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_engine_layouts_vs_oracle(ssp, gpu, nz, variant):
     s = W.munk_deep(nsteps=16, nz=nz)
     s.out_every = 4
