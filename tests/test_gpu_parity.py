@@ -415,6 +415,35 @@ def test_engine_layouts_vs_oracle(ssp, gpu, nz, variant):
     compare(f"layout {variant} nz={nz}", fld, tl, ref)
 
 
+def test_layout_option_and_engine_query(ssp, gpu):
+    # the layout a plan reports: the tuned default, an explicit choice, or layout 0 where the
+    # length has no such layout; invalid values are rejected and leave the plan unchanged
+    pl = ssp.ssp_plan_create(4096, 5000.0, 50.0, 1500.0, 25.0, 6, 48, 1e-10)
+    try:
+        v0, t0, p0 = ssp.ssp_plan_engine(pl)
+        assert p0 == 8192 and v0 in (0, 1, 2)
+        seen = {}
+        for v in (0, 1, 2):
+            ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, v)
+            seen[v] = ssp.ssp_plan_engine(pl)
+        assert seen[0][1] == 1024 and seen[1][1] == 512 and seen[2][1] == 256
+        for bad in (3, -2, 0.5):
+            with pytest.raises(ssp.SspError) as e:
+                ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, bad)
+            assert e.value.status == ssp.SSP_E_INVAL
+        assert ssp.ssp_plan_engine(pl) == seen[2]
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, -1)
+        assert ssp.ssp_plan_engine(pl) == (v0, t0, p0)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    pl = ssp.ssp_plan_create(300, 1000.0, 50.0, 1500.0, 10.0, 2, 0, 1e-10)  # FFT length 1024
+    try:
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, 2)  # no layout 2 at this length
+        assert ssp.ssp_plan_engine(pl)[0] == 0
+    finally:
+        ssp.ssp_plan_destroy(pl)
+
+
 def test_plain_form_reports_divergence(ssp, gpu):
     s = W.munk_deep(nsteps=3, nz=511)
     s.dr = 1.0 / s.k0
