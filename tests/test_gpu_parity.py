@@ -583,3 +583,28 @@ def test_munk_full_size_full_range_vs_stored_oracle(ssp, gpu):
         field = g["field"]
         tl = transmission_loss(g["field"], g["ranges"])
     compare("munk full range", fld, tl, Ref)
+
+
+def test_eddy_full_size_long_range_vs_stored_oracle(ssp, gpu):
+    # Munk + eddy at its full size (Nz = 16384, [8/8], split transforms, potential on the
+    # device) for 3000 steps (60 km, through the eddy core), against the stored FP64 oracle
+    import os
+    from oracle import transmission_loss
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "eddy16384_zs1000.npz"))
+    s = W.munk_eddy(nsteps=int(g["nsteps"]))
+    s.out_every = int(g["out_every"])
+    pl = make_plan(ssp, s, profile="analytic")
+    try:
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    _report("eddy long range", status=st, oracle_status=int(g["status"]),
+            terms=stats["neumann_terms"], oracle_terms=int(np.sum(g["iterations"])),
+            not_converged=stats["not_converged"], oracle_not_converged=int(g["not_converged"]))
+    assert st in (OK, NOT_CONVERGED) and int(g["status"]) in (OK, NOT_CONVERGED)
+    assert stats["steps_done"] == s.nsteps
+
+    class Ref:
+        field = g["field"]
+        tl = transmission_loss(g["field"], g["ranges"])
+    compare("eddy long range", fld, tl, Ref)
