@@ -44,8 +44,8 @@ PEAK_HBM = 8.0e12      # MI355X HBM3E (B/s)
 # shape and a fingerprint of the kernel sources and layout table: any change to them makes
 # the figure stale, and it is then reported as null.
 TRAFFIC = {
-    ("munk4096", 512, 100): {"fingerprint": "c504238869213089", "fetch": 1199649734.0,
-                             "write": 11166548432.0},
+    ("munk4096", 512, 100): {"fingerprint": "a56bee6aa290f14f", "fetch": 719515269.0,
+                             "write": 10674211424.0},
 }
 
 
@@ -92,9 +92,16 @@ def _solve(workload, nz=None, nsteps=None, zs=None, index=None):
     return s
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result is the only line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _oracle_worker(args):
     workload, nz, nsteps, zs, index = args
     import scipy.fft  # noqa: F401
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)   # one thread per solve process: `cores` counts the processes
     from oracle import Plan
     s = _solve(workload, nz, nsteps, zs, index)
     pl = Plan(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol,
@@ -128,6 +135,7 @@ def cpu_baseline(workload, nz, seconds_target=20.0):
         zs = W.source_depths(cores, lo, hi)
         jobs = [(workload, nz, steps, float(z), None) for z in zs]
         what = f"{cores} solves x {steps} range steps of the Nz={nz} {workload} workload"
+    log(f"cpu baseline: {what} on {cores} processes")
     t = time.perf_counter()
     with mp.get_context("spawn").Pool(cores) as pool:
         res = pool.map(_oracle_worker, jobs)
@@ -449,11 +457,15 @@ def main():
         del a, b
 
     runner = {"broadband": run_broadband, "serving": run_serving}.get(args.workload, run_device_batch)
+    log(f"{args.workload}: batch {args.batch}, {args.warmup} warm-up + {args.steps} timed steps")
     updates, wall, roof, config, statuses, plain, nz = runner(args, ssp, torch, stream, dev)
+    log(f"{args.workload}: {updates / wall:.4g} field updates/s")
     value = updates / wall
     timed_steps = args.steps or config.get("ticks") or 1   # serving: a step is one tick
 
     transforms = None if args.no_transforms else transform_rooflines(ssp, torch, stream, dev)
+    if transforms is not None:
+        log("stand-alone transforms measured")
 
     cpu = None
     if not args.no_cpu:
