@@ -9,6 +9,8 @@ the seeded generators in workloads/.
 Modules:
   pade       Pade coefficients in 60-digit arithmetic (Sec. 2; Algorithm 1, first step)
   dst        orthonormal DST-I (Sec. 3.1) and its O(N^2) definition
+  bases      grids, eigenvalues and transforms of the Dirichlet, Neumann and periodic
+             boundary conditions (Sec. 3.1)
   sssp       the range march in sum and product form (Sec. 3, eq. neumannseries, Alg. 1)
   reference  closed-form and brute-force references used to pin the oracle itself
 

@@ -12,6 +12,11 @@ is used by the march; these are independent routes to quantities the march must 
     propagator applied through a symmetric eigendecomposition (numpy.linalg.eigh), for
     tiny grids.  The rational step e^{i sigma} R(X) then needs no series, and the exact
     step exp(i sigma sqrt(1 + X)) is available for the same matrix.
+  * modal_field_bc / dense_operator_bc: the same two references for the Neumann and
+    periodic boundaries of Sec. 3.1.  The modal sum expands the starter by solving the
+    linear system of the sampled eigenfunctions cos(l pi z/H) or e^{2 pi i l z/H} (no
+    transform, no normalisation weights); the dense operator is d_z^2 = Phi diag(-mu)
+    Phi^{-1} from the same sampled eigenfunctions (again no transform).
 """
 from __future__ import annotations
 
@@ -52,9 +57,9 @@ def dense_operator(nz: int, depth: float, k0: float, v: np.ndarray) -> np.ndarra
 
 
 def dense_step(X: np.ndarray, u: np.ndarray, func) -> np.ndarray:
-    """func(X) u through X = Q diag(lam) Q^T."""
+    """func(X) u through X = Q diag(lam) Q^H (X real symmetric or Hermitian)."""
     lam, Q = np.linalg.eigh(X)
-    return Q @ (func(lam) * (Q.T @ u))
+    return Q @ (func(lam) * (Q.conj().T @ u))
 
 
 def dense_term(X: np.ndarray, u: np.ndarray, bj: complex) -> np.ndarray:
@@ -71,3 +76,54 @@ def dense_operator_from_c(nz: int, depth: float, freq: float, c0: float,
     k = 2 * math.pi * freq / np.asarray(c, dtype=np.float64)
     d2 = S @ np.diag(-(np.arange(1, nz + 1) * math.pi / depth) ** 2) @ S
     return (d2 + np.diag(k ** 2 - k0 ** 2)) / k0 ** 2
+
+
+def eigenfunctions(bc: str, z: np.ndarray, depth: float):
+    """Sampled eigenfunctions of d_z^2 under boundary condition bc, as columns, and the
+    squared vertical wavenumbers mu_l (d_z^2 phi_l = -mu_l phi_l)."""
+    nz = len(z)
+    if bc == "dirichlet":
+        ell = np.arange(1, nz + 1)
+        return np.sin(np.outer(z, ell) * math.pi / depth), (ell * math.pi / depth) ** 2
+    if bc == "neumann":
+        ell = np.arange(nz)
+        return np.cos(np.outer(z, ell) * math.pi / depth), (ell * math.pi / depth) ** 2
+    if bc == "periodic":
+        ell = np.arange(nz) - (nz - 1) // 2          # -(Nz-1)/2 .. Nz/2
+        return np.exp(2j * math.pi * np.outer(z, ell) / depth), (2 * math.pi * ell / depth) ** 2
+    raise ValueError(bc)
+
+
+def modal_field_bc(bc: str, psi0: np.ndarray, z: np.ndarray, depth: float, k0: float,
+                   ranges) -> np.ndarray:
+    """Exact one-way modal sum of a homogeneous waveguide with boundary condition bc:
+    u(r, z_n) = sum_l c_l e^{i kappa_l r} phi_l(z_n), kappa_l = sqrt(k0^2 - mu_l)
+    (Im kappa >= 0), the c_l from phi(z_n) c = psi0."""
+    Phi, mu = eigenfunctions(bc, np.asarray(z, dtype=np.float64), depth)
+    coef = np.linalg.solve(Phi.astype(np.complex128), np.asarray(psi0, dtype=np.complex128))
+    kappa = np.sqrt((k0 ** 2 - mu).astype(np.complex128))
+    kappa = np.where(kappa.imag < 0, -kappa, kappa)
+    return np.array([Phi @ (coef * np.exp(1j * kappa * r)) for r in np.atleast_1d(ranges)])
+
+
+def dense_operator_bc(bc: str, z: np.ndarray, depth: float, freq: float, c0: float,
+                      c: np.ndarray) -> np.ndarray:
+    """X = k0^-2 (d_z^2 + k^2 - k0^2) with d_z^2 = Phi diag(-mu) Phi^{-1}, Phi the sampled
+    eigenfunctions of bc on the grid z (a dense, in general non-symmetric matrix)."""
+    Phi, mu = eigenfunctions(bc, np.asarray(z, dtype=np.float64), depth)
+    Phi = Phi.astype(np.complex128)
+    d2 = Phi @ np.diag(-mu) @ np.linalg.inv(Phi)
+    if bc != "periodic":
+        d2 = d2.real
+    k0 = 2 * math.pi * freq / c0
+    k = 2 * math.pi * freq / np.asarray(c, dtype=np.float64)
+    return (d2 + np.diag(k ** 2 - k0 ** 2)) / k0 ** 2
+
+
+def dense_rational(X: np.ndarray, u: np.ndarray, C: complex, a, b) -> np.ndarray:
+    """C prod_j (1 + a_j X)(1 + b_j X)^{-1} u by dense solves (no eigendecomposition)."""
+    out = np.asarray(u, dtype=np.complex128)
+    eye = np.eye(X.shape[0])
+    for aj, bj in zip(a, b):
+        out = (eye + aj * X) @ np.linalg.solve(eye + bj * X, out)
+    return C * out

@@ -11,7 +11,9 @@ Follows the paper's method in its own order and notation:
   * Sec. 3, inverse of the isovelocity operator: L_j is diagonal in the transform basis;
     for Dirichlet boundaries (Sec. 3.1) the basis is the sine basis, where d_z^2 has the
     eigenvalues -(l pi/H)^2, so L_j^{-1} = S diag(1/(1 + b_j x_l)) S with
-    x_l = -(l pi / (H k0))^2 and S the orthonormal DST-I.
+    x_l = -(l pi / (H k0))^2 and S the orthonormal DST-I.  Neumann and periodic
+    boundaries (Sec. 3.1) swap in the cosine and Fourier bases of oracle.bases, with their
+    grids and eigenvalues; everything else is unchanged.
   * Sec. 3, eq. (neumannseries): w_j = sum_{m=0..M} (-b~_j L_j^{-1} delta k^2)^m L_j^{-1} u,
     evaluated term by term, each term from the previous one.
   * Algorithm 1: for every range step, every Pade term's w_j from the series, then
@@ -19,7 +21,8 @@ Follows the paper's method in its own order and notation:
 
 Readings where the paper is silent (each also listed in the design notes):
   * Neumann stopping: the series for a term stops at the first m >= 1 with
-    ||term_m|| <= tol ||w^{(m)}|| (2-norms over depth) or at m = neumann_max; with
+    ||term_m|| <= tol ||w^{(m)}|| (2-norms over depth, in coefficient space: the
+    trapezoidal norm of oracle.bases.weights for the cosine basis) or at m = neumann_max; with
     neumann_max = 0 only the m = 0 term is taken (the isovelocity case of Sec. 4.1).
   * Divergence: a series that reaches neumann_max without meeting tol and whose last
     term is not smaller than its first, or any non-finite value, stops the march.
@@ -39,7 +42,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from .dst import dst
+from . import bases
 from .pade import PadeCoeffs, pade
 
 OK = 0
@@ -64,18 +67,21 @@ class Plan:
 
     def __init__(self, nz: int, depth: float, freq: float, c0: float, dr: float,
                  pade_order: int, neumann_max: int, tol: float, rotation: float = 0.0,
-                 form: str = "product"):
+                 form: str = "product", bc: str = "dirichlet"):
         if nz < 2 or depth <= 0 or freq <= 0 or c0 <= 0 or dr <= 0:
             raise ValueError("invalid plan parameters")
         if form not in ("product", "sum"):
             raise ValueError("form must be 'product' or 'sum'")
+        self.bc = bases.check_bc(bc)
         self.nz, self.depth, self.freq, self.c0, self.dr = nz, depth, freq, c0, dr
         self.neumann_max, self.tol, self.form = int(neumann_max), float(tol), form
         self.k0 = 2.0 * math.pi * freq / c0
         self.sigma = self.k0 * dr
-        self.dz = depth / (nz + 1)
-        ell = np.arange(1, nz + 1, dtype=np.float64)
-        self.x = -(ell * math.pi / (depth * self.k0)) ** 2      # eigenvalues of d_z^2/k0^2
+        self.z = bases.grid(bc, nz, depth)
+        # eigenvalues of d_z^2/k0^2 in the basis of the boundary condition
+        self.x = -(bases.wavenumbers(bc, nz, depth) / self.k0) ** 2
+        # weights of the coefficient-space norm (all 1 except the Neumann boundary points)
+        self.wnorm = bases.weights(bc, nz)
         self.pade: PadeCoeffs = pade(self.sigma, pade_order, rotation)
         self.b = self.pade.b
         self.g = self.pade.a / self.pade.b
@@ -85,21 +91,27 @@ class Plan:
         """v = delta k^2 / k0^2 = (c0/c)^2 - 1 (Sec. 2, X = (delta k^2 + d_z^2)/k0^2)."""
         return (self.c0 / np.asarray(c, dtype=np.float64)) ** 2 - 1.0
 
+    def norm(self, u: np.ndarray) -> float:
+        """2-norm over depth in coefficient space (Parseval): ||u|| for the sine and Fourier
+        bases, the trapezoidal ||e u|| for the cosine basis."""
+        return float(np.linalg.norm(self.wnorm * u))
+
     def l_inverse(self, u: np.ndarray, bj: complex) -> np.ndarray:
-        """L_j^{-1} u = S diag(1/(1 + b_j x)) S u (Sec. 3, isovelocity inverse, DST basis)."""
-        return dst(dst(u) / (1.0 + bj * self.x))
+        """L_j^{-1} u = T^{-1} diag(1/(1 + b_j x)) T u (Sec. 3, isovelocity inverse; T the
+        transform of the boundary condition, the DST-I for Dirichlet)."""
+        return bases.inverse(self.bc, bases.forward(self.bc, u) / (1.0 + bj * self.x))
 
     def term_solve(self, u: np.ndarray, bj: complex, v: np.ndarray):
         """w = (1 + b_j X)^{-1} u by the Neumann series (eq. neumannseries).
         Returns (w, terms beyond m=0, final residual, status)."""
         term = self.l_inverse(u, bj)
         w = term.copy()
-        first = np.linalg.norm(term)
+        first = self.norm(term)
         m, res = 0, 0.0
         for m in range(1, self.neumann_max + 1):
             term = -bj * self.l_inverse(v * term, bj)
             w = w + term
-            tn, wn = np.linalg.norm(term), np.linalg.norm(w)
+            tn, wn = self.norm(term), self.norm(w)
             res = tn / wn if wn > 0 else 0.0
             if not (np.isfinite(tn) and np.isfinite(wn)):
                 return w, m, float("inf"), DIVERGED
@@ -107,7 +119,7 @@ class Plan:
                 return w, m, res, OK
         if self.neumann_max == 0:
             return w, 0, 0.0, OK
-        if np.linalg.norm(term) >= first:
+        if self.norm(term) >= first:
             return w, m, res, DIVERGED
         return w, m, res, NOT_CONVERGED
 

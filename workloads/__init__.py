@@ -18,7 +18,9 @@ Environments follow the paper's numerical section:
     Gaussian form with an image term so that it vanishes at the Dirichlet surface.
 
 The grid convention: Nz interior unknowns, dz = H / (Nz + 1), z_n = n dz for n = 1..Nz
-(homogeneous Dirichlet values at z = 0 and z = H are not stored).
+(homogeneous Dirichlet values at z = 0 and z = H are not stored).  The other boundary
+conditions of Sec. 3.1 use z_n = n H/(Nz - 1), n = 0..Nz-1 (Neumann, both boundaries on the
+grid) and z_n = n H/Nz, n = 0..Nz-1 (periodic).
 """
 from __future__ import annotations
 
@@ -35,10 +37,16 @@ SEED = 20251103
 # ----------------------------------------------------------------------------------------
 
 
-def depth_grid(nz: int, depth: float) -> np.ndarray:
-    """Interior depth points z_n = n H/(Nz+1), n = 1..Nz (float64)."""
-    dz = depth / (nz + 1)
-    return dz * np.arange(1, nz + 1, dtype=np.float64)
+def depth_grid(nz: int, depth: float, bc: str = "dirichlet") -> np.ndarray:
+    """Depth points of the grid (float64): interior points n H/(Nz+1), n = 1..Nz, for
+    Dirichlet boundaries; n H/(Nz-1), n = 0..Nz-1, for Neumann; n H/Nz for periodic."""
+    if bc == "dirichlet":
+        return depth / (nz + 1) * np.arange(1, nz + 1, dtype=np.float64)
+    if bc == "neumann":
+        return depth / (nz - 1) * np.arange(nz, dtype=np.float64)
+    if bc == "periodic":
+        return depth / nz * np.arange(nz, dtype=np.float64)
+    raise ValueError(f"unknown boundary condition {bc!r}")
 
 
 def munk(z: np.ndarray) -> np.ndarray:
@@ -74,10 +82,10 @@ def sound_speed(kind: str, z: np.ndarray, r: float = 0.0, c_const: float = 1500.
 
 
 def profile_steps(kind: str, nz: int, depth: float, dr: float, step0: int, nsteps: int,
-                  eddy: Optional[Eddy] = None) -> np.ndarray:
+                  eddy: Optional[Eddy] = None, bc: str = "dirichlet") -> np.ndarray:
     """c(r, z) for range steps step0+1 .. step0+nsteps, each sampled at the step's mid-range
     r = (n - 1/2) dr, shape [nsteps][Nz] float64."""
-    z = depth_grid(nz, depth)
+    z = depth_grid(nz, depth, bc)
     out = np.empty((nsteps, nz), dtype=np.float64)
     for i in range(nsteps):
         n = step0 + i + 1
@@ -90,11 +98,15 @@ def profile_steps(kind: str, nz: int, depth: float, dr: float, step0: int, nstep
 # ----------------------------------------------------------------------------------------
 
 
-def gaussian_starter(nz: int, depth: float, freq: float, c0: float, zs: float) -> np.ndarray:
-    """Gaussian starter with a surface image term, complex128 [Nz]."""
+def gaussian_starter(nz: int, depth: float, freq: float, c0: float, zs: float,
+                     bc: str = "dirichlet") -> np.ndarray:
+    """Gaussian starter with a surface image term, complex128 [Nz]: the image is subtracted
+    for Dirichlet boundaries (zero at z = 0), added for Neumann (zero slope at z = 0) and
+    left out for periodic ones."""
     k0 = 2.0 * math.pi * freq / c0
-    z = depth_grid(nz, depth)
-    g = np.exp(-0.5 * (k0 * (z - zs)) ** 2) - np.exp(-0.5 * (k0 * (z + zs)) ** 2)
+    z = depth_grid(nz, depth, bc)
+    sign = {"dirichlet": -1.0, "neumann": 1.0, "periodic": 0.0}[bc]
+    g = np.exp(-0.5 * (k0 * (z - zs)) ** 2) + sign * np.exp(-0.5 * (k0 * (z + zs)) ** 2)
     return (math.sqrt(k0) * g).astype(np.complex128)
 
 
@@ -131,22 +143,24 @@ class Solve:
     rotation: float = 0.0          # branch-cut rotation angle (rad); 0 = standard Pade
     out_every: int = 1
     eddy: Optional[Eddy] = None
+    bc: str = "dirichlet"          # "dirichlet" | "neumann" | "periodic" (Sec. 3.1)
 
     @property
     def k0(self) -> float:
         return 2.0 * math.pi * self.freq / self.c0
 
     def starter(self) -> np.ndarray:
-        return gaussian_starter(self.nz, self.depth, self.freq, self.c0, self.zs)
+        return gaussian_starter(self.nz, self.depth, self.freq, self.c0, self.zs, self.bc)
 
     def profile(self, step0: int = 0, nsteps: Optional[int] = None) -> np.ndarray:
         """c for steps step0+1..step0+nsteps ([nsteps][Nz]); range-independent
         environments return a single row [1][Nz]."""
         if self.env != "munk+eddy":
-            z = depth_grid(self.nz, self.depth)
+            z = depth_grid(self.nz, self.depth, self.bc)
             return sound_speed(self.env, z, c_const=self.c0)[None, :]
         return profile_steps(self.env, self.nz, self.depth, self.dr, step0,
-                             self.nsteps if nsteps is None else nsteps, self.eddy or Eddy())
+                             self.nsteps if nsteps is None else nsteps, self.eddy or Eddy(),
+                             self.bc)
 
     def updates(self) -> int:
         return self.nz * self.nsteps
