@@ -760,8 +760,9 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     constexpr int EK = eng_key<P, V>();
     // elements that can hold data (the lower half for unsplit lengths); the others stay zero
     constexpr int RL = live_elems<P, V>();
-    // the Neumann multiplier stays in registers for up to 8 elements per thread
-    constexpr bool kBInRegs = (RT <= 8) && (T < 1024);
+    // the Neumann multiplier stays in registers for up to 8 live elements per thread below
+    // 1024 threads (those layouts run two waves per SIMD, so 256 registers per lane)
+    constexpr bool kBInRegs = (RL <= 8) && (T < 1024);
     constexpr int EB = kBInRegs ? RL : 1;
     // ... and so does the potential A = v (.) dmod; otherwise both come from L2
     constexpr bool kAInRegs = kBInRegs;
