@@ -58,8 +58,8 @@ def source_fingerprint():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, batch, chunk):
-    t = TRAFFIC.get((workload, batch, chunk))
+def measured_traffic(workload, batch, chunk, bc="dirichlet"):
+    t = TRAFFIC.get((workload, batch, chunk)) if bc == "dirichlet" else None
     if t is None or t["fingerprint"] != source_fingerprint():
         return None
     return t["fetch"] + t["write"]
@@ -73,8 +73,9 @@ def algorithmic_flops(nz, pade_order, terms, steps, outputs):
     return terms * 2 * (tr + 8 * nz) + steps * pade_order * 16 * nz + outputs * tr
 
 
-def _solve(workload, nz=None, nsteps=None, zs=None, index=None):
-    """The Solve of one job of a workload (index: frequency index of the broadband set)."""
+def _solve(workload, nz=None, nsteps=None, zs=None, index=None, bc="dirichlet"):
+    """The Solve of one job of a workload (index: frequency index of the broadband set;
+    bc: boundary condition of the device-batch workloads)."""
     if workload == "munk4096":
         s = W.munk_deep(nz=nz or 4096)
     elif workload == "homogeneous":
@@ -89,6 +90,7 @@ def _solve(workload, nz=None, nsteps=None, zs=None, index=None):
         s.nsteps = nsteps
     if zs is not None:
         s.zs = zs
+    s.bc = bc
     return s
 
 
@@ -98,43 +100,45 @@ def log(msg):
 
 
 def _oracle_worker(args):
-    workload, nz, nsteps, zs, index = args
+    workload, nz, nsteps, zs, index, bc = args
     import scipy.fft  # noqa: F401
     from threadpoolctl import threadpool_limits
     threadpool_limits(1)   # one thread per solve process: `cores` counts the processes
     from oracle import Plan
-    s = _solve(workload, nz, nsteps, zs, index)
+    s = _solve(workload, nz, nsteps, zs, index, bc)
     pl = Plan(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol,
-              rotation=s.rotation)
+              rotation=s.rotation, bc=s.bc)
     t = time.perf_counter()
     pl.march(s.starter(), nsteps, s.profile(), out_every=s.out_every)
     return s.nz * nsteps, time.perf_counter() - t
 
 
-def cpu_baseline(workload, nz, seconds_target=20.0):
+def cpu_baseline(workload, nz, seconds_target=20.0, bc="dirichlet"):
     """The FP64 oracle on the host cores: one solve per process, a bounded number of steps."""
     cores = max(1, min(16, os.cpu_count() or 1))
     if workload == "serving":
         reqs = W.serving_requests(duration=0.2)[:cores]
-        jobs = [("serving", None, None, None, i) for i in range(len(reqs))]
-        upd, dt = _oracle_worker(("serving", None, 1, None, 0))
+        jobs = [("serving", None, None, None, i, bc) for i in range(len(reqs))]
+        upd, dt = _oracle_worker(("serving", None, 1, None, 0, bc))
         steps = max(1, int(seconds_target / max(dt, 1e-3)))
-        jobs = [(w, n, steps, z, i) for (w, n, _, z, i) in jobs]
+        jobs = [(w, n, steps, z, i, b) for (w, n, _, z, i, b) in jobs]
         what = f"the first {len(jobs)} requests of the stream x {steps} range steps each"
     elif workload == "broadband":
         # every 16th frequency (uneven Nz), the same bounded step count each
-        jobs = [(workload, None, 1, None, i) for i in range(0, 256, 256 // cores)][:cores]
+        jobs = [(workload, None, 1, None, i, bc) for i in range(0, 256, 256 // cores)][:cores]
         upd, dt = _oracle_worker(jobs[len(jobs) // 2])
         steps = max(1, int(seconds_target / max(dt, 1e-3)))
-        jobs = [(w, n, steps, z, i) for (w, n, _, z, i) in jobs]
+        jobs = [(w, n, steps, z, i, b) for (w, n, _, z, i, b) in jobs]
         what = f"{len(jobs)} of the 256 frequencies (every {256 // cores}th) x {steps} range steps"
     else:
         lo, hi = (20.0, 180.0) if workload == "homogeneous" else (50.0, 2000.0)
-        upd, dt = _oracle_worker((workload, nz, 1, 0.5 * (lo + hi), None))
+        upd, dt = _oracle_worker((workload, nz, 1, 0.5 * (lo + hi), None, bc))
         steps = max(1, int(seconds_target / max(dt, 1e-3)))
         zs = W.source_depths(cores, lo, hi)
-        jobs = [(workload, nz, steps, float(z), None) for z in zs]
+        jobs = [(workload, nz, steps, float(z), None, bc) for z in zs]
         what = f"{cores} solves x {steps} range steps of the Nz={nz} {workload} workload"
+        if bc != "dirichlet":
+            what += f" ({bc} boundaries)"
     log(f"cpu baseline: {what} on {cores} processes")
     t = time.perf_counter()
     with mp.get_context("spawn").Pool(cores) as pool:
@@ -168,7 +172,8 @@ DESCRIPTIONS = {
 
 
 def make_plan(ssp, s):
-    pl = ssp.ssp_plan_create(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol)
+    pl = ssp.ssp_plan_create_bc(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max,
+                                s.tol, s.bc)
     if s.rotation:
         ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_ROTATION, s.rotation)
     ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_OUT_EVERY, s.out_every)
@@ -200,7 +205,7 @@ def plain_vs_fused(ssp, s, nsteps):
 
 def run_device_batch(args, ssp, torch, stream, dev):
     """One plan, a batch of B solves marched on the device (munk4096, eddy16384)."""
-    s = _solve(args.workload, args.nz)
+    s = _solve(args.workload, args.nz, bc=args.bc)
     B = args.batch
     pl = make_plan(ssp, s)
     ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
@@ -209,7 +214,7 @@ def run_device_batch(args, ssp, torch, stream, dev):
 
     zs = (W.source_depths(B, 20.0, 180.0) if args.workload == "homogeneous"
           else W.source_depths(B, 50.0, 2000.0))
-    psi = np.stack([W.gaussian_starter(s.nz, s.depth, s.freq, s.c0, z) for z in zs])
+    psi = np.stack([W.gaussian_starter(s.nz, s.depth, s.freq, s.c0, z, s.bc) for z in zs])
     d_psi = torch.from_numpy(psi.astype(np.complex64)).to(dev)
     d_step = torch.zeros(B, dtype=torch.int64, device=dev)
     d_stats = torch.zeros((B, 48), dtype=torch.uint8, device=dev)
@@ -257,14 +262,14 @@ def run_device_batch(args, ssp, torch, stream, dev):
     ssp.ssp_plan_destroy(pl)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
-            "traffic": measured_traffic(args.workload, B, args.chunk),
+            "traffic": measured_traffic(args.workload, B, args.chunk, args.bc),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": f"k_march<{P}, {layout}> ({threads} threads per workgroup)",
             "avg_launch_ms": 1e3 * sum(launch_s) / len(launch_s),
             "steps_per_launch": args.chunk,
             "neumann_terms_per_solve_step": stats["terms"] / B / args.chunk}
     config = {"batch_solves": B, "nz": s.nz, "range_steps_timed": args.steps,
-              "steps_per_launch": args.chunk, "hip_graph": bool(args.graph)}
+              "steps_per_launch": args.chunk, "hip_graph": bool(args.graph), "boundary": s.bc}
     plain = None
     if args.plain_steps > 0:
         plain = plain_vs_fused(ssp, s, args.plain_steps)
@@ -427,7 +432,13 @@ def main():
     ap.add_argument("--no-transforms", action="store_true",
                     help="skip the stand-alone transform measurements")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--bc", choices=["dirichlet", "neumann", "periodic"], default="dirichlet",
+                    help="boundary condition (Sec. 3.1) of the munk4096, eddy16384 and "
+                         "homogeneous workloads")
     args = ap.parse_args()
+    if args.bc != "dirichlet" and args.workload in ("broadband", "serving"):
+        print("--bc applies to the munk4096, eddy16384 and homogeneous workloads", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); every solve of the batch is "
               "independent, so several GPUs would each run their own batch", file=sys.stderr)
@@ -469,7 +480,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(args.workload, nz, args.cpu_seconds)
+        cpu = cpu_baseline(args.workload, nz, args.cpu_seconds, args.bc)
 
     out = {
         "metric": "field updates (Nz x range steps)/s at TL err<=0.1 dB",
@@ -484,7 +495,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded Munk profile and Gaussian starters)",
-        "config": {"workload": DESCRIPTIONS[args.workload], **config},
+        "config": {"workload": DESCRIPTIONS[args.workload] + (
+            f", {args.bc} boundaries (Sec. 3.1)" if args.bc != "dirichlet" else ""), **config},
         "roofline": roof,
         "status": statuses,
         "plain_form": plain,

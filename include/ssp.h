@@ -10,7 +10,9 @@
  *             transform -> diagonal scale -> inverse transform -> multiply by
  *             v(z) = (c0/c(z))^2 - 1 otherwise.
  *   Sec. 3.1  homogeneous Dirichlet boundaries at z = 0 and z = H: the transform is the
- *             orthonormal DST-I on the interior grid z_n = n H/(Nz+1), n = 1..Nz.
+ *             orthonormal DST-I on the interior grid z_n = n H/(Nz+1), n = 1..Nz.  The
+ *             same section's Neumann (cosine transform) and periodic (Fourier transform)
+ *             boundaries are available through ssp_plan_create_bc.
  *   Alg. 1    the range march: for every step, every Pade term, then the carrier.
  *
  * All entry points are extern "C", return an ssp_status and never throw.  Pointers are
@@ -96,6 +98,23 @@ typedef struct {
     int32_t pad_;
 } ssp_stats;
 
+/* Boundary conditions at z = 0 and z = H (Sec. 3.1), each with its grid and transform:
+ *   SSP_BC_DIRICHLET  u = 0;  z_n = n H/(Nz+1), n = 1..Nz (interior points);  orthonormal
+ *                     DST-I, basis sin(l pi z/H), l = 1..Nz
+ *   SSP_BC_NEUMANN    d_z u = 0;  z_n = n H/(Nz-1), n = 0..Nz-1 (both boundaries on the
+ *                     grid);  basis cos(l pi z/H), l = 0..Nz-1, through the orthonormal DCT-I
+ *                     C applied to the grid values with the two boundary values scaled by
+ *                     1/sqrt(2) (forward C e u, inverse C a / e);  Neumann-series norms are
+ *                     the norms of e u (trapezoidal weights)
+ *   SSP_BC_PERIODIC   u(0) = u(H);  z_n = n H/Nz, n = 0..Nz-1;  orthonormal DFT (forward
+ *                     e^{-2 pi i l n/Nz}/sqrt(Nz)), basis e^{2 pi i l' z/H}, l' = l for
+ *                     l <= Nz/2 and l - Nz above
+ * Every basis function is an eigenfunction of d_z^2 (eigenvalue -kappa_l^2, kappa_l = l pi/H
+ * or 2 pi l'/H), which makes the isovelocity operator of every Pade term diagonal.  The
+ * coefficient-space field kept on the device ("sine basis" below) is that of the plan's
+ * basis. */
+enum { SSP_BC_DIRICHLET = 0, SSP_BC_NEUMANN = 1, SSP_BC_PERIODIC = 2 };
+
 /* Create a plan (Alg. 1 "compute d_j and b_j"; Sec. 2 Pade form; Sec. 3.1 grid).
  *   Nz           interior depth points, 2 <= Nz <= ssp_max_nz();  dz = H/(Nz+1)
  *   H            waveguide depth (m) > 0;  f  frequency (Hz) > 0
@@ -109,6 +128,13 @@ typedef struct {
  * SSP_E_DEVICE.  *out is set to NULL on error. */
 ssp_status ssp_plan_create(int Nz, double H, double f, double c0, double dr, int pade_order,
                            int neumann_max, double tol, ssp_plan **out);
+/* ssp_plan_create with the boundary condition bc (SSP_BC_*; Sec. 3.1): grid, transform and
+ * eigenvalues as listed above; ssp_plan_create is bc = SSP_BC_DIRICHLET.  Sound-speed
+ * tables and starters are sampled on the bc's grid; every entry point below works on any
+ * bc except ssp_dst_dense_device (Dirichlet only).  Errors as ssp_plan_create, and
+ * SSP_E_INVAL for an unknown bc. */
+ssp_status ssp_plan_create_bc(int Nz, double H, double f, double c0, double dr, int pade_order,
+                              int neumann_max, double tol, int bc, ssp_plan **out);
 void ssp_plan_destroy(ssp_plan *plan); /* NULL-safe; releases device memory */
 ssp_status ssp_plan_set_option(ssp_plan *plan, int key, double value);
 ssp_status ssp_plan_set_stream(ssp_plan *plan, void *hip_stream);
@@ -188,7 +214,9 @@ ssp_status ssp_from_sine(ssp_plan *plan, int B, const void *d_sine, const void *
                          void *d_phys);
 
 /* Stand-alone batched orthonormal DST-I (Sec. 3.1) of B complex64 vectors of length Nz,
- * device in/out (may alias), asynchronous on the plan's stream. */
+ * device in/out (may alias), asynchronous on the plan's stream.  For Neumann and periodic
+ * plans: the forward transform of the plan's basis (grid values -> coefficients, as
+ * listed with SSP_BC_*). */
 ssp_status ssp_dst_device(ssp_plan *plan, int B, const void *d_in, void *d_out);
 
 /* The same transform as a dense matrix product Y = S X on the matrix cores (Sec. 3.1: S is
@@ -198,7 +226,8 @@ ssp_status ssp_dst_device(ssp_plan *plan, int B, const void *d_in, void *d_out);
  * scaling of S and of each column, so the relative error is about 2^-22 (a few 1e-7).
  * Device in/out [B][Nz] complex64 (may alias); asynchronous on the plan's stream.  The
  * plan builds S (2 x 2 bytes per entry, Nz rounded up to 128) and scratch for the split
- * operands on first use.  Nz > ssp_max_dense_nz() -> SSP_E_UNIMPL. */
+ * operands on first use.  Nz > ssp_max_dense_nz() or a plan that is not Dirichlet ->
+ * SSP_E_UNIMPL. */
 ssp_status ssp_dst_dense_device(ssp_plan *plan, int B, const void *d_in, void *d_out);
 int ssp_max_dense_nz(void);
 

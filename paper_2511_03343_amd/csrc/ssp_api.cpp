@@ -51,16 +51,22 @@ void dev_free(T *&p) {
 
 }  // namespace
 
+static_assert(SSP_BC_DIRICHLET == ssp::kBcDirichlet && SSP_BC_NEUMANN == ssp::kBcNeumann &&
+                  SSP_BC_PERIODIC == ssp::kBcPeriodic,
+              "boundary-condition codes of the ABI and the tables agree");
+
 struct ssp_plan {
     int N = 0, P = 0, p = 0, nmax = 0;
     double H = 0, f = 0, c0 = 0, dr = 0, tol = 0, k0 = 0, sigma = 0, alpha = 0;
     int out_every = 1, engine = 0;
+    int bc = ssp::kBcDirichlet;         // boundary condition (Sec. 3.1)
     int variant_opt = -1;               // SSP_OPT_VARIANT
     hipStream_t stream = nullptr;
     ssp::PadeSet ps;
     ssp::DeviceTables tab;
     // device tables
     float2 *d_k1 = nullptr, *d_k2 = nullptr, *d_dmod = nullptr, *d_post = nullptr, *d_pre = nullptr;
+    float2 *d_k1i = nullptr, *d_k2i = nullptr, *d_postf = nullptr;  // only where they differ
     uint32_t *d_tw = nullptr;
     float4 *d_s = nullptr, *d_bmul = nullptr, *d_alpha = nullptr, *d_beta = nullptr;
     float4 *d_twist = nullptr;
@@ -153,6 +159,9 @@ void free_side_streams(ssp_plan *pl) {
 void free_tables(ssp_plan *pl) {
     dev_free(pl->d_k1);
     dev_free(pl->d_k2);
+    dev_free(pl->d_k1i);
+    dev_free(pl->d_k2i);
+    dev_free(pl->d_postf);
     dev_free(pl->d_dmod);
     dev_free(pl->d_post);
     dev_free(pl->d_pre);
@@ -175,7 +184,7 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     ssp::PadeSet ps;
     if (!ssp::pade_coefficients(pl->sigma, pl->p, pl->alpha, ps, err)) return fail(SSP_E_INVAL, err);
     ssp::DeviceTables tab;
-    ssp::build_tables(pl->N, pl->H, pl->k0, ps, tab);
+    ssp::build_tables(pl->N, pl->H, pl->k0, ps, pl->bc, tab);
     if (!(tab.max_gain <= 1.0 + 1e-6))
         return fail(SSP_E_UNSTABLE, "max |e^{i sigma} R(x_l)| = " + std::to_string(tab.max_gain) +
                                         " exceeds 1 + 1e-6");
@@ -193,6 +202,12 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     HIP_TRY(dev_alloc(&pl->d_alpha, p));
     HIP_TRY(dev_alloc(&pl->d_beta, p));
     HIP_TRY(dev_alloc(&pl->d_twist, tab.twist.size() / 4));
+    HIP_TRY(dev_alloc(&pl->d_k1i, tab.k1i.size() / 2));
+    HIP_TRY(dev_alloc(&pl->d_k2i, tab.k2i.size() / 2));
+    HIP_TRY(dev_alloc(&pl->d_postf, tab.postf.size() / 2));
+    if (!tab.k1i.empty()) HIP_TRY(upload(pl->d_k1i, tab.k1i));
+    if (!tab.k2i.empty()) HIP_TRY(upload(pl->d_k2i, tab.k2i));
+    if (!tab.postf.empty()) HIP_TRY(upload(pl->d_postf, tab.postf));
     HIP_TRY(upload(pl->d_k1, tab.k1));
     HIP_TRY(upload(pl->d_k2, tab.k2));
     HIP_TRY(upload(pl->d_tw, tab.twiddle));
@@ -226,10 +241,13 @@ ssp::SolveDesc base_desc(const ssp_plan *pl) {
     ssp::SolveDesc d{};
     d.k1 = pl->d_k1;
     d.k2 = pl->d_k2;
+    d.k1i = pl->d_k1i ? pl->d_k1i : pl->d_k1;
+    d.k2i = pl->d_k2i ? pl->d_k2i : pl->d_k2;
     d.tw = pl->d_tw;
     d.dmod = pl->d_dmod;
     d.post = pl->d_post;
     d.pre = pl->d_pre;
+    d.postf = pl->d_postf ? pl->d_postf : pl->d_post;
     d.s = pl->d_s;
     d.bmul = pl->d_bmul;
     d.alpha = pl->d_alpha;
@@ -241,7 +259,9 @@ ssp::SolveDesc base_desc(const ssp_plan *pl) {
     d.nmax = pl->nmax;
     d.tol2 = pl->tol * pl->tol;
     d.sigma = pl->sigma;
-    d.dz = pl->H / (pl->N + 1);
+    const ssp::GridSpec g = ssp::grid_spec(pl->bc, pl->N, pl->H);
+    d.dz = g.dz;
+    d.zoff = g.zoff;
     d.dr = pl->dr;
     d.c0 = pl->c0;
     d.prof_mode = pl->prof_mode;
@@ -371,8 +391,15 @@ ssp_status ssp_pade_coefficients(double sigma, int pade_order, double alpha, dou
 
 ssp_status ssp_plan_create(int Nz, double H, double f, double c0, double dr, int pade_order,
                            int neumann_max, double tol, ssp_plan **out) {
+    return ssp_plan_create_bc(Nz, H, f, c0, dr, pade_order, neumann_max, tol, SSP_BC_DIRICHLET, out);
+}
+
+ssp_status ssp_plan_create_bc(int Nz, double H, double f, double c0, double dr, int pade_order,
+                              int neumann_max, double tol, int bc, ssp_plan **out) {
     if (!out) return fail(SSP_E_INVAL, "out is NULL");
     *out = nullptr;
+    if (bc != SSP_BC_DIRICHLET && bc != SSP_BC_NEUMANN && bc != SSP_BC_PERIODIC)
+        return fail(SSP_E_INVAL, "bc must be SSP_BC_DIRICHLET, SSP_BC_NEUMANN or SSP_BC_PERIODIC");
     if (Nz < 2) return fail(SSP_E_INVAL, "Nz must be >= 2");
     if (Nz > ssp_max_nz()) return fail(SSP_E_UNIMPL, "Nz above ssp_max_nz()");
     if (!(H > 0) || !(f > 0) || !(c0 > 0) || !(dr > 0) || !std::isfinite(H) || !std::isfinite(f) ||
@@ -384,6 +411,7 @@ ssp_status ssp_plan_create(int Nz, double H, double f, double c0, double dr, int
     ssp_plan *pl = new (std::nothrow) ssp_plan;
     if (!pl) return fail(SSP_E_NOMEM, "host allocation failed");
     pl->N = Nz;
+    pl->bc = bc;
     pl->H = H;
     pl->f = f;
     pl->c0 = c0;
@@ -574,14 +602,14 @@ ssp_status ssp_set_profile_analytic(ssp_plan *pl, const ssp_env *env) {
     // range-independent part: the Munk potential on the grid, in FP64, stored as row 0 of
     // the profile table; the device adds the eddy term each step
     const int N = pl->N;
-    const double dz = pl->H / (N + 1);
+    const ssp::GridSpec g = ssp::grid_spec(pl->bc, N, pl->H);
     std::vector<float> v(N);
-    for (int n = 1; n <= N; ++n) {
-        const double z = n * dz, eta = 2.0 * (z - e[2]) / e[2];
+    for (int m = 0; m < N; ++m) {
+        const double z = (m + g.zoff) * g.dz, eta = 2.0 * (z - e[2]) / e[2];
         const double c = e[0] * (1.0 + e[1] * (eta + std::exp(-eta) - 1.0));
         if (!(c > 0)) return fail(SSP_E_INVAL, "Munk profile gives c <= 0 on the grid");
         const double q = pl->c0 / c;
-        v[n - 1] = static_cast<float>(q * q - 1.0);
+        v[m] = static_cast<float>(q * q - 1.0);
     }
     if (static_cast<size_t>(N) > pl->v_cap) {
         dev_free(pl->d_v);
@@ -935,6 +963,7 @@ int ssp_max_dense_nz(void) { return ssp::kMaxDenseNz; }
 ssp_status ssp_dst_dense_device(ssp_plan *pl, int B, const void *d_in, void *d_out) {
     if (!pl || B <= 0 || !d_in || !d_out) return fail(SSP_E_INVAL, "bad argument");
     if (pl->N > ssp::kMaxDenseNz) return fail(SSP_E_UNIMPL, "Nz above ssp_max_dense_nz()");
+    if (pl->bc != ssp::kBcDirichlet) return fail(SSP_E_UNIMPL, "the dense transform is the DST-I (Dirichlet plans)");
     if (B > (1 << 20)) return fail(SSP_E_INVAL, "B too large");
     if (!pl->d_dense_sh) {
         std::vector<uint16_t> sh, sl;

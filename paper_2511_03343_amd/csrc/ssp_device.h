@@ -23,10 +23,13 @@ enum ProfileMode : int { PROF_TABLE_FIXED = 0, PROF_TABLE_STEPS = 1, PROF_ANALYT
 // Everything one workgroup needs to march one solve.  Table pointers are shared by all
 // solves of a plan; state pointers are per solve.
 struct SolveDesc {
-    const float2 *k1, *k2;      // [P] chirp-window spectra
+    const float2 *k1, *k2;      // [P] chirp-window spectra, forward direction (grid -> basis)
+    const float2 *k1i, *k2i;    // [P] the same for the inverse direction (== k1, k2 for the
+                                //     sine and cosine transforms, their own inverses)
     const uint32_t *tw;         // first-octant twiddle table (see DeviceTables::twiddle)
-    const float2 *dmod, *post;  // [N]
-    const float2 *pre;          // [N] conj chirp (physical -> chirp-z input)
+    const float2 *dmod, *post;  // [N] folded modulation; inverse post-modulation
+    const float2 *pre;          // [N] forward pre-modulation (grid values -> chirp-z input)
+    const float2 *postf;        // [N] forward post-modulation (stand-alone transform)
     const float4 *s, *bmul;     // [p][N] double-float
     const float4 *alpha, *beta; // [p] double-float
     const float4 *twist;        // [P/2] double-float w_P^n (split transforms, P > 16384), else null
@@ -34,6 +37,7 @@ struct SolveDesc {
     double tol2;                // tol^2 (squared-norm test)
     double sigma;               // k0 dr (carrier phase per step)
     double dz, dr, c0;
+    int zoff;                   // depth of position m is (m + zoff) dz
     int prof_mode, v_rows;
     long long v_step0;
     const float *v;             // [v_rows][N] FP32 potential (table modes)
@@ -90,9 +94,10 @@ hipError_t launch_output(int P, const SolveDesc *d_descs, int nsolves, int nout,
 
 // Batched transforms over B vectors of a plan's grid (tables from desc, one desc on the
 // device shared by the whole batch).
-//   mode 0: orthonormal DST-I (in -> out)
-//   mode 1: physical -> modulated sine representation
-//   mode 2: modulated sine representation -> physical field with carrier at step[b]
+//   mode 0: the forward transform of the plan's basis, grid values -> coefficients
+//           (orthonormal DST-I for Dirichlet boundaries)
+//   mode 1: physical -> modulated coefficient representation
+//   mode 2: modulated coefficient representation -> physical field with carrier at step[b]
 hipError_t launch_transform(int P, int mode, const SolveDesc *d_desc, int B, const float2 *in,
                             float2 *out, const long long *step, hipStream_t stream);
 

@@ -578,19 +578,20 @@ using ECfg = Cfg<eng_key<P, V>()>;
 template <int P, int V>
 constexpr int live_elems() { return eng_len<P>() == P ? ECfg<P, V>::RT / 2 : ECfg<P, V>::RT; }
 
-// One DST core for convolution length P (positions 0 .. eng_len-1 distributed as in the
-// engine).  For P above kMaxEngine the odd-frequency half needs the input again after the
+// One transform core for convolution length P (positions 0 .. eng_len-1 distributed as in
+// the engine), with the chirp-window spectra k1, k2 of the direction it runs in.  For P above kMaxEngine the odd-frequency half needs the input again after the
 // even half has overwritten x: KEEP_GLOBAL keeps it (and the even result) in the solve's
 // scratch keep[0 .. 2N), else in registers.  Both give identical results.  Positions >= N
 // of the input must be zero.  Output: split lengths return zero at positions >= N; unsplit
 // lengths return zero at positions >= P/2 and values without meaning in [N, P/2).
 template <int P, int V, bool KEEP_GLOBAL, int EKEY = eng_key<P, V>()>
 __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBufs &L,
-                                         const Twiddles<EKEY> &tw, const SolveDesc &d, float2 *keep) {
+                                         const Twiddles<EKEY> &tw, const SolveDesc &d, float2 *keep,
+                                         const float2 *k1, const float2 *k2) {
     constexpr int H = eng_len<P>();
     constexpr int EK = eng_key<P, V>();
     if constexpr (H == P) {
-        chirp_core<EK, false, true>(x, L, tw, d.k1, d.k2);
+        chirp_core<EK, false, true>(x, L, tw, k1, k2);
     } else {
         constexpr int T = Cfg<EK>::T, RT = Cfg<EK>::RT;
         const int N = d.N;
@@ -607,7 +608,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
                 y[i] = v;
             }
         }
-        chirp_core<EK, false>(x, L, tw, d.k1, d.k2);
+        chirp_core<EK, false>(x, L, tw, k1, k2);
         if constexpr (KEEP_GLOBAL) {
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
@@ -615,7 +616,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
                 if (pos < N) st2(keep + N, pos, x[i]);
                 x[i] = pos < N ? ld2(keep, pos) : make_float2(0.f, 0.f);
             }
-            chirp_core<EK, true>(x, L, tw, d.k1 + H, d.k2 + H);
+            chirp_core<EK, true>(x, L, tw, k1 + H, k2 + H);
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T;
@@ -623,7 +624,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
                                : make_float2(0.f, 0.f);
             }
         } else {
-            chirp_core<EK, true>(y, L, tw, d.k1 + H, d.k2 + H);
+            chirp_core<EK, true>(y, L, tw, k1 + H, k2 + H);
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T;
@@ -743,7 +744,7 @@ __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, 
         if (pos < N) {
             float v = ldf(vrow, m);
             if (d.prof_mode == PROF_ANALYTIC)
-                v += eddy_correction(d, v, static_cast<float>((pos + 1) * d.dz), r);
+                v += eddy_correction(d, v, static_cast<float>((pos + d.zoff) * d.dz), r);
             const float2 dm = ld2(d.dmod, m);
             val = make_float2(v * dm.x, v * dm.y);
             if constexpr (!IN_REGS) st2(d.pot, m, val);
@@ -827,7 +828,9 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
             // half-iteration h: even -> a = A (.) S a (multiply by v); odd -> a = B_j (.) S a
             // (diagonal solve) and the term is accumulated; one transform site per loop
             for (int h = 0; h < 2 * nmax; ++h) {
-                dst_core<P, V, kKeepGlobal>(a, L, tw, d, d.xs);
+                // even h: coefficients -> grid (inverse direction); odd h: grid -> coefficients
+                const bool fwd = (h & 1) != 0;
+                dst_core<P, V, kKeepGlobal>(a, L, tw, d, d.xs, fwd ? d.k1 : d.k1i, fwd ? d.k2 : d.k2i);
                 if ((h & 1) == 0) {
 #pragma unroll
                     for (int i = 0; i < RL; ++i) {
@@ -991,14 +994,14 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_transform(const SolveDesc *
         }
         x[i] = v;
     }
-    dst_core<P, 0, false>(x, L, tw, d, nullptr);
+    dst_core<P, 0, false>(x, L, tw, d, nullptr, mode == 2 ? d.k1i : d.k1, mode == 2 ? d.k2i : d.k2);
     float2 car = make_float2(1.f, 0.f);
     if (mode == 2) car = carrier(d.sigma, step[blockIdx.x]);
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
         const int pos = opaque_tid() + i * T, m = pos;
         if (pos < N) {
-            float2 v = cmul(x[i], mode == 1 ? ld2(d.dmod, m) : ld2(d.post, m));
+            float2 v = cmul(x[i], mode == 1 ? ld2(d.dmod, m) : ld2(mode == 0 ? d.postf : d.post, m));
             if (mode == 2) v = cmul(v, car);
             st2(vout, m, v);
         }
@@ -1029,7 +1032,7 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_output(const SolveDesc *__r
         const int pos = tid + i * T;
         x[i] = (pos < N) ? ld2(src, pos) : make_float2(0.f, 0.f);
     }
-    dst_core<P, 0, false>(x, L, tw, d, nullptr);
+    dst_core<P, 0, false>(x, L, tw, d, nullptr, d.k1i, d.k2i);
     const float2 car = carrier(d.sigma, n);
     const float lr = log10f(static_cast<float>(static_cast<double>(n) * d.dr));
 #pragma unroll
@@ -1103,7 +1106,7 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_plain_half(const SolveDesc 
         const int pos = opaque_tid() + i * T;
         x[i] = (pos < N) ? ld2(a, pos) : make_float2(0.f, 0.f);
     }
-    dst_core<P, 0, false>(x, L, tw, d, nullptr);
+    dst_core<P, 0, false>(x, L, tw, d, nullptr, (h & 1) ? d.k1 : d.k1i, (h & 1) ? d.k2 : d.k2i);
     if ((h & 1) == 0) {
         float2 A[RT];
         load_potential<P, 0, true>(d, n, A);

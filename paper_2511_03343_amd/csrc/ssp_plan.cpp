@@ -268,35 +268,77 @@ int chirp_fft_length(int n_min) {
 }
 
 // ------------------------------------------------------------------------------ tables
-void build_tables(int nz, double depth, double k0, const PadeSet &ps, DeviceTables &t) {
-    const int N = nz, M = nz + 1, P = chirp_fft_length(2 * nz - 1);
+GridSpec grid_spec(int bc, int nz, double depth) {
+    if (bc == kBcNeumann) return {0, depth / (nz - 1)};   // n H/(Nz-1), n = 0..Nz-1
+    if (bc == kBcPeriodic) return {0, depth / nz};        // n H/Nz, n = 0..Nz-1
+    return {1, depth / (nz + 1)};                         // n H/(Nz+1), n = 1..Nz
+}
+
+namespace {
+
+void put_c(std::vector<float> &v, size_t i, cd z) {
+    v[2 * i] = static_cast<float>(z.real());
+    v[2 * i + 1] = static_cast<float>(z.imag());
+}
+
+// FFT of a window given on positions 0..P-1, stored in the engine's slot order.
+std::vector<float> window_spectrum(std::vector<cd> w, int P, bool split) {
+    host_fft(w, -1);
+    const int PE = split ? P / 2 : P;
+    std::vector<float> out(2 * static_cast<size_t>(P));
+    for (int q = 0; q < P; ++q) {
+        const int slot = split ? ((q & 1) ? PE + q / 2 : q / 2) : q;
+        put_c(out, slot, w[q]);
+    }
+    return out;
+}
+
+}  // namespace
+
+void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, DeviceTables &t) {
+    const int N = nz, P = chirp_fft_length(2 * nz - 1);
     t.nz = N;
     t.P = P;
-    // chirp c_d = exp(i pi d^2 / (2M)) for d = 0..2N (even in d), the argument reduced
-    // exactly with d^2 mod 4M
+    t.bc = bc;
+    // Every transform kernel is a sum over n of x_n times exp(+-i theta k n) terms, and
+    // k n = (k^2 + n^2 - (k-n)^2)/2 = ((k+n)^2 - k^2 - n^2)/2 turns each into a chirp
+    // pre-modulation, a convolution (Toeplitz window, k - n) or correlation (Hankel window,
+    // k + n) with the chirp, and a chirp post-modulation:
+    //   sine    sin(pi k n/M), M = Nz+1:  (i conj(c_k)/2)(conv - corr), y_n = conj(c_n) x_n
+    //   cosine  cos(pi k n/M), M = Nz-1:  (conj(c_k)/2)(conv + corr),  y_n = conj(c_n) x_n
+    //   Fourier exp(-2 pi i k n/Nz):      conj(c_k) conv, y_n = conj(c_n) x_n; the inverse
+    //           exp(+2 pi i k n/Nz):      c_k conv', y_n = c_n x_n, window conj(c_d)
+    // with c_d = exp(i pi d^2 / D), D = 2M (sine, cosine) or Nz (Fourier).
+    const long long D = bc == kBcDirichlet ? 2LL * (N + 1) : (bc == kBcNeumann ? 2LL * (N - 1) : N);
+    // c_d for d = 0..2N (even in d), the argument reduced exactly with d^2 mod 2D
     std::vector<cd> ch(2 * static_cast<size_t>(N) + 1);
     for (long long d = 0; d <= 2LL * N; ++d) {
-        const long long r = (d * d) % (4LL * M);
-        const double ang = kPiD * static_cast<double>(r) / (2.0 * M);
+        const long long r = (d * d) % (2 * D);
+        const double ang = kPiD * static_cast<double>(r) / static_cast<double>(D);
         ch[d] = cd(std::cos(ang), std::sin(ang));
     }
     auto chirp = [&](long long d) { return ch[d < 0 ? -d : d]; };
-    std::vector<cd> K1(P, 0.0), K2(P, 0.0);
-    // element n (1..N) at position n-1: Toeplitz window c_{k-n}, Hankel window c_{(k-1)+(n-1)+2}
-    for (long long d = 1 - N; d <= N - 1; ++d) K1[((d % P) + P) % P] = chirp(d);
-    for (long long d = 0; d <= 2LL * N - 2; ++d) K2[d % P] = chirp(d + 2);
-    host_fft(K1, -1);
-    host_fft(K2, -1);
     const bool split = P > kMaxEngineFFT;
     const int PE = split ? P / 2 : P;
-    t.k1.resize(2 * P);
-    t.k2.resize(2 * P);
-    for (int q = 0; q < P; ++q) {
-        const int slot = split ? ((q & 1) ? PE + q / 2 : q / 2) : q;
-        t.k1[2 * slot] = static_cast<float>(K1[q].real());
-        t.k1[2 * slot + 1] = static_cast<float>(K1[q].imag());
-        t.k2[2 * slot] = static_cast<float>(K2[q].real());
-        t.k2[2 * slot + 1] = static_cast<float>(K2[q].imag());
+    {
+        std::vector<cd> K1(P, 0.0), K2(P, 0.0);
+        for (long long d = 1 - N; d <= N - 1; ++d) K1[((d % P) + P) % P] = chirp(d);
+        if (bc == kBcDirichlet) {
+            // element n (1..N) at position n-1: Hankel window c_{(k-1)+(n-1)+2}
+            for (long long d = 0; d <= 2LL * N - 2; ++d) K2[d % P] = chirp(d + 2);
+        } else if (bc == kBcNeumann) {
+            // the sum conv + corr as conv - (-corr)
+            for (long long d = 0; d <= 2LL * N - 2; ++d) K2[d % P] = -chirp(d);
+        }
+        t.k1 = window_spectrum(K1, P, split);
+        t.k2 = window_spectrum(K2, P, split);
+        t.k1i.clear();
+        t.k2i.clear();
+        if (bc == kBcPeriodic) {
+            for (long long d = 1 - N; d <= N - 1; ++d) K1[((d % P) + P) % P] = std::conj(chirp(d));
+            t.k1i = window_spectrum(K1, P, split);
+            t.k2i = t.k2;  // zero
+        }
     }
     t.twist.clear();
     if (split) {
@@ -307,22 +349,56 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, DeviceTabl
             split_df(std::sin(ang), t.twist[4 * n + 1], t.twist[4 * n + 3]);
         }
     }
-    const double scale = 0.5 * std::sqrt(2.0 / M) / P;  // (i/2) sqrt(2/M) / P, i applied below
+    // Modulations per position m = 0..N-1 (index n = m + 1 for the sine transform, n = m
+    // otherwise).  The coefficient-space representation kept on the device is the inverse
+    // transform's pre-modulated input, so that every transform of the march runs without
+    // its pre- and post-modulations: they are folded into dmod (post of one direction times
+    // pre of the other), which is the same in both directions.
+    //   sine:    pre = conj(c_n), post = i conj(c_k) sqrt(2/M)/(2P) (orthonormal DST-I)
+    //   cosine:  forward C e on grid values, inverse C/e (C the orthonormal DCT-I,
+    //            e = 1/sqrt(2) at both ends): pre_f = conj(c_n) e_n^2,
+    //            post_f = conj(c_k) e_k sqrt(2/M)/(2P); pre_i = conj(c_n) e_n,
+    //            post_i = conj(c_k) sqrt(2/M)/(2P)
+    //   Fourier: pre_f = conj(c_n), post_f = conj(c_k)/(sqrt(N) P); pre_i = c_n,
+    //            post_i = c_k/(sqrt(N) P); dmod = 1/(sqrt(N) P)
     const cd I(0, 1);
     std::vector<cd> dmod(N);
-    t.pre.resize(2 * N);
-    t.post.resize(2 * N);
-    t.dmod.resize(2 * N);
-    for (int n = 1; n <= N; ++n) {
-        cd cb = std::conj(chirp(n));
-        cd post = cb * I * scale;
-        dmod[n - 1] = cb * cb * I * scale;
-        t.pre[2 * (n - 1)] = static_cast<float>(cb.real());
-        t.pre[2 * (n - 1) + 1] = static_cast<float>(cb.imag());
-        t.post[2 * (n - 1)] = static_cast<float>(post.real());
-        t.post[2 * (n - 1) + 1] = static_cast<float>(post.imag());
-        t.dmod[2 * (n - 1)] = static_cast<float>(dmod[n - 1].real());
-        t.dmod[2 * (n - 1) + 1] = static_cast<float>(dmod[n - 1].imag());
+    t.pre.assign(2 * N, 0.f);
+    t.post.assign(2 * N, 0.f);
+    t.dmod.assign(2 * N, 0.f);
+    t.postf.clear();
+    if (bc != kBcDirichlet) t.postf.assign(2 * N, 0.f);
+    for (int m = 0; m < N; ++m) {
+        cd pre_f, post_i, post_f, pre_i;
+        if (bc == kBcDirichlet) {
+            const double scale = 0.5 * std::sqrt(2.0 / (N + 1)) / P;
+            const cd cb = std::conj(chirp(m + 1));
+            pre_f = pre_i = cb;
+            post_i = post_f = cb * I * scale;
+        } else if (bc == kBcNeumann) {
+            const double scale = 0.5 * std::sqrt(2.0 / (N - 1)) / P;
+            const double e = (m == 0 || m == N - 1) ? std::sqrt(0.5) : 1.0;
+            const cd cb = std::conj(chirp(m));
+            pre_f = cb * (e * e);
+            post_f = cb * (e * scale);
+            pre_i = cb * e;
+            post_i = cb * scale;
+        } else {
+            const double scale = 1.0 / (std::sqrt(static_cast<double>(N)) * P);
+            const cd c = chirp(m);
+            pre_f = std::conj(c);
+            post_f = std::conj(c) * scale;
+            pre_i = c;
+            post_i = c * scale;
+        }
+        // (the sine transform's product in the order of its original derivation)
+        dmod[m] = bc == kBcDirichlet ? std::conj(chirp(m + 1)) * std::conj(chirp(m + 1)) * I *
+                                           (0.5 * std::sqrt(2.0 / (N + 1)) / P)
+                                     : post_f * pre_i;
+        put_c(t.pre, m, pre_f);
+        put_c(t.post, m, post_i);
+        put_c(t.dmod, m, dmod[m]);
+        if (bc != kBcDirichlet) put_c(t.postf, m, post_f);
     }
     const int O = PE / 8;
     t.twiddle.resize(3 * static_cast<size_t>(O + 1));
@@ -342,14 +418,20 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, DeviceTabl
     t.alpha.resize(4 * p);
     t.beta.resize(4 * p);
     double gain = 0;
-    for (int l = 1; l <= N; ++l) {
-        double x = -std::pow(l * static_cast<double>(kPi) / (depth * k0), 2);
+    for (int m = 0; m < N; ++m) {
+        // eigenvalue of d_z^2 / k0^2 of basis function m: -(l pi/(H k0))^2 with l = m+1
+        // (sine), m (cosine) or 2 l' (Fourier, l' = m, or m - N above N/2)
+        double l;
+        if (bc == kBcDirichlet) l = m + 1;
+        else if (bc == kBcNeumann) l = m;
+        else l = 2.0 * static_cast<double>(2 * m <= N ? m : m - N);
+        const double x = -std::pow(l * kPiD / (depth * k0), 2);
         cd G = std::exp(cd(0, ps.sigma)) * pade_eval(ps, cd(x, 0));
         gain = std::max(gain, std::abs(G));
         for (int j = 0; j < p; ++j) {
             cd sj = 1.0 / (1.0 + ps.b[j] * x);
-            cd bj = -ps.b[j] * sj * dmod[l - 1];
-            size_t o = (static_cast<size_t>(j) * N + (l - 1)) * 4;
+            cd bj = -ps.b[j] * sj * dmod[m];
+            size_t o = (static_cast<size_t>(j) * N + m) * 4;
             split_df(sj.real(), t.s[o], t.s[o + 2]);
             split_df(sj.imag(), t.s[o + 1], t.s[o + 3]);
             split_df(bj.real(), t.bmul[o], t.bmul[o + 2]);

@@ -1,8 +1,8 @@
 // ssp_plan.h - host-side plan mathematics of the SSSP library (no HIP dependencies).
 //
 // Pade coefficients (Sec. 2, the [p/p] approximant of exp(i sigma (sqrt(1+x) - 1)); Alg. 1
-// first step), the sine-basis eigenvalues of the vertical operator (Sec. 3 and 3.1), and
-// the tables that the device kernels consume.  Everything here is computed in FP64 or
+// first step), the eigenvalues of the vertical operator in the sine, cosine or Fourier
+// basis (Sec. 3 and 3.1), and the tables that the device kernels consume.  Everything here is computed in FP64 or
 // extended precision on the host and rounded once when stored.
 #pragma once
 
@@ -43,16 +43,34 @@ int chirp_fft_length(int n_min);
 // Largest FFT one workgroup computes in LDS; longer convolutions are split in two.
 constexpr int kMaxEngineFFT = 16384;
 
+// Boundary conditions at z = 0 and z = H (Sec. 3.1) and their transforms.
+enum Boundary : int { kBcDirichlet = 0, kBcNeumann = 1, kBcPeriodic = 2 };
+
+// Grid of a boundary condition: z of position m (0-based) is (m + zoff) dz.
+struct GridSpec {
+    int zoff;
+    double dz;
+};
+GridSpec grid_spec(int bc, int nz, double depth);
+
 struct DeviceTables {
-    int nz = 0, P = 0;
-    // chirp-z DST (orthonormal DST-I of length nz through a cyclic convolution of length P):
-    // [P] complex FP32 spectra of the two chirp windows (Toeplitz c_d, d in [1-nz, nz-1];
-    // Hankel c_{d+2}, d in [0, 2nz-2]).  For P > kMaxEngineFFT they are stored as the even
-    // frequencies followed by the odd ones (the two halves of a split transform).
-    std::vector<float> k1, k2;
-    std::vector<float> pre;           // [nz] complex FP32  conj(c_n)
-    std::vector<float> post;          // [nz] complex FP32  conj(c_k) (i/2) sqrt(2/(nz+1)) / P
-    std::vector<float> dmod;          // [nz] complex FP32  conj(c_k)^2 (i/2) sqrt(2/(nz+1)) / P
+    int nz = 0, P = 0, bc = kBcDirichlet;
+    // chirp-z transform of length nz through a cyclic convolution of length P, with the
+    // chirp c_d = exp(i pi d^2 / D) (D = 2(nz+1) sine, 2(nz-1) cosine, nz Fourier):
+    // [P] complex FP32 spectra of the two chirp windows, Toeplitz c_d (d in [1-nz, nz-1])
+    // and Hankel (d in [0, 2nz-2]: c_{d+2} for the sine transform, whose element n sits
+    // at position n-1, and -c_d for the cosine transform; zero for the Fourier
+    // transform).  k1/k2 serve the forward direction (grid values -> coefficients);
+    // k1i/k2i, when not empty, the inverse direction (the Fourier transform only; the sine
+    // and cosine transforms are their own inverses).  For P > kMaxEngineFFT they are stored
+    // as the even frequencies followed by the odd ones (the two halves of a split
+    // transform).
+    std::vector<float> k1, k2, k1i, k2i;
+    std::vector<float> pre;           // [nz] complex FP32 forward pre-modulation
+    std::vector<float> post;          // [nz] complex FP32 inverse post-modulation (incl. 1/P)
+    std::vector<float> postf;         // [nz] forward post-modulation, when it differs from post
+    std::vector<float> dmod;          // [nz] complex FP32 post-modulation of one direction
+                                      // times pre-modulation of the other (the same both ways)
     // exp(-2 pi i e / PE) for e = 0..PE/8, PE = the engine FFT length (P, or P/2 when split;
     // the first octant, the device rebuilds the other octants by symmetry): per entry
     // hi.re, hi.im (FP32 bit patterns) and the rounding remainders lo.re, lo.im packed as two
@@ -67,8 +85,8 @@ struct DeviceTables {
     double max_gain = 0;              // max_l |e^{i sigma} R(x_l)|
 };
 
-// Build all device tables for a grid (nz, H, k0) and a coefficient set.
-void build_tables(int nz, double depth, double k0, const PadeSet &ps, DeviceTables &t);
+// Build all device tables for a grid (nz, H, k0, boundary condition) and a coefficient set.
+void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, DeviceTables &t);
 
 // Split a double into hi + lo floats (hi = nearest float, lo = nearest float of the rest).
 inline void split_df(double v, float &hi, float &lo) {

@@ -32,6 +32,11 @@ SSP_OPT_ENGINE = 4
 SSP_OPT_GRAPH = 5
 SSP_OPT_VARIANT = 6
 
+SSP_BC_DIRICHLET = 0
+SSP_BC_NEUMANN = 1
+SSP_BC_PERIODIC = 2
+BC_CODES = {"dirichlet": SSP_BC_DIRICHLET, "neumann": SSP_BC_NEUMANN, "periodic": SSP_BC_PERIODIC}
+
 
 class ssp_stats(C.Structure):
     _fields_ = [("steps_done", C.c_int64), ("step_index", C.c_int64),
@@ -78,6 +83,8 @@ def lib() -> C.CDLL:
         sig = {
             "ssp_plan_create": (S, [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                                     C.c_int, C.c_int, C.c_double, C.POINTER(_VP)]),
+            "ssp_plan_create_bc": (S, [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                                       C.c_int, C.c_int, C.c_double, C.c_int, C.POINTER(_VP)]),
             "ssp_plan_destroy": (None, [_VP]),
             "ssp_plan_set_option": (S, [_VP, C.c_int, C.c_double]),
             "ssp_plan_set_stream": (S, [_VP, _VP]),
@@ -139,6 +146,16 @@ def ssp_plan_create(Nz, H, f, c0, dr, pade_order, neumann_max, tol):
     out = _VP()
     _check(lib().ssp_plan_create(int(Nz), float(H), float(f), float(c0), float(dr),
                                  int(pade_order), int(neumann_max), float(tol), C.byref(out)))
+    return out.value
+
+
+def ssp_plan_create_bc(Nz, H, f, c0, dr, pade_order, neumann_max, tol, bc):
+    """bc: SSP_BC_* code or one of "dirichlet", "neumann", "periodic"."""
+    code = BC_CODES[bc] if isinstance(bc, str) else int(bc)
+    out = _VP()
+    _check(lib().ssp_plan_create_bc(int(Nz), float(H), float(f), float(c0), float(dr),
+                                    int(pade_order), int(neumann_max), float(tol), code,
+                                    C.byref(out)))
     return out.value
 
 
