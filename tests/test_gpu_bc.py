@@ -215,3 +215,57 @@ def test_mixed_boundaries_batch_equals_alone_bitwise(ssp, gpu):
             ssp.ssp_plan_destroy(pl)
     for a, b in zip(alone, fl):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_munk_bench_launch_configuration_sampled(ssp, gpu, bc):
+    # 512 solves at Nz = 4096 as `bench.py --bc` times them: one plan on a dedicated
+    # stream, graph-recorded launches, TL rows on the device; sampled solves vs the oracle
+    torch = gpu
+    s = with_bc(W.munk_deep(), bc)
+    B, nsteps = 512, 24
+    stream = torch.cuda.Stream()
+    pl = make_plan(ssp, s)
+    zs = W.source_depths(B, 50.0, 2000.0)
+    try:
+        ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_GRAPH, 1)
+        psi = np.stack([W.gaussian_starter(s.nz, s.depth, s.freq, s.c0, z, bc) for z in zs])
+        with torch.cuda.stream(stream):
+            d_psi = torch.from_numpy(psi.astype(np.complex64)).cuda()
+            steps = torch.zeros(B, dtype=torch.int64, device="cuda")
+            d_tl = torch.zeros((B, nsteps // s.out_every + 1, s.nz), dtype=torch.float32, device="cuda")
+            out = torch.empty_like(d_psi)
+        stream.synchronize()
+        ssp.ssp_to_sine(pl, B, d_psi.data_ptr(), d_psi.data_ptr())
+        ssp.ssp_march_device(pl, B, d_psi.data_ptr(), steps.data_ptr(), nsteps, d_tl.data_ptr())
+        ssp.ssp_from_sine(pl, B, d_psi.data_ptr(), steps.data_ptr(), out.data_ptr())
+        stream.synchronize()
+        tl = d_tl.cpu().numpy()
+        fld = out.cpu().numpy().astype(np.complex128)
+        assert steps.cpu().tolist() == [nsteps] * B
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    for b in (0, 511):
+        s1 = dataclasses.replace(s, zs=float(zs[b]), nsteps=nsteps)
+        ref = oracle_march(s1)
+        mask = ref.tl < 120.0
+        dtl = np.abs(tl[b, :ref.tl.shape[0]].astype(np.float64) - ref.tl)[mask]
+        err = np.linalg.norm(fld[b] - ref.final) / np.linalg.norm(ref.final)
+        _report(f"bench config {bc} b={b}", relL2=f"{err:.3e}", max_dTL=f"{dtl.max():.3e}")
+        assert err <= REL_L2 and dtl.max() <= DTL
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_munk_long_range(ssp, gpu, bc):
+    # 400 steps (10 km) at Nz = 1000: error growth over range stays within the bar
+    s = with_bc(W.munk_deep(nsteps=400, nz=1000), bc)
+    s.out_every = 100
+    pl = make_plan(ssp, s)
+    try:
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert st == ref.status
+    compare(f"munk long {bc}", fld, tl, ref)
