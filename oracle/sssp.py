@@ -33,6 +33,11 @@ Readings where the paper is silent (each also listed in the design notes):
   * Transmission loss TL = -20 log10(|u| / sqrt(r)) in dB re 1 m (the field u carries
     no cylindrical spreading factor, Sec. 2).
   * Output steps are n = out_every, 2 out_every, ... up to nsteps.
+  * Complex absorbing potential (Sec. 3.1 names it as a simple absorbing boundary): an
+    imaginary part i eta(z) added to v, i.e. to delta k^2 / k0^2, fixed in range, its
+    depth profile an input; eta > 0 damps (the one-way propagator
+    exp(i sigma sqrt(1 + X)) then has modulus below one).  The series, its stopping rule
+    and the step are unchanged, now in complex v.
 """
 from __future__ import annotations
 
@@ -150,17 +155,25 @@ class Plan:
 
     # --- the range march -----------------------------------------------------------------
     def march(self, psi0: np.ndarray, nsteps: int, c_steps: np.ndarray,
-              out_every: int = 1, r0: float = 0.0) -> MarchResult:
+              out_every: int = 1, r0: float = 0.0,
+              absorber: Optional[np.ndarray] = None) -> MarchResult:
         """March psi0 through nsteps range steps.  c_steps is [nsteps][Nz] (one sound-speed
-        sample per step) or [1][Nz] (range independent)."""
+        sample per step) or [1][Nz] (range independent).  absorber: imaginary part eta(z) of
+        a complex absorbing potential (Sec. 3.1), v -> v + i eta, eta >= 0 absorbs."""
         u = np.asarray(psi0, dtype=np.complex128).copy()
         c_steps = np.atleast_2d(np.asarray(c_steps, dtype=np.float64))
         fields, ranges = [], []
         iters, resid = [], []
         status, done = OK, 0
-        v_fixed = self.potential(c_steps[0]) if c_steps.shape[0] == 1 else None
+        eta = None if absorber is None else np.asarray(absorber, dtype=np.float64)
+
+        def pot(c):
+            v = self.potential(c)
+            return v if eta is None else v + 1j * eta
+
+        v_fixed = pot(c_steps[0]) if c_steps.shape[0] == 1 else None
         for n in range(1, nsteps + 1):
-            v = v_fixed if v_fixed is not None else self.potential(c_steps[n - 1])
+            v = v_fixed if v_fixed is not None else pot(c_steps[n - 1])
             un, it, rs, st = self.step(u, v)
             if st == DIVERGED:
                 status = DIVERGED

@@ -93,6 +93,16 @@ def profile_steps(kind: str, nz: int, depth: float, dr: float, step0: int, nstep
     return out
 
 
+def absorbing_layer(nz: int, depth: float, thickness: float, strength: float,
+                    bc: str = "dirichlet") -> np.ndarray:
+    """Imaginary part eta(z) of a complex absorbing potential in a bottom layer: zero above
+    H - thickness, rising as strength ((z - (H - thickness))/thickness)^2 to `strength` at
+    z = H (float64 [Nz])."""
+    z = depth_grid(nz, depth, bc)
+    t = np.clip((z - (depth - thickness)) / thickness, 0.0, None)
+    return strength * t * t
+
+
 # ----------------------------------------------------------------------------------------
 # starters
 # ----------------------------------------------------------------------------------------
