@@ -100,7 +100,7 @@ def log(msg):
 
 
 def _oracle_worker(args):
-    workload, nz, nsteps, zs, index, bc = args
+    workload, nz, nsteps, zs, index, bc, layer = args
     import scipy.fft  # noqa: F401
     from threadpoolctl import threadpool_limits
     threadpool_limits(1)   # one thread per solve process: `cores` counts the processes
@@ -108,37 +108,40 @@ def _oracle_worker(args):
     s = _solve(workload, nz, nsteps, zs, index, bc)
     pl = Plan(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol,
               rotation=s.rotation, bc=s.bc)
+    eta = None if layer is None else W.absorbing_layer(s.nz, s.depth, layer[0], layer[1], s.bc)
     t = time.perf_counter()
-    pl.march(s.starter(), nsteps, s.profile(), out_every=s.out_every)
+    pl.march(s.starter(), nsteps, s.profile(), out_every=s.out_every, absorber=eta)
     return s.nz * nsteps, time.perf_counter() - t
 
 
-def cpu_baseline(workload, nz, seconds_target=20.0, bc="dirichlet"):
+def cpu_baseline(workload, nz, seconds_target=20.0, bc="dirichlet", layer=None):
     """The FP64 oracle on the host cores: one solve per process, a bounded number of steps."""
     cores = max(1, min(16, os.cpu_count() or 1))
     if workload == "serving":
         reqs = W.serving_requests(duration=0.2)[:cores]
-        jobs = [("serving", None, None, None, i, bc) for i in range(len(reqs))]
-        upd, dt = _oracle_worker(("serving", None, 1, None, 0, bc))
+        jobs = [("serving", None, None, None, i, bc, None) for i in range(len(reqs))]
+        upd, dt = _oracle_worker(("serving", None, 1, None, 0, bc, None))
         steps = max(1, int(seconds_target / max(dt, 1e-3)))
-        jobs = [(w, n, steps, z, i, b) for (w, n, _, z, i, b) in jobs]
+        jobs = [(w, n, steps, z, i, b, y) for (w, n, _, z, i, b, y) in jobs]
         what = f"the first {len(jobs)} requests of the stream x {steps} range steps each"
     elif workload == "broadband":
         # every 16th frequency (uneven Nz), the same bounded step count each
-        jobs = [(workload, None, 1, None, i, bc) for i in range(0, 256, 256 // cores)][:cores]
+        jobs = [(workload, None, 1, None, i, bc, None) for i in range(0, 256, 256 // cores)][:cores]
         upd, dt = _oracle_worker(jobs[len(jobs) // 2])
         steps = max(1, int(seconds_target / max(dt, 1e-3)))
-        jobs = [(w, n, steps, z, i, b) for (w, n, _, z, i, b) in jobs]
+        jobs = [(w, n, steps, z, i, b, y) for (w, n, _, z, i, b, y) in jobs]
         what = f"{len(jobs)} of the 256 frequencies (every {256 // cores}th) x {steps} range steps"
     else:
         lo, hi = (20.0, 180.0) if workload == "homogeneous" else (50.0, 2000.0)
-        upd, dt = _oracle_worker((workload, nz, 1, 0.5 * (lo + hi), None, bc))
+        upd, dt = _oracle_worker((workload, nz, 1, 0.5 * (lo + hi), None, bc, layer))
         steps = max(1, int(seconds_target / max(dt, 1e-3)))
         zs = W.source_depths(cores, lo, hi)
-        jobs = [(workload, nz, steps, float(z), None, bc) for z in zs]
+        jobs = [(workload, nz, steps, float(z), None, bc, layer) for z in zs]
         what = f"{cores} solves x {steps} range steps of the Nz={nz} {workload} workload"
         if bc != "dirichlet":
             what += f" ({bc} boundaries)"
+        if layer is not None:
+            what += f" (absorbing layer {layer[0]:g} m, eta {layer[1]:g})"
     log(f"cpu baseline: {what} on {cores} processes")
     t = time.perf_counter()
     with mp.get_context("spawn").Pool(cores) as pool:
@@ -208,6 +211,8 @@ def run_device_batch(args, ssp, torch, stream, dev):
     s = _solve(args.workload, args.nz, bc=args.bc)
     B = args.batch
     pl = make_plan(ssp, s)
+    if args.absorber is not None:
+        ssp.ssp_set_absorber(pl, W.absorbing_layer(s.nz, s.depth, args.absorber[0], args.absorber[1], s.bc))
     ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
     ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_GRAPH, 1 if args.graph else 0)
     layout, threads, P = ssp.ssp_plan_engine(pl)
@@ -262,7 +267,8 @@ def run_device_batch(args, ssp, torch, stream, dev):
     ssp.ssp_plan_destroy(pl)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
-            "traffic": measured_traffic(args.workload, B, args.chunk, args.bc),
+            "traffic": measured_traffic(args.workload, B, args.chunk, args.bc)
+            if args.absorber is None else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": f"k_march<{P}, {layout}> ({threads} threads per workgroup)",
             "avg_launch_ms": 1e3 * sum(launch_s) / len(launch_s),
@@ -270,6 +276,8 @@ def run_device_batch(args, ssp, torch, stream, dev):
             "neumann_terms_per_solve_step": stats["terms"] / B / args.chunk}
     config = {"batch_solves": B, "nz": s.nz, "range_steps_timed": args.steps,
               "steps_per_launch": args.chunk, "hip_graph": bool(args.graph), "boundary": s.bc}
+    if args.absorber is not None:
+        config["absorber"] = {"thickness_m": args.absorber[0], "eta_max": args.absorber[1]}
     plain = None
     if args.plain_steps > 0:
         plain = plain_vs_fused(ssp, s, args.plain_steps)
@@ -435,10 +443,17 @@ def main():
     ap.add_argument("--bc", choices=["dirichlet", "neumann", "periodic"], default="dirichlet",
                     help="boundary condition (Sec. 3.1) of the munk4096, eddy16384 and "
                          "homogeneous workloads")
+    ap.add_argument("--absorber", default=None, metavar="THICKNESS,ETA",
+                    help="complex absorbing layer at the bottom (Sec. 3.1): thickness in m and "
+                         "the largest imaginary part of v, for the device-batch workloads")
     args = ap.parse_args()
-    if args.bc != "dirichlet" and args.workload in ("broadband", "serving"):
-        print("--bc applies to the munk4096, eddy16384 and homogeneous workloads", file=sys.stderr)
+    if (args.bc != "dirichlet" or args.absorber) and args.workload in ("broadband", "serving"):
+        print("--bc and --absorber apply to the munk4096, eddy16384 and homogeneous workloads",
+              file=sys.stderr)
         sys.exit(2)
+    if args.absorber is not None:
+        th, eta = (float(x) for x in args.absorber.split(","))
+        args.absorber = (th, eta)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); every solve of the batch is "
               "independent, so several GPUs would each run their own batch", file=sys.stderr)
@@ -480,7 +495,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(args.workload, nz, args.cpu_seconds, args.bc)
+        cpu = cpu_baseline(args.workload, nz, args.cpu_seconds, args.bc, args.absorber)
 
     out = {
         "metric": "field updates (Nz x range steps)/s at TL err<=0.1 dB",
@@ -496,7 +511,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded Munk profile and Gaussian starters)",
         "config": {"workload": DESCRIPTIONS[args.workload] + (
-            f", {args.bc} boundaries (Sec. 3.1)" if args.bc != "dirichlet" else ""), **config},
+            f", {args.bc} boundaries (Sec. 3.1)" if args.bc != "dirichlet" else "") + (
+            f", bottom absorbing layer {args.absorber[0]:g} m (eta up to {args.absorber[1]:g})"
+            if args.absorber else ""), **config},
         "roofline": roof,
         "status": statuses,
         "plain_form": plain,

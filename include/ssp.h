@@ -166,6 +166,15 @@ ssp_status ssp_set_profile(ssp_plan *plan, int step0, int nsteps, const double *
 /* Analytic profile evaluated on the device each step (replaces any table). */
 ssp_status ssp_set_profile_analytic(ssp_plan *plan, const ssp_env *env);
 
+/* Complex absorbing potential (Sec. 3.1: an imaginary part of the wavenumber in a layer,
+ * a simple absorbing boundary that lets a computational domain be truncated):
+ * v -> v + i eta(z) on top of whatever profile is set, fixed in range.  eta [Nz] (doubles,
+ * finite; eta >= 0 damps, typically zero above a bottom layer and rising inside it) is
+ * stored on the device in FP32; NULL removes the absorber.  The Neumann series then runs in
+ * complex v; a strong absorber raises the number of terms per series (and, past the
+ * series' convergence radius, is reported as SSP_E_DIVERGED by the march). */
+ssp_status ssp_set_absorber(ssp_plan *plan, const double *eta);
+
 /* Starter: psi0 [Nz] complex (re, im doubles), physical space.  Resets the step
  * counter to 0 and r to 0.  The field is transformed to the sine basis on the device. */
 ssp_status ssp_set_field(ssp_plan *plan, const double *psi0);

@@ -75,6 +75,7 @@ struct ssp_plan {
     long long v_step0 = 0;
     float *d_v = nullptr;
     size_t v_cap = 0;
+    float *d_vi = nullptr;              // absorbing layer: imaginary part of v [N], or null
     double env[8] = {0};
     // state of the plan's own solve
     float2 *d_field = nullptr, *d_work = nullptr;
@@ -268,6 +269,7 @@ ssp::SolveDesc base_desc(const ssp_plan *pl) {
     d.v_rows = pl->v_rows;
     d.v_step0 = pl->v_step0;
     d.v = pl->d_v;
+    d.vi = pl->d_vi;
     for (int i = 0; i < 8; ++i) d.env[i] = pl->env[i];
     d.out_every = pl->out_every;
     d.variant = effective_variant(pl);
@@ -456,6 +458,7 @@ void ssp_plan_destroy(ssp_plan *pl) {
     free_side_streams(pl);
     free_tables(pl);
     dev_free(pl->d_v);
+    dev_free(pl->d_vi);
     dev_free(pl->d_field);
     dev_free(pl->d_work);
     dev_free(pl->d_bwork);
@@ -557,6 +560,26 @@ ssp_status ssp_plan_info(const ssp_plan *pl, double *sigma, double *k0, double *
         d0[0] = pl->ps.d0.real();
         d0[1] = pl->ps.d0.imag();
     }
+    return SSP_OK;
+}
+
+ssp_status ssp_set_absorber(ssp_plan *pl, const double *eta) {
+    if (!pl) return fail(SSP_E_INVAL, "NULL plan");
+    drop_graph(pl);
+    if (!eta) {
+        if (pl->stream) HIP_TRY(hipStreamSynchronize(pl->stream));
+        else HIP_TRY(hipDeviceSynchronize());
+        dev_free(pl->d_vi);
+        return SSP_OK;
+    }
+    std::vector<float> v(pl->N);
+    for (int m = 0; m < pl->N; ++m) {
+        if (!std::isfinite(eta[m])) return fail(SSP_E_INVAL, "non-finite absorber value");
+        v[m] = static_cast<float>(eta[m]);
+    }
+    if (!pl->d_vi) HIP_TRY(dev_alloc(&pl->d_vi, pl->N));
+    HIP_TRY(hipMemcpyAsync(pl->d_vi, v.data(), pl->N * sizeof(float), hipMemcpyHostToDevice, pl->stream));
+    HIP_TRY(hipStreamSynchronize(pl->stream));
     return SSP_OK;
 }
 

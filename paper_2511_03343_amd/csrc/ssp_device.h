@@ -41,6 +41,7 @@ struct SolveDesc {
     int prof_mode, v_rows;
     long long v_step0;
     const float *v;             // [v_rows][N] FP32 potential (table modes)
+    const float *vi;            // [N] imaginary part of the potential (absorbing layer) or null
     double env[8];              // analytic environment (ssp_env order)
     float2 *field;              // [N] sine-basis state (modulated representation)
     float2 *work;               // [N] scratch state between Pade factors

@@ -724,7 +724,8 @@ __device__ __forceinline__ float eddy_correction(const SolveDesc &d, float vm, f
     return q * (-e * (2.0f + e) / ((1.0f + e) * (1.0f + e)));
 }
 
-// A = v (.) dmod at the thread's positions (zero at positions >= N); v of global step n.
+// A = v (.) dmod at the thread's positions (zero at positions >= N); v of global step n,
+// plus i eta when the plan has an absorbing layer (complex absorbing potential).
 // Written to registers (A) when the kernel keeps it there, else to the solve's pot array.
 template <int P, int V, bool IN_REGS>
 __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, float2 *A) {
@@ -746,7 +747,8 @@ __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, 
             if (d.prof_mode == PROF_ANALYTIC)
                 v += eddy_correction(d, v, static_cast<float>((pos + d.zoff) * d.dz), r);
             const float2 dm = ld2(d.dmod, m);
-            val = make_float2(v * dm.x, v * dm.y);
+            if (d.vi) val = cmul(make_float2(v, ldf(d.vi, m)), dm);
+            else val = make_float2(v * dm.x, v * dm.y);
             if constexpr (!IN_REGS) st2(d.pot, m, val);
         }
         if constexpr (IN_REGS) A[i] = val;

@@ -94,6 +94,7 @@ def lib() -> C.CDLL:
             "ssp_pade_coefficients": (S, [C.c_double, C.c_int, C.c_double, _DP, _DP, _DP, _DP, _DP]),
             "ssp_set_profile": (S, [_VP, C.c_int, C.c_int, _DP]),
             "ssp_set_profile_analytic": (S, [_VP, C.POINTER(ssp_env)]),
+            "ssp_set_absorber": (S, [_VP, _DP]),
             "ssp_set_field": (S, [_VP, _DP]),
             "ssp_get_field": (S, [_VP, _DP]),
             "ssp_march": (S, [_VP, _DP, C.c_int, _DP, _FP, C.POINTER(ssp_stats)]),
@@ -215,6 +216,12 @@ def ssp_set_profile_analytic(plan, munk=(1500.0, 0.00737, 1300.0), eddy=None):
     if eddy is not None:
         e.eddy_amp, e.eddy_r0, e.eddy_rr, e.eddy_z0, e.eddy_rz = eddy
     return _check(lib().ssp_set_profile_analytic(plan, C.byref(e)))
+
+
+def ssp_set_absorber(plan, eta=None):
+    """eta: [Nz] imaginary part of the potential (None removes the absorber)."""
+    arr = None if eta is None else np.ascontiguousarray(eta, dtype=np.float64)
+    return _check(lib().ssp_set_absorber(plan, _dp(arr)))
 
 
 def ssp_set_field(plan, psi0, nz):
