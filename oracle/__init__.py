@@ -11,6 +11,7 @@ Modules:
   dst        orthonormal DST-I (Sec. 3.1) and its O(N^2) definition
   bases      grids, eigenvalues and transforms of the Dirichlet, Neumann and periodic
              boundary conditions (Sec. 3.1)
+  modal      normal-mode starter and normal-mode field (Sec. 3.2)
   sssp       the range march in sum and product form (Sec. 3, eq. neumannseries, Alg. 1)
   reference  closed-form and brute-force references used to pin the oracle itself
 
