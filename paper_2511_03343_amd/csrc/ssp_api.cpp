@@ -14,6 +14,7 @@
 #include "ssp_device.h"
 #include "ssp_plan.h"
 #include "ssp_dense.h"
+#include "ssp_modal.h"
 #include "ssp_tuned.h"
 
 namespace {
@@ -560,6 +561,36 @@ ssp_status ssp_plan_info(const ssp_plan *pl, double *sigma, double *k0, double *
         d0[0] = pl->ps.d0.real();
         d0[1] = pl->ps.d0.imag();
     }
+    return SSP_OK;
+}
+
+ssp_status ssp_modal_starter(ssp_plan *pl, const double *c, double zs, int max_modes, double *psi0,
+                             double *kappa, int *n_modes) {
+    if (!pl || !c || !psi0) return fail(SSP_E_INVAL, "NULL argument");
+    if (pl->bc != ssp::kBcDirichlet) return fail(SSP_E_UNIMPL, "the modal starter is built for Dirichlet plans");
+    if (pl->N > ssp::kMaxModalNz) return fail(SSP_E_UNIMPL, "Nz above the modal starter's limit (16384)");
+    if (!(zs > 0) || !(zs < pl->H)) return fail(SSP_E_INVAL, "zs must lie inside (0, H)");
+    const int N = pl->N;
+    std::vector<double> v(N);
+    for (int m = 0; m < N; ++m) {
+        if (!std::isfinite(c[m]) || !(c[m] > 0)) return fail(SSP_E_INVAL, "sound speed must be finite and > 0");
+        const double q = pl->c0 / c[m];
+        v[m] = q * q - 1.0;
+    }
+    std::vector<double> u, kap;
+    std::string err;
+    const hipError_t e = ssp::modal_starter(N, pl->H, pl->k0, v, zs, max_modes, pl->stream, u, kap, err);
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory) return fail(SSP_E_NOMEM, err);
+        return fail(SSP_E_DEVICE, err);
+    }
+    for (int m = 0; m < N; ++m) {
+        psi0[2 * m] = u[m];
+        psi0[2 * m + 1] = 0.0;
+    }
+    if (kappa)
+        for (size_t k = 0; k < kap.size(); ++k) kappa[k] = kap[k];
+    if (n_modes) *n_modes = static_cast<int>(kap.size());
     return SSP_OK;
 }
 
