@@ -80,6 +80,8 @@ def _solve(workload, nz=None, nsteps=None, zs=None, index=None, bc="dirichlet"):
         s = W.munk_deep(nz=nz or 4096)
     elif workload == "homogeneous":
         s = W.homogeneous_waveguide()
+    elif workload == "modal8001":
+        s = W.first_experiment()
     elif workload == "eddy16384":
         s = W.munk_eddy(nz=nz or 16384)
     elif workload == "serving":
@@ -132,7 +134,7 @@ def cpu_baseline(workload, nz, seconds_target=20.0, bc="dirichlet", layer=None):
         jobs = [(w, n, steps, z, i, b, y) for (w, n, _, z, i, b, y) in jobs]
         what = f"{len(jobs)} of the 256 frequencies (every {256 // cores}th) x {steps} range steps"
     else:
-        lo, hi = (20.0, 180.0) if workload == "homogeneous" else (50.0, 2000.0)
+        lo, hi = {"homogeneous": (20.0, 180.0), "modal8001": (100.0, 3900.0)}.get(workload, (50.0, 2000.0))
         upd, dt = _oracle_worker((workload, nz, 1, 0.5 * (lo + hi), None, bc, layer))
         steps = max(1, int(seconds_target / max(dt, 1e-3)))
         zs = W.source_depths(cores, lo, hi)
@@ -142,6 +144,8 @@ def cpu_baseline(workload, nz, seconds_target=20.0, bc="dirichlet", layer=None):
             what += f" ({bc} boundaries)"
         if layer is not None:
             what += f" (absorbing layer {layer[0]:g} m, eta {layer[1]:g})"
+        if workload == "modal8001":
+            what += " (Gaussian starters: with every series cut at M = 2 a step costs the same for any starter)"
     log(f"cpu baseline: {what} on {cores} processes")
     t = time.perf_counter()
     with mp.get_context("spawn").Pool(cores) as pool:
@@ -158,6 +162,7 @@ DEFAULTS = {  # batch, timed steps, warmup steps, steps per launch
     "eddy16384": (256, 100, 10, 50),
     "broadband": (256, 200, 40, 200),
     "serving": (1024, 0, 0, 50),
+    "modal8001": (512, 500, 20, 100),
 }
 DESCRIPTIONS = {
     "homogeneous": "homogeneous Dirichlet waveguide, H=200 m, c=1500 m/s, 100 Hz, Nz=256, rotated [4/4] "
@@ -168,6 +173,9 @@ DESCRIPTIONS = {
                  "(cap 12), potential on device every step, TL every 5 steps",
     "broadband": "256 frequencies 50..300 Hz, Munk, Nz=2667..16000 (16 pts/wavelength), [6/6] Pade, "
                  "dr=25 m, Neumann tol 1e-10 (cap 48), TL every 40 steps to host",
+    "modal8001": "range-independent Munk waveguide of the paper's first experiment: H=4 km, 100 Hz, "
+                 "Nz=8001, [4/4] Pade, dr=100 m, Neumann series cut at M=2, normal-mode starters "
+                 "(one device eigendecomposition for all source depths), TL every 10 steps",
     "serving": "Poisson request stream: f ~ U[25, 400] Hz, Nz a power of two 512..16384 (>= 4 pts/"
                "wavelength), range U[10, 100] km, Munk or Munk + eddy, [6/6], dr = max(25 m, 5/k0), "
                "continuous batching, TL rows to host every tick",
@@ -218,8 +226,16 @@ def run_device_batch(args, ssp, torch, stream, dev):
     layout, threads, P = ssp.ssp_plan_engine(pl)
 
     zs = (W.source_depths(B, 20.0, 180.0) if args.workload == "homogeneous"
+          else W.source_depths(B, 100.0, 3900.0) if args.workload == "modal8001"
           else W.source_depths(B, 50.0, 2000.0))
-    psi = np.stack([W.gaussian_starter(s.nz, s.depth, s.freq, s.c0, z, s.bc) for z in zs])
+    starter_s = None
+    if args.workload == "modal8001":
+        t_st = time.perf_counter()
+        psi, kappa = ssp.ssp_modal_starter(pl, s.profile()[0], zs)
+        starter_s = time.perf_counter() - t_st
+        log(f"modal starters: {B} sources, {len(kappa)} modes, {starter_s:.2f} s")
+    else:
+        psi = np.stack([W.gaussian_starter(s.nz, s.depth, s.freq, s.c0, z, s.bc) for z in zs])
     d_psi = torch.from_numpy(psi.astype(np.complex64)).to(dev)
     d_step = torch.zeros(B, dtype=torch.int64, device=dev)
     d_stats = torch.zeros((B, 48), dtype=torch.uint8, device=dev)
@@ -278,6 +294,9 @@ def run_device_batch(args, ssp, torch, stream, dev):
               "steps_per_launch": args.chunk, "hip_graph": bool(args.graph), "boundary": s.bc}
     if args.absorber is not None:
         config["absorber"] = {"thickness_m": args.absorber[0], "eta_max": args.absorber[1]}
+    if starter_s is not None:
+        config["modal_starters"] = {"sources": B, "modes": int(len(kappa)), "seconds": starter_s,
+                                    "note": "FP64 eigendecomposition on the device, outside the timed region"}
     plain = None
     if args.plain_steps > 0:
         plain = plain_vs_fused(ssp, s, args.plain_steps)

@@ -175,20 +175,20 @@ ssp_status ssp_set_profile_analytic(ssp_plan *plan, const ssp_env *env);
  * series' convergence radius, is reported as SSP_E_DIVERGED by the march). */
 ssp_status ssp_set_absorber(ssp_plan *plan, const double *eta);
 
-/* Normal-mode starter (Sec. 3.2): u(0, z) = sqrt(2 pi) sum_m Psi_m(zs) Psi_m(z)/sqrt(kappa_m)
- * for a point source at depth zs in (0, H), with the mode functions Psi_m (unit L2 norm over
- * depth) and horizontal wavenumbers kappa_m of d_z^2 Psi + (k^2(z) - kappa^2) Psi = 0, i.e.
- * of the plan's own vertical operator: k0^2 (1 + X) Psi = kappa^2 Psi.  X is formed densely
- * in the sine basis in FP64 on the device and diagonalised there (rocSOLVER dsyevd; three
- * Nz x Nz FP64 matrices of device memory during the call).  Modes: the propagating ones
- * (kappa^2 > 0), lowest first, at most max_modes of them (max_modes <= 0: all).  c [Nz] is
- * the sound speed on the plan's grid (m/s, finite, > 0).  Outputs: psi0 [Nz] complex (re,
- * im doubles; the starter is real), kappa [Nz] or NULL (the modes' kappa_m, decreasing),
- * n_modes or NULL.  Dirichlet plans with Nz <= 16384 only (SSP_E_UNIMPL otherwise);
- * SSP_E_DEVICE if the eigensolver fails.  Synchronous; the plan's field is not touched
- * (pass psi0 to ssp_set_field or ssp_march). */
-ssp_status ssp_modal_starter(ssp_plan *plan, const double *c, double zs, int max_modes,
-                             double *psi0, double *kappa, int *n_modes);
+/* Normal-mode starters (Sec. 3.2): u(0, z) = sqrt(2 pi) sum_m Psi_m(zs) Psi_m(z)/sqrt(kappa_m)
+ * for point sources at depths zs[0..nsrc-1] in (0, H), with the mode functions Psi_m (unit L2
+ * norm over depth) and horizontal wavenumbers kappa_m of d_z^2 Psi + (k^2(z) - kappa^2) Psi = 0,
+ * i.e. of the plan's own vertical operator: k0^2 (1 + X) Psi = kappa^2 Psi.  X is formed
+ * densely in the sine basis in FP64 on the device and diagonalised there once for all sources
+ * (rocSOLVER dsyevd; three Nz x Nz FP64 matrices of device memory during the call).  Modes:
+ * the propagating ones (kappa^2 > 0), lowest first, at most max_modes of them (max_modes <= 0:
+ * all).  c [Nz] is the sound speed on the plan's grid (m/s, finite, > 0).  Outputs: psi0
+ * [nsrc][Nz] complex (re, im doubles; the starters are real), kappa [Nz] or NULL (the modes'
+ * kappa_m, decreasing), n_modes or NULL.  Dirichlet plans with Nz <= 16384 only
+ * (SSP_E_UNIMPL otherwise); SSP_E_DEVICE if the eigensolver fails.  Synchronous; the plan's
+ * field is not touched (pass a starter to ssp_set_field, ssp_march or ssp_to_sine). */
+ssp_status ssp_modal_starter(ssp_plan *plan, const double *c, int nsrc, const double *zs,
+                             int max_modes, double *psi0, double *kappa, int *n_modes);
 
 /* Starter: psi0 [Nz] complex (re, im doubles), physical space.  Resets the step
  * counter to 0 and r to 0.  The field is transformed to the sine basis on the device. */

@@ -564,12 +564,13 @@ ssp_status ssp_plan_info(const ssp_plan *pl, double *sigma, double *k0, double *
     return SSP_OK;
 }
 
-ssp_status ssp_modal_starter(ssp_plan *pl, const double *c, double zs, int max_modes, double *psi0,
-                             double *kappa, int *n_modes) {
-    if (!pl || !c || !psi0) return fail(SSP_E_INVAL, "NULL argument");
+ssp_status ssp_modal_starter(ssp_plan *pl, const double *c, int nsrc, const double *zs, int max_modes,
+                             double *psi0, double *kappa, int *n_modes) {
+    if (!pl || !c || !zs || !psi0 || nsrc < 1) return fail(SSP_E_INVAL, "NULL argument or nsrc < 1");
     if (pl->bc != ssp::kBcDirichlet) return fail(SSP_E_UNIMPL, "the modal starter is built for Dirichlet plans");
     if (pl->N > ssp::kMaxModalNz) return fail(SSP_E_UNIMPL, "Nz above the modal starter's limit (16384)");
-    if (!(zs > 0) || !(zs < pl->H)) return fail(SSP_E_INVAL, "zs must lie inside (0, H)");
+    for (int q = 0; q < nsrc; ++q)
+        if (!(zs[q] > 0) || !(zs[q] < pl->H)) return fail(SSP_E_INVAL, "every zs must lie inside (0, H)");
     const int N = pl->N;
     std::vector<double> v(N);
     for (int m = 0; m < N; ++m) {
@@ -579,14 +580,14 @@ ssp_status ssp_modal_starter(ssp_plan *pl, const double *c, double zs, int max_m
     }
     std::vector<double> u, kap;
     std::string err;
-    const hipError_t e = ssp::modal_starter(N, pl->H, pl->k0, v, zs, max_modes, pl->stream, u, kap, err);
+    const hipError_t e = ssp::modal_starter(N, pl->H, pl->k0, v, nsrc, zs, max_modes, pl->stream, u, kap, err);
     if (e != hipSuccess) {
         if (e == hipErrorOutOfMemory) return fail(SSP_E_NOMEM, err);
         return fail(SSP_E_DEVICE, err);
     }
-    for (int m = 0; m < N; ++m) {
-        psi0[2 * m] = u[m];
-        psi0[2 * m + 1] = 0.0;
+    for (size_t i = 0; i < u.size(); ++i) {
+        psi0[2 * i] = u[i];
+        psi0[2 * i + 1] = 0.0;
     }
     if (kappa)
         for (size_t k = 0; k < kap.size(); ++k) kappa[k] = kap[k];

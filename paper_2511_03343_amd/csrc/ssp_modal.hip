@@ -8,7 +8,8 @@
 // T (rocBLAS dgemm), v on the diagonal (a kernel), then rocSOLVER dsyevd.  The unit
 // eigenvectors y_m give Psi_m(z_n) = y_m[n]/sqrt(dz); Psi_m(zs) comes from the sine-basis
 // coefficients a = T y_m (dgemm over the selected modes) dotted with the basis functions
-// sqrt(2/H) sin(l pi zs/H) at zs (dgemv), so the source need not sit on a grid point.
+// sqrt(2/H) sin(l pi zs/H) at zs (dgemm over the sources), so a source need not sit on a
+// grid point.  One eigendecomposition serves every source depth of the call.
 #include "ssp_modal.h"
 
 #include <rocblas/rocblas.h>
@@ -62,8 +63,8 @@ struct DevBuf {
 
 }  // namespace
 
-hipError_t modal_starter(int N, double depth, double k0, const std::vector<double> &v, double zs,
-                         int max_modes, hipStream_t stream, std::vector<double> &u,
+hipError_t modal_starter(int N, double depth, double k0, const std::vector<double> &v, int nsrc,
+                         const double *zs, int max_modes, hipStream_t stream, std::vector<double> &u,
                          std::vector<double> &kappa, std::string &err) {
 #define MODAL_HIP(x)                                              \
     do {                                                          \
@@ -91,10 +92,11 @@ hipError_t modal_starter(int N, double depth, double k0, const std::vector<doubl
     MODAL_HIP(dv.alloc(N));
     MODAL_HIP(eig.alloc(N));
     MODAL_HIP(off.alloc(N));
-    MODAL_HIP(phi.alloc(N));
-    MODAL_HIP(psz.alloc(N));
-    MODAL_HIP(w.alloc(N));
-    MODAL_HIP(ud.alloc(N));
+    const size_t NS = static_cast<size_t>(N) * nsrc;
+    MODAL_HIP(phi.alloc(NS));
+    MODAL_HIP(psz.alloc(NS));
+    MODAL_HIP(w.alloc(NS));
+    MODAL_HIP(ud.alloc(NS));
     MODAL_HIP(hipMalloc(reinterpret_cast<void **>(&d_info), sizeof(rocblas_int)));
     struct InfoFree {
         rocblas_int *&p;
@@ -103,14 +105,16 @@ hipError_t modal_starter(int N, double depth, double k0, const std::vector<doubl
         }
     } info_free{d_info};
 
-    std::vector<double> hx(N), hphi(N);
+    // x_l, and the basis functions at the sources, [nsrc] columns of [N]
+    std::vector<double> hx(N), hphi(NS);
     for (int l = 1; l <= N; ++l) {
         hx[l - 1] = -std::pow(l * kPiM / (depth * k0), 2);
-        hphi[l - 1] = std::sqrt(2.0 / depth) * std::sin(l * kPiM * zs / depth);
+        for (int q = 0; q < nsrc; ++q)
+            hphi[static_cast<size_t>(q) * N + (l - 1)] = std::sqrt(2.0 / depth) * std::sin(l * kPiM * zs[q] / depth);
     }
     MODAL_HIP(hipMemcpyAsync(x.p, hx.data(), N * sizeof(double), hipMemcpyHostToDevice, stream));
     MODAL_HIP(hipMemcpyAsync(dv.p, v.data(), N * sizeof(double), hipMemcpyHostToDevice, stream));
-    MODAL_HIP(hipMemcpyAsync(phi.p, hphi.data(), N * sizeof(double), hipMemcpyHostToDevice, stream));
+    MODAL_HIP(hipMemcpyAsync(phi.p, hphi.data(), NS * sizeof(double), hipMemcpyHostToDevice, stream));
 
     const dim3 blk(256), grid2((N + 255) / 256, N);
     hipLaunchKernelGGL(k_sine_matrix, grid2, blk, 0, stream, T.p, N);
@@ -148,25 +152,32 @@ hipError_t modal_starter(int N, double depth, double k0, const std::vector<doubl
     while (m < N && lam[N - 1 - m] > -1.0 && (max_modes <= 0 || m < max_modes)) ++m;
     kappa.resize(m);
     for (int k = 0; k < m; ++k) kappa[k] = k0 * std::sqrt(1.0 + lam[N - 1 - k]);
-    u.assign(N, 0.0);
+    u.assign(NS, 0.0);
     if (m > 0) {
         const double *Y = X.p + static_cast<size_t>(N - m) * N;  // columns N-m .. N-1
-        // sine coefficients of the selected modes, A = T Y (into D), and Psi_m(zs) = A^T phi
+        // sine coefficients of the selected modes, A = T Y (into D), and
+        // Psi_m(zs_q) = (A^T Phi)[m][q]
         MODAL_LIB(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, m, N, &one, T.p, N,
                                 Y, N, &zero, D.p, N));
-        MODAL_LIB(rocblas_dgemv(h, rocblas_operation_transpose, N, m, &one, D.p, N, phi.p, 1, &zero, psz.p, 1));
-        std::vector<double> ps(m), wt(m);
-        MODAL_HIP(hipMemcpyAsync(ps.data(), psz.p, m * sizeof(double), hipMemcpyDeviceToHost, stream));
+        MODAL_LIB(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, m, nsrc, N, &one,
+                                D.p, N, phi.p, N, &zero, psz.p, m));
+        const size_t MS = static_cast<size_t>(m) * nsrc;
+        std::vector<double> ps(MS), wt(MS);
+        MODAL_HIP(hipMemcpyAsync(ps.data(), psz.p, MS * sizeof(double), hipMemcpyDeviceToHost, stream));
         MODAL_HIP(hipStreamSynchronize(stream));
         const double dz = depth / (N + 1);
-        for (int c = 0; c < m; ++c) {
-            // column c of the block is mode m-1-c (ascending eigenvalues)
-            const double kap = kappa[m - 1 - c];
-            wt[c] = std::sqrt(2.0 * kPiM) * ps[c] / (std::sqrt(dz) * std::sqrt(kap));
-        }
-        MODAL_HIP(hipMemcpyAsync(w.p, wt.data(), m * sizeof(double), hipMemcpyHostToDevice, stream));
-        MODAL_LIB(rocblas_dgemv(h, rocblas_operation_none, N, m, &one, Y, N, w.p, 1, &zero, ud.p, 1));
-        MODAL_HIP(hipMemcpyAsync(u.data(), ud.p, N * sizeof(double), hipMemcpyDeviceToHost, stream));
+        for (int q = 0; q < nsrc; ++q)
+            for (int c = 0; c < m; ++c) {
+                // column c of the block is mode m-1-c (ascending eigenvalues)
+                const double kap = kappa[m - 1 - c];
+                const size_t o = static_cast<size_t>(q) * m + c;
+                wt[o] = std::sqrt(2.0 * kPiM) * ps[o] / (std::sqrt(dz) * std::sqrt(kap));
+            }
+        MODAL_HIP(hipMemcpyAsync(w.p, wt.data(), MS * sizeof(double), hipMemcpyHostToDevice, stream));
+        // U = Y W: [N][nsrc]
+        MODAL_LIB(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, nsrc, m, &one, Y, N,
+                                w.p, m, &zero, ud.p, N));
+        MODAL_HIP(hipMemcpyAsync(u.data(), ud.p, NS * sizeof(double), hipMemcpyDeviceToHost, stream));
         MODAL_HIP(hipStreamSynchronize(stream));
     }
     return hipSuccess;

@@ -95,7 +95,7 @@ def lib() -> C.CDLL:
             "ssp_set_profile": (S, [_VP, C.c_int, C.c_int, _DP]),
             "ssp_set_profile_analytic": (S, [_VP, C.POINTER(ssp_env)]),
             "ssp_set_absorber": (S, [_VP, _DP]),
-            "ssp_modal_starter": (S, [_VP, _DP, C.c_double, C.c_int, _DP, _DP, C.POINTER(C.c_int)]),
+            "ssp_modal_starter": (S, [_VP, _DP, C.c_int, _DP, C.c_int, _DP, _DP, C.POINTER(C.c_int)]),
             "ssp_set_field": (S, [_VP, _DP]),
             "ssp_get_field": (S, [_VP, _DP]),
             "ssp_march": (S, [_VP, _DP, C.c_int, _DP, _FP, C.POINTER(ssp_stats)]),
@@ -226,15 +226,18 @@ def ssp_set_absorber(plan, eta=None):
 
 
 def ssp_modal_starter(plan, c, zs, max_modes=0):
-    """Normal-mode starter for sound speed c [Nz]: (psi0 complex128 [Nz], kappa [modes])."""
+    """Normal-mode starters for sound speed c [Nz] and source depth(s) zs (a number or a
+    sequence): (psi0 complex128 [Nz] or [nsrc][Nz], kappa [modes])."""
     c = np.ascontiguousarray(c, dtype=np.float64)
     nz = c.shape[0]
-    out = np.zeros(nz, dtype=np.complex128)
+    single = np.ndim(zs) == 0
+    zarr = np.ascontiguousarray(np.atleast_1d(zs), dtype=np.float64)
+    out = np.zeros((len(zarr), nz), dtype=np.complex128)
     kap = np.zeros(nz, dtype=np.float64)
     n = C.c_int(0)
-    _check(lib().ssp_modal_starter(plan, _dp(c), float(zs), int(max_modes), _dp(out.view(np.float64)),
-                                   _dp(kap), C.byref(n)))
-    return out, kap[:n.value].copy()
+    _check(lib().ssp_modal_starter(plan, _dp(c), len(zarr), _dp(zarr), int(max_modes),
+                                   _dp(out.view(np.float64)), _dp(kap), C.byref(n)))
+    return (out[0] if single else out), kap[:n.value].copy()
 
 
 def ssp_set_field(plan, psi0, nz):

@@ -127,3 +127,22 @@ def test_first_experiment_march_from_the_modal_starter(ssp, gpu):
     _report("E1 march", status=st, relL2=f"{err.max():.3e}", max_dTL=f"{dtl.max():.3e}",
             not_converged=stats["not_converged"])
     assert err.max() <= 1e-4 and dtl.max() <= 0.1
+
+
+def test_modal_starters_for_several_sources(ssp, gpu):
+    # one eigendecomposition, several source depths (one of them on a grid point)
+    nz, H, f, c0 = 800, 4000.0, 60.0, 1500.0
+    z = W.depth_grid(nz, H)
+    c = W.munk(z)
+    zs = np.array([250.0, 1100.0, z[401], 3700.0])
+    pl = ssp.ssp_plan_create(nz, H, f, c0, 25.0, 4, 8, 1e-10)
+    try:
+        got, kap = ssp.ssp_modal_starter(pl, c, zs)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    assert got.shape == (len(zs), nz)
+    for q, zq in enumerate(zs):
+        ref = modal_starter(nz, H, f, c0, c, zq)
+        err = np.linalg.norm(got[q] - ref) / np.linalg.norm(ref)
+        _report(f"modal source {zq:.1f}", relL2=f"{err:.3e}")
+        assert err < 1e-8

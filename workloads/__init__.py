@@ -176,6 +176,16 @@ class Solve:
         return self.nz * self.nsteps
 
 
+def first_experiment(nsteps: int = 250, zs: float = 1100.0, nz: int = 8001) -> Solve:
+    """Sec. 4.1's range-independent set-up: Munk profile in a 4 km waveguide, source at
+    1100 m, 8001 depth points, range step 100 m, [4/4] Pade at 100 Hz, the series cut at
+    M = 2 terms (the paper's largest M of the experiment; tol never reached), TL every
+    10 steps (1 km).  The starter of the experiment is the normal-mode starter; starter()
+    returns the Gaussian one."""
+    return Solve(nz=nz, depth=4000.0, freq=100.0, c0=1500.0, dr=100.0, pade_order=4,
+                 neumann_max=2, tol=1e-10, nsteps=nsteps, zs=zs, env="munk", out_every=10)
+
+
 def homogeneous_waveguide(nsteps: int = 1000, zs: float = 50.0) -> Solve:
     """Range-independent homogeneous waveguide: H = 200 m, c = c0 = 1500 m/s, 100 Hz,
     Nz = 256, rotated [4/4] Pade (alpha = pi/16), dr = 5 m, V = 0."""
