@@ -286,7 +286,8 @@ def run_device_batch(args, ssp, torch, stream, dev):
             "traffic": measured_traffic(args.workload, B, args.chunk, args.bc)
             if args.absorber is None else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel": f"k_march<{P}, {layout}> ({threads} threads per workgroup)",
+            "kernel": (f"k_march_direct<{P}, {layout}>" if (s.bc == "periodic" and P == s.nz)
+                       else f"k_march<{P}, {layout}>") + f" ({threads} threads per workgroup)",
             "avg_launch_ms": 1e3 * sum(launch_s) / len(launch_s),
             "steps_per_launch": args.chunk,
             "neumann_terms_per_solve_step": stats["terms"] / B / args.chunk}

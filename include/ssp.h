@@ -108,7 +108,10 @@ typedef struct {
  *                     the norms of e u (trapezoidal weights)
  *   SSP_BC_PERIODIC   u(0) = u(H);  z_n = n H/Nz, n = 0..Nz-1;  orthonormal DFT (forward
  *                     e^{-2 pi i l n/Nz}/sqrt(Nz)), basis e^{2 pi i l' z/H}, l' = l for
- *                     l <= Nz/2 and l - Nz above
+ *                     l <= Nz/2 and l - Nz above.  Nz a power of two in [128, 16384]: the
+ *                     transforms are direct FFTs of length Nz (else chirp-z ones of length
+ *                     >= 2 Nz - 1); such plans run the fused kernel in its autotuned layout
+ *                     only (SSP_OPT_VARIANT is ignored, SSP_OPT_ENGINE = 1 gives SSP_E_UNIMPL)
  * Every basis function is an eigenfunction of d_z^2 (eigenvalue -kappa_l^2, kappa_l = l pi/H
  * or 2 pi l'/H), which makes the isovelocity operator of every Pade term diagonal.  The
  * coefficient-space field kept on the device ("sine basis" below) is that of the plan's

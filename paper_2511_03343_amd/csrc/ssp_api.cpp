@@ -193,8 +193,8 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     if (!ssp::fft_length_supported(tab.P)) return fail(SSP_E_UNIMPL, "unsupported FFT length");
     free_tables(pl);
     const int N = pl->N, P = tab.P, p = ps.p;
-    HIP_TRY(dev_alloc(&pl->d_k1, P));
-    HIP_TRY(dev_alloc(&pl->d_k2, P));
+    HIP_TRY(dev_alloc(&pl->d_k1, tab.k1.size() / 2));   // [P], none for direct transforms
+    HIP_TRY(dev_alloc(&pl->d_k2, tab.k2.size() / 2));
     HIP_TRY(dev_alloc(&pl->d_tw, tab.twiddle.size()));
     HIP_TRY(dev_alloc(&pl->d_dmod, N));
     HIP_TRY(dev_alloc(&pl->d_post, N));
@@ -210,8 +210,8 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     if (!tab.k1i.empty()) HIP_TRY(upload(pl->d_k1i, tab.k1i));
     if (!tab.k2i.empty()) HIP_TRY(upload(pl->d_k2i, tab.k2i));
     if (!tab.postf.empty()) HIP_TRY(upload(pl->d_postf, tab.postf));
-    HIP_TRY(upload(pl->d_k1, tab.k1));
-    HIP_TRY(upload(pl->d_k2, tab.k2));
+    if (!tab.k1.empty()) HIP_TRY(upload(pl->d_k1, tab.k1));
+    if (!tab.k2.empty()) HIP_TRY(upload(pl->d_k2, tab.k2));
     HIP_TRY(upload(pl->d_tw, tab.twiddle));
     HIP_TRY(upload(pl->d_dmod, tab.dmod));
     HIP_TRY(upload(pl->d_post, tab.post));
@@ -229,6 +229,7 @@ ssp_status build_plan_tables(ssp_plan *pl) {
 
 // Engine layout of the plan's march: the option if set, else the autotuned choice.
 int effective_variant(const ssp_plan *pl) {
+    if (pl->tab.direct) return ssp::direct_variant(pl->P);  // one layout per direct length
     int v = pl->variant_opt;
     if (v < 0) {
         int lg = 0;
@@ -274,6 +275,7 @@ ssp::SolveDesc base_desc(const ssp_plan *pl) {
     for (int i = 0; i < 8; ++i) d.env[i] = pl->env[i];
     d.out_every = pl->out_every;
     d.variant = effective_variant(pl);
+    d.direct = pl->tab.direct ? 1 : 0;
     return d;
 }
 
@@ -317,7 +319,7 @@ ssp_status set_field_internal(ssp_plan *pl, const double *psi0) {
                            pl->stream));
     ssp::SolveDesc d = base_desc(pl);
     HIP_TRY(hipMemcpyAsync(pl->d_desc, &d, sizeof(d), hipMemcpyHostToDevice, pl->stream));
-    HIP_TRY(ssp::launch_transform(pl->P, 1, pl->d_desc, 1, pl->d_field, pl->d_field, nullptr,
+    HIP_TRY(ssp::launch_transform(pl->P, pl->tab.direct, 1, pl->d_desc, 1, pl->d_field, pl->d_field, nullptr,
                                   pl->stream));
     long long zero = 0;
     HIP_TRY(hipMemcpyAsync(pl->d_step, &zero, sizeof(zero), hipMemcpyHostToDevice, pl->stream));
@@ -694,7 +696,7 @@ ssp_status ssp_get_field(const ssp_plan *cpl, double *psi) {
     if (st != SSP_OK) return st;
     ssp::SolveDesc d = base_desc(pl);
     HIP_TRY(hipMemcpyAsync(pl->d_desc, &d, sizeof(d), hipMemcpyHostToDevice, pl->stream));
-    HIP_TRY(ssp::launch_transform(pl->P, 2, pl->d_desc, 1, pl->d_field, pl->d_out_fld, pl->d_step,
+    HIP_TRY(ssp::launch_transform(pl->P, pl->tab.direct, 2, pl->d_desc, 1, pl->d_field, pl->d_out_fld, pl->d_step,
                                   pl->stream));
     std::vector<float> h(2 * static_cast<size_t>(pl->N));
     HIP_TRY(hipMemcpyAsync(h.data(), pl->d_out_fld, h.size() * sizeof(float), hipMemcpyDeviceToHost,
@@ -779,11 +781,14 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     // (the family: lengths of the 1024-thread kernel in their default layout)
-    auto fam = [](const ssp::SolveDesc &d) { return ssp::march_family_member(d.P) && d.variant == 0; };
+    auto fam = [](const ssp::SolveDesc &d) {
+        return ssp::march_family_member(d.P) && d.variant == 0 && !d.direct;
+    };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         const ssp::SolveDesc &a = descs[x], &b = descs[y];
         if (fam(a) != fam(b)) return fam(a);
         if (a.P != b.P) return a.P > b.P;
+        if (a.direct != b.direct) return a.direct < b.direct;
         if (a.variant != b.variant) return a.variant < b.variant;
         return a.nsteps > b.nsteps;
     });
@@ -795,6 +800,9 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
         if (n == 1 && owner->engine == 1) {
             // plain form: one kernel per stage, one solve
             ssp_plan *pl = owner;
+            if (pl->tab.direct)
+                return fail(SSP_E_UNIMPL, "the plain form runs chirp-z transforms only; periodic plans with a "
+                                          "power-of-two grid run the fused kernel");
             if (!pl->d_plain) {
                 HIP_TRY(dev_alloc(&pl->d_plain, 2 * static_cast<size_t>(pl->N)));
                 HIP_TRY(hipMalloc(reinterpret_cast<void **>(&pl->d_plain_flags), ssp::plain_state_bytes()));
@@ -805,7 +813,7 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
             z.step_index = idx;
             HIP_TRY(hipMemcpyAsync(pl->d_stats, &z, sizeof(z), hipMemcpyHostToDevice, stream));
             HIP_TRY(ssp::plain_march(sorted[0], owner->d_descs, nsteps, pl->d_plain, pl->d_plain_flags, stream));
-            if (sorted[0].snap) HIP_TRY(ssp::launch_output(sorted[0].P, owner->d_descs, 1, sorted[0].nout, stream));
+            if (sorted[0].snap) HIP_TRY(ssp::launch_output(sorted[0].P, false, owner->d_descs, 1, sorted[0].nout, stream));
         } else {
             // launch groups: the 1024-thread lengths together (one launch), then one per other
             // length; each group's march is followed by its output launches (one per length)
@@ -817,7 +825,8 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
             else nf = 0;
             for (int start = nf; start < n;) {
                 int end = start;
-                while (end < n && sorted[end].P == sorted[start].P && sorted[end].variant == sorted[start].variant)
+                while (end < n && sorted[end].P == sorted[start].P && sorted[end].variant == sorted[start].variant &&
+                       sorted[end].direct == sorted[start].direct)
                     ++end;
                 groups.push_back({start, end, false});
                 start = end;
@@ -838,14 +847,16 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
                 if (G.family)
                     HIP_TRY(ssp::launch_march_family(owner->d_descs + G.start, G.end - G.start, gmax, gs));
                 else
-                    HIP_TRY(ssp::launch_march(sorted[G.start].P, sorted[G.start].variant, owner->d_descs + G.start,
-                                              G.end - G.start, gmax, gs));
+                    HIP_TRY(ssp::launch_march(sorted[G.start].P, sorted[G.start].variant, sorted[G.start].direct != 0,
+                                              owner->d_descs + G.start, G.end - G.start, gmax, gs));
                 for (int start = G.start; start < G.end;) {
                     int end = start;
-                    while (end < G.end && sorted[end].P == sorted[start].P) ++end;
+                    while (end < G.end && sorted[end].P == sorted[start].P && sorted[end].direct == sorted[start].direct)
+                        ++end;
                     int rows = 0;
                     for (int k = start; k < end; ++k) rows = std::max(rows, sorted[k].snap ? sorted[k].nout : 0);
-                    HIP_TRY(ssp::launch_output(sorted[start].P, owner->d_descs + start, end - start, rows, gs));
+                    HIP_TRY(ssp::launch_output(sorted[start].P, sorted[start].direct != 0, owner->d_descs + start,
+                                               end - start, rows, gs));
                     start = end;
                 }
             }
@@ -965,8 +976,10 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
         // record the launches once; the descriptors above stay valid for later replays
         drop_graph(pl);
         HIP_TRY(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = ssp::launch_march(pl->P, effective_variant(pl), pl->d_descs, B, nsteps, pl->stream);
-        if (e == hipSuccess && d_tl && nout > 0) e = ssp::launch_output(pl->P, pl->d_descs, B, nout, pl->stream);
+        hipError_t e = ssp::launch_march(pl->P, effective_variant(pl), pl->tab.direct, pl->d_descs, B, nsteps,
+                                         pl->stream);
+        if (e == hipSuccess && d_tl && nout > 0)
+            e = ssp::launch_output(pl->P, pl->tab.direct, pl->d_descs, B, nout, pl->stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(pl->stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -978,8 +991,8 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
         pl->graph_key = key;
         HIP_TRY(hipGraphLaunch(pl->graph_exec, pl->stream));
     } else {
-        HIP_TRY(ssp::launch_march(pl->P, effective_variant(pl), pl->d_descs, B, nsteps, pl->stream));
-        if (d_tl && nout > 0) HIP_TRY(ssp::launch_output(pl->P, pl->d_descs, B, nout, pl->stream));
+        HIP_TRY(ssp::launch_march(pl->P, effective_variant(pl), pl->tab.direct, pl->d_descs, B, nsteps, pl->stream));
+        if (d_tl && nout > 0) HIP_TRY(ssp::launch_output(pl->P, pl->tab.direct, pl->d_descs, B, nout, pl->stream));
     }
     pl->step_index += nsteps;
     return SSP_OK;
@@ -989,7 +1002,7 @@ ssp_status ssp_to_sine(ssp_plan *pl, int B, const void *d_phys, void *d_sine) {
     if (!pl || B <= 0 || !d_phys || !d_sine) return fail(SSP_E_INVAL, "bad argument");
     ssp::SolveDesc d = base_desc(pl);
     HIP_TRY(hipMemcpyAsync(pl->d_desc, &d, sizeof(d), hipMemcpyHostToDevice, pl->stream));
-    HIP_TRY(ssp::launch_transform(pl->P, 1, pl->d_desc, B, static_cast<const float2 *>(d_phys),
+    HIP_TRY(ssp::launch_transform(pl->P, pl->tab.direct, 1, pl->d_desc, B, static_cast<const float2 *>(d_phys),
                                   static_cast<float2 *>(d_sine), nullptr, pl->stream));
     return SSP_OK;
 }
@@ -998,7 +1011,7 @@ ssp_status ssp_from_sine(ssp_plan *pl, int B, const void *d_sine, const void *d_
     if (!pl || B <= 0 || !d_sine || !d_step || !d_phys) return fail(SSP_E_INVAL, "bad argument");
     ssp::SolveDesc d = base_desc(pl);
     HIP_TRY(hipMemcpyAsync(pl->d_desc, &d, sizeof(d), hipMemcpyHostToDevice, pl->stream));
-    HIP_TRY(ssp::launch_transform(pl->P, 2, pl->d_desc, B, static_cast<const float2 *>(d_sine),
+    HIP_TRY(ssp::launch_transform(pl->P, pl->tab.direct, 2, pl->d_desc, B, static_cast<const float2 *>(d_sine),
                                   static_cast<float2 *>(d_phys), static_cast<const long long *>(d_step),
                                   pl->stream));
     return SSP_OK;
@@ -1008,7 +1021,7 @@ ssp_status ssp_dst_device(ssp_plan *pl, int B, const void *d_in, void *d_out) {
     if (!pl || B <= 0 || !d_in || !d_out) return fail(SSP_E_INVAL, "bad argument");
     ssp::SolveDesc d = base_desc(pl);
     HIP_TRY(hipMemcpyAsync(pl->d_desc, &d, sizeof(d), hipMemcpyHostToDevice, pl->stream));
-    HIP_TRY(ssp::launch_transform(pl->P, 0, pl->d_desc, B, static_cast<const float2 *>(d_in),
+    HIP_TRY(ssp::launch_transform(pl->P, pl->tab.direct, 0, pl->d_desc, B, static_cast<const float2 *>(d_in),
                                   static_cast<float2 *>(d_out), nullptr, pl->stream));
     return SSP_OK;
 }

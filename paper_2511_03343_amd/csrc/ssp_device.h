@@ -57,11 +57,13 @@ struct SolveDesc {
     int nout;                   // output rows available in snap / tl_out / fld_out
     int nsteps;                 // range steps of this solve in the launch
     int variant;                // engine layout of the march (host-side grouping only)
+    int direct;                 // 1: periodic plan with P = Nz, direct FFTs (host-side grouping)
 };
 
 // Launch the fused persistent march: one workgroup per descriptor, all with the same FFT
 // length P, each marching its own descriptor's nsteps (nsteps here: the largest, 0 = no
-// launch).  Returns hipSuccess or the launch error.
+// launch).  direct: periodic plans whose grid length is the FFT length (direct FFTs
+// instead of chirp-z cores; P <= 16384).  Returns hipSuccess or the launch error.
 // Scratch elements (complex) per solve behind SolveDesc::work: work, pot, wacc, xs.
 constexpr int kWorkPerSolve = 5;
 inline void set_work(SolveDesc &d, float2 *base) {
@@ -71,8 +73,10 @@ inline void set_work(SolveDesc &d, float2 *base) {
     d.xs = base + 3 * static_cast<size_t>(d.N);
 }
 
-hipError_t launch_march(int P, int variant, const SolveDesc *d_descs, int nsolves, int nsteps,
+hipError_t launch_march(int P, int variant, bool direct, const SolveDesc *d_descs, int nsolves, int nsteps,
                         hipStream_t stream);
+// Layout of the direct-transform march of length P (the autotuned layout of that length).
+int direct_variant(int P);
 
 // Engine layouts of the march kernel: variant 0 is the default; variants 1 and 2 (where they
 // exist) use other thread counts, i.e. other radices for the first and last FFT passes
@@ -91,7 +95,7 @@ hipError_t launch_march_family(const SolveDesc *d_descs, int nsolves, int nsteps
 // starts at step n0 are the steps (n0/out_every + 1) out_every + row out_every; the step at
 // the start is recovered from the solve's statistics (step_index - steps_done), so stats
 // must be present whenever snapshots are.
-hipError_t launch_output(int P, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream);
+hipError_t launch_output(int P, bool direct, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream);
 
 // Batched transforms over B vectors of a plan's grid (tables from desc, one desc on the
 // device shared by the whole batch).
@@ -99,7 +103,7 @@ hipError_t launch_output(int P, const SolveDesc *d_descs, int nsolves, int nout,
 //           (orthonormal DST-I for Dirichlet boundaries)
 //   mode 1: physical -> modulated coefficient representation
 //   mode 2: modulated coefficient representation -> physical field with carrier at step[b]
-hipError_t launch_transform(int P, int mode, const SolveDesc *d_desc, int B, const float2 *in,
+hipError_t launch_transform(int P, bool direct, int mode, const SolveDesc *d_desc, int B, const float2 *in,
                             float2 *out, const long long *step, hipStream_t stream);
 
 // Plain form: one kernel per stage (start, Neumann half-term, finish, commit) for the single

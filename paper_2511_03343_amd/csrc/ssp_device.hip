@@ -31,6 +31,7 @@
 // that no fixed rounding of a table enters every step; residual norms in FP64; carrier
 // phase in FP64.
 #include "ssp_device.h"
+#include "ssp_tuned.h"
 
 #include <math.h>
 
@@ -577,6 +578,21 @@ using ECfg = Cfg<eng_key<P, V>()>;
 // lengths, the lower half otherwise (positions t + i T >= P/2 are always beyond N).
 template <int P, int V>
 constexpr int live_elems() { return eng_len<P>() == P ? ECfg<P, V>::RT / 2 : ECfg<P, V>::RT; }
+// ... and for the direct transform of a periodic grid of P points, all of them
+template <int P, int V, bool DIRECT>
+constexpr int live_of() { return DIRECT ? ECfg<P, V>::RT : live_elems<P, V>(); }
+
+// The transform of a periodic plan whose grid length is itself an engine length: the
+// forward FFT (grid -> coefficients) or the unnormalised inverse FFT of the P points in
+// registers, natural order in and out; the 1/sqrt(P) factors sit in the plan's modulation
+// tables.  The opening barrier separates it from the previous transform's LDS reads.
+template <int EK>
+__device__ __forceinline__ void direct_core(float2 (&x)[Cfg<EK>::RT], const LdsBufs &L,
+                                            const Twiddles<EK> &tw, bool fwd) {
+    __syncthreads();
+    if (fwd) fft<EK, false, 0>(x, L, tw);
+    else fft<EK, true, 0>(x, L, tw);
+}
 
 // One transform core for convolution length P (positions 0 .. eng_len-1 distributed as in
 // the engine), with the chirp-window spectra k1, k2 of the direction it runs in.  For P above kMaxEngine the odd-frequency half needs the input again after the
@@ -727,9 +743,9 @@ __device__ __forceinline__ float eddy_correction(const SolveDesc &d, float vm, f
 // A = v (.) dmod at the thread's positions (zero at positions >= N); v of global step n,
 // plus i eta when the plan has an absorbing layer (complex absorbing potential).
 // Written to registers (A) when the kernel keeps it there, else to the solve's pot array.
-template <int P, int V, bool IN_REGS>
+template <int P, int V, bool IN_REGS, bool DIRECT = false>
 __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, float2 *A) {
-    constexpr int T = ECfg<P, V>::T, RL = live_elems<P, V>();
+    constexpr int T = ECfg<P, V>::T, RL = live_of<P, V, DIRECT>();
     const int N = d.N;
     long long row = 0;
     if (d.prof_mode == PROF_TABLE_STEPS) {
@@ -757,12 +773,13 @@ __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, 
 
 // ----------------------------------------------------------------------------- march
 // One workgroup marches one solve through nsteps range steps.
-template <int P, int V>
+template <int P, int V, bool DIRECT = false>
 __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float4 *lds_raw, double *red) {
     constexpr int T = ECfg<P, V>::T, RT = ECfg<P, V>::RT;
     constexpr int EK = eng_key<P, V>();
-    // elements that can hold data (the lower half for unsplit lengths); the others stay zero
-    constexpr int RL = live_elems<P, V>();
+    // elements that can hold data (the lower half for unsplit chirp-z lengths, all for the
+    // direct transform); the others stay zero
+    constexpr int RL = live_of<P, V, DIRECT>();
     // the Neumann multiplier stays in registers for up to 8 live elements per thread below
     // 1024 threads (those layouts run two waves per SIMD, so 256 registers per lane)
     constexpr bool kBInRegs = (RL <= 8) && (T < 1024);
@@ -791,7 +808,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     long long n = *d.step;
     // outputs of this launch: steps out_base, out_base + out_every, ... (row = slot)
     const long long out_base = d.out_every > 0 ? (n / d.out_every + 1) * d.out_every : 0;
-    if (d.prof_mode == PROF_TABLE_FIXED) load_potential<P, V, kAInRegs>(d, n + 1, A);
+    if (d.prof_mode == PROF_TABLE_FIXED) load_potential<P, V, kAInRegs, DIRECT>(d, n + 1, A);
 
     long long terms = 0, done = 0;
     int max_used = 0, notconv = 0, status = kOK;
@@ -799,7 +816,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
 
     for (int s = 0; s < nsteps; ++s) {
         const long long nn = n + 1;
-        if (d.prof_mode != PROF_TABLE_FIXED) load_potential<P, V, kAInRegs>(d, nn, A);
+        if (d.prof_mode != PROF_TABLE_FIXED) load_potential<P, V, kAInRegs, DIRECT>(d, nn, A);
         bool bad = false;
         for (int j = 0; j < p; ++j) {
             const float2 *cur = (j == 0) ? d.field : d.work;
@@ -832,7 +849,8 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
             for (int h = 0; h < 2 * nmax; ++h) {
                 // even h: coefficients -> grid (inverse direction); odd h: grid -> coefficients
                 const bool fwd = (h & 1) != 0;
-                dst_core<P, V, kKeepGlobal>(a, L, tw, d, d.xs, fwd ? d.k1 : d.k1i, fwd ? d.k2 : d.k2i);
+                if constexpr (DIRECT) direct_core<EK>(a, L, tw, fwd);
+                else dst_core<P, V, kKeepGlobal>(a, L, tw, d, d.xs, fwd ? d.k1 : d.k1i, fwd ? d.k2 : d.k2i);
                 if ((h & 1) == 0) {
 #pragma unroll
                     for (int i = 0; i < RL; ++i) {
@@ -953,6 +971,16 @@ __global__ __launch_bounds__((ECfg<P, V>::T), (ECfg<P, V>::MINW)) void k_march(c
     march_body<P, V>(descs[blockIdx.x], descs[blockIdx.x].nsteps, lds_raw, red);
 }
 
+// The same march for periodic plans whose grid length is an engine length (P = Nz): the
+// transforms are direct FFTs instead of chirp-z cores.
+template <int P, int V>
+__global__ __launch_bounds__((ECfg<P, V>::T), (ECfg<P, V>::MINW)) void k_march_direct(
+    const SolveDesc *__restrict__ descs, int nsteps) {
+    __shared__ float4 lds_raw[lds_words<eng_key<P, V>()>()];
+    __shared__ double red[2 * (ECfg<P, V>::T / 64)];
+    march_body<P, V, true>(descs[blockIdx.x], descs[blockIdx.x].nsteps, lds_raw, red);
+}
+
 // Solves of uneven length in one launch: every length that runs with 1024-thread workgroups
 // (P = 8192, 16384, 32768); each workgroup takes the code path of its own descriptor's P.
 constexpr int kFamilyT = 1024;
@@ -973,7 +1001,7 @@ __global__ __launch_bounds__(kFamilyT) void k_march_family(const SolveDesc *__re
 }
 
 // ----------------------------------------------------------------------------- transforms
-template <int P>
+template <int P, bool DIRECT>
 __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_transform(const SolveDesc *__restrict__ desc, int mode,
                                                          const float2 *__restrict__ in, float2 *out,
                                                          const long long *__restrict__ step) {
@@ -996,7 +1024,8 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_transform(const SolveDesc *
         }
         x[i] = v;
     }
-    dst_core<P, 0, false>(x, L, tw, d, nullptr, mode == 2 ? d.k1i : d.k1, mode == 2 ? d.k2i : d.k2);
+    if constexpr (DIRECT) direct_core<eng_key<P, 0>()>(x, L, tw, mode != 2);
+    else dst_core<P, 0, false>(x, L, tw, d, nullptr, mode == 2 ? d.k1i : d.k1, mode == 2 ? d.k2i : d.k2);
     float2 car = make_float2(1.f, 0.f);
     if (mode == 2) car = carrier(d.sigma, step[blockIdx.x]);
 #pragma unroll
@@ -1013,7 +1042,7 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_transform(const SolveDesc *
 // Output rows: blockIdx.x = solve * nout + row.  Snapshot (sine basis) -> physical field
 // with the carrier of its step -> field row (complex64, in place over the snapshot when
 // fld_out == snap) and TL row.
-template <int P>
+template <int P, bool DIRECT>
 __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_output(const SolveDesc *__restrict__ descs, int nout) {
     constexpr int T = ECfg<P, 0>::T, RT = ECfg<P, 0>::RT;
     SSP_LDS_DECL((eng_key<P, 0>()));
@@ -1034,7 +1063,8 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_output(const SolveDesc *__r
         const int pos = tid + i * T;
         x[i] = (pos < N) ? ld2(src, pos) : make_float2(0.f, 0.f);
     }
-    dst_core<P, 0, false>(x, L, tw, d, nullptr, d.k1i, d.k2i);
+    if constexpr (DIRECT) direct_core<eng_key<P, 0>()>(x, L, tw, false);
+    else dst_core<P, 0, false>(x, L, tw, d, nullptr, d.k1i, d.k2i);
     const float2 car = carrier(d.sigma, n);
     const float lr = log10f(static_cast<float>(static_cast<double>(n) * d.dr));
 #pragma unroll
@@ -1239,8 +1269,15 @@ hipError_t plain_march_P(const SolveDesc &hd, const SolveDesc *dd, int nsteps, f
 }
 
 template <int P>
-hipError_t launch_output_P(const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream) {
-    hipLaunchKernelGGL((k_output<P>), dim3(nsolves * nout), dim3(ECfg<P, 0>::T), 0, stream, d_descs, nout);
+hipError_t launch_output_P(bool direct, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream) {
+    if constexpr (P <= kMaxEngine) {
+        if (direct) {
+            hipLaunchKernelGGL((k_output<P, true>), dim3(nsolves * nout), dim3(ECfg<P, 0>::T), 0, stream,
+                               d_descs, nout);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_output<P, false>), dim3(nsolves * nout), dim3(ECfg<P, 0>::T), 0, stream, d_descs, nout);
     return hipGetLastError();
 }
 
@@ -1263,10 +1300,35 @@ hipError_t launch_march_PV(int v, const SolveDesc *d_descs, int nsolves, int nst
 }
 
 template <int P>
-hipError_t launch_transform_P(int mode, const SolveDesc *d_desc, int B, const float2 *in,
+hipError_t launch_transform_P(bool direct, int mode, const SolveDesc *d_desc, int B, const float2 *in,
                               float2 *out, const long long *step, hipStream_t stream) {
-    hipLaunchKernelGGL((k_transform<P>), dim3(B), dim3(ECfg<P, 0>::T), 0, stream, d_desc, mode, in, out, step);
+    if constexpr (P <= kMaxEngine) {
+        if (direct) {
+            hipLaunchKernelGGL((k_transform<P, true>), dim3(B), dim3(ECfg<P, 0>::T), 0, stream, d_desc, mode,
+                               in, out, step);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_transform<P, false>), dim3(B), dim3(ECfg<P, 0>::T), 0, stream, d_desc, mode, in, out,
+                       step);
     return hipGetLastError();
+}
+
+// direct periodic marches run the autotuned layout of their length only
+constexpr int tuned_variant(int P) {
+    int lg = 0;
+    while ((1 << lg) < P) ++lg;
+    return kTunedVariant[lg - 7];
+}
+template <int P>
+hipError_t launch_march_direct_P(const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
+    if constexpr (P <= kMaxEngine) {
+        constexpr int V = variant_exists(P, tuned_variant(P)) ? tuned_variant(P) : 0;
+        hipLaunchKernelGGL((k_march_direct<P, V>), dim3(nsolves), dim3(ECfg<P, V>::T), 0, stream, d_descs, nsteps);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -1307,18 +1369,27 @@ bool fft_length_supported(int P) {
         default: return hipErrorInvalidValue; \
     }
 
-hipError_t launch_march(int P, int variant, const SolveDesc *d_descs, int nsolves, int nsteps,
+hipError_t launch_march(int P, int variant, bool direct, const SolveDesc *d_descs, int nsolves, int nsteps,
                         hipStream_t stream) {
     if (nsolves <= 0 || nsteps <= 0) return hipSuccess;
+    if (direct) {
+#define CALL_D(PP) launch_march_direct_P<PP>(d_descs, nsolves, nsteps, stream)
+        SSP_DISPATCH_P(P, CALL_D)
+#undef CALL_D
+    }
     const int v = engine_variant_exists(P, variant) ? variant : 0;
 #define CALL_M(PP) launch_march_PV<PP>(v, d_descs, nsolves, nsteps, stream)
     SSP_DISPATCH_P(P, CALL_M)
 #undef CALL_M
 }
 
-hipError_t launch_output(int P, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream) {
+int direct_variant(int P) {
+    return (P >= 128 && P <= kMaxEngine && variant_exists(P, tuned_variant(P))) ? tuned_variant(P) : 0;
+}
+
+hipError_t launch_output(int P, bool direct, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream) {
     if (nsolves <= 0 || nout <= 0) return hipSuccess;
-#define CALL_O(PP) launch_output_P<PP>(d_descs, nsolves, nout, stream)
+#define CALL_O(PP) launch_output_P<PP>(direct, d_descs, nsolves, nout, stream)
     SSP_DISPATCH_P(P, CALL_O)
 #undef CALL_O
 }
@@ -1333,10 +1404,10 @@ hipError_t plain_march(const SolveDesc &h_desc, const SolveDesc *d_desc, int nst
 
 size_t plain_state_bytes() { return sizeof(PlainState); }
 
-hipError_t launch_transform(int P, int mode, const SolveDesc *d_desc, int B, const float2 *in,
+hipError_t launch_transform(int P, bool direct, int mode, const SolveDesc *d_desc, int B, const float2 *in,
                             float2 *out, const long long *step, hipStream_t stream) {
     if (B <= 0) return hipSuccess;
-#define CALL_T(PP) launch_transform_P<PP>(mode, d_desc, B, in, out, step, stream)
+#define CALL_T(PP) launch_transform_P<PP>(direct, mode, d_desc, B, in, out, step, stream)
     SSP_DISPATCH_P(P, CALL_T)
 #undef CALL_T
 }

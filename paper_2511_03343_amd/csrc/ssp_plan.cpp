@@ -296,10 +296,13 @@ std::vector<float> window_spectrum(std::vector<cd> w, int P, bool split) {
 }  // namespace
 
 void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, DeviceTables &t) {
-    const int N = nz, P = chirp_fft_length(2 * nz - 1);
+    const int N = nz;
+    const bool direct = bc == kBcPeriodic && N >= 128 && N <= kMaxEngineFFT && (N & (N - 1)) == 0;
+    const int P = direct ? N : chirp_fft_length(2 * nz - 1);
     t.nz = N;
     t.P = P;
     t.bc = bc;
+    t.direct = direct;
     // Every transform kernel is a sum over n of x_n times exp(+-i theta k n) terms, and
     // k n = (k^2 + n^2 - (k-n)^2)/2 = ((k+n)^2 - k^2 - n^2)/2 turns each into a chirp
     // pre-modulation, a convolution (Toeplitz window, k - n) or correlation (Hankel window,
@@ -320,7 +323,11 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
     auto chirp = [&](long long d) { return ch[d < 0 ? -d : d]; };
     const bool split = P > kMaxEngineFFT;
     const int PE = split ? P / 2 : P;
-    {
+    t.k1.clear();
+    t.k2.clear();
+    t.k1i.clear();
+    t.k2i.clear();
+    if (!direct) {
         std::vector<cd> K1(P, 0.0), K2(P, 0.0);
         for (long long d = 1 - N; d <= N - 1; ++d) K1[((d % P) + P) % P] = chirp(d);
         if (bc == kBcDirichlet) {
@@ -332,8 +339,6 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
         }
         t.k1 = window_spectrum(K1, P, split);
         t.k2 = window_spectrum(K2, P, split);
-        t.k1i.clear();
-        t.k2i.clear();
         if (bc == kBcPeriodic) {
             for (long long d = 1 - N; d <= N - 1; ++d) K1[((d % P) + P) % P] = std::conj(chirp(d));
             t.k1i = window_spectrum(K1, P, split);
@@ -361,6 +366,7 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
     //            post_i = conj(c_k) sqrt(2/M)/(2P)
     //   Fourier: pre_f = conj(c_n), post_f = conj(c_k)/(sqrt(N) P); pre_i = c_n,
     //            post_i = c_k/(sqrt(N) P); dmod = 1/(sqrt(N) P)
+    //   Fourier, direct (N an engine length): pre = 1, post = 1/sqrt(N) both ways
     const cd I(0, 1);
     std::vector<cd> dmod(N);
     t.pre.assign(2 * N, 0.f);
@@ -383,13 +389,18 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
             post_f = cb * (e * scale);
             pre_i = cb * e;
             post_i = cb * scale;
-        } else {
+        } else if (!direct) {
             const double scale = 1.0 / (std::sqrt(static_cast<double>(N)) * P);
             const cd c = chirp(m);
             pre_f = std::conj(c);
             post_f = std::conj(c) * scale;
             pre_i = c;
             post_i = c * scale;
+        } else {
+            // forward FFT(x)/sqrt(N), inverse unnormalised IFFT(a)/sqrt(N)
+            const double scale = 1.0 / std::sqrt(static_cast<double>(N));
+            pre_f = pre_i = 1.0;
+            post_f = post_i = scale;
         }
         // (the sine transform's product in the order of its original derivation)
         dmod[m] = bc == kBcDirichlet ? std::conj(chirp(m + 1)) * std::conj(chirp(m + 1)) * I *

@@ -55,6 +55,10 @@ GridSpec grid_spec(int bc, int nz, double depth);
 
 struct DeviceTables {
     int nz = 0, P = 0, bc = kBcDirichlet;
+    // periodic grid whose length is an engine FFT length (a power of two, 128 .. 16384):
+    // the transforms are direct FFTs of length P = nz, no chirp windows; pre = 1 and the
+    // modulations are 1/sqrt(nz)
+    bool direct = false;
     // chirp-z transform of length nz through a cyclic convolution of length P, with the
     // chirp c_d = exp(i pi d^2 / D) (D = 2(nz+1) sine, 2(nz-1) cosine, nz Fourier):
     // [P] complex FP32 spectra of the two chirp windows, Toeplitz c_d (d in [1-nz, nz-1])

@@ -269,3 +269,38 @@ def test_munk_long_range(ssp, gpu, bc):
     ref = oracle_march(s)
     assert st == ref.status
     compare(f"munk long {bc}", fld, tl, ref)
+
+
+@pytest.mark.parametrize("nz,nsteps", [(128, 100), (512, 100), (2048, 50), (8192, 12), (16384, 6)])
+def test_periodic_direct_fft_lengths_vs_oracle(ssp, gpu, nz, nsteps):
+    # periodic grids whose length is a power of two run direct FFTs of length Nz
+    s = with_bc(W.munk_deep(nsteps=nsteps, nz=nz), "periodic")
+    s.out_every = max(1, nsteps // 3)
+    pl = make_plan(ssp, s)
+    try:
+        layout, threads, P = ssp.ssp_plan_engine(pl)
+        assert P == nz
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert st == ref.status
+    compare(f"periodic direct nz={nz}", fld, tl, ref)
+
+
+def test_periodic_direct_rejects_the_plain_form(ssp, gpu):
+    s = with_bc(W.munk_deep(nsteps=2, nz=1024), "periodic")
+    pl = make_plan(ssp, s)
+    try:
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_ENGINE, 1)
+        with pytest.raises(ssp.SspError) as e:
+            ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+        assert e.value.status == ssp.SSP_E_UNIMPL
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    # a periodic grid of another length keeps the chirp-z transform of length >= 2 Nz - 1
+    pl = ssp.ssp_plan_create_bc(1000, 5000.0, 50.0, 1500.0, 25.0, 6, 48, 1e-10, "periodic")
+    try:
+        assert ssp.ssp_plan_engine(pl)[2] == 2048
+    finally:
+        ssp.ssp_plan_destroy(pl)
