@@ -24,6 +24,7 @@ import json
 import math
 import multiprocessing as mp
 import os
+import re
 import sys
 import time
 
@@ -195,6 +196,13 @@ DESCRIPTIONS = {
 }
 
 
+def _describe(workload, nz):
+    text = DESCRIPTIONS[workload]
+    if nz is not None:
+        text = re.sub(r"Nz=[0-9.]+(?:\.\.[0-9]+)?", f"Nz={nz}", text, count=1)
+    return text
+
+
 def make_plan(ssp, s):
     pl = ssp.ssp_plan_create_bc(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max,
                                 s.tol, s.bc)
@@ -299,7 +307,9 @@ def run_device_batch(args, ssp, torch, stream, dev):
             "traffic": measured_traffic(args.workload, B, args.chunk, args.bc)
             if args.absorber is None else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel": (f"k_march_direct<{P}, {layout}>" if (s.bc == "periodic" and P == s.nz)
+            "kernel": (f"k_march_direct<{P}, {layout}, 1>" if (s.bc == "periodic" and P == s.nz)
+                       else f"k_march_direct<{P}, {layout}, 2>"
+                       if (s.bc == "dirichlet" and P == 2 * (s.nz + 1))
                        else f"k_march<{P}, {layout}>") + f" ({threads} threads per workgroup)",
             "avg_launch_ms": 1e3 * sum(launch_s) / len(launch_s),
             "steps_per_launch": args.chunk,
@@ -543,7 +553,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded Munk profile and Gaussian starters)",
-        "config": {"workload": DESCRIPTIONS[args.workload] + (
+        "config": {"workload": _describe(args.workload, args.nz) + (
             f", {args.bc} boundaries (Sec. 3.1)" if args.bc != "dirichlet" else "") + (
             f", bottom absorbing layer {args.absorber[0]:g} m (eta up to {args.absorber[1]:g})"
             if args.absorber else ""), **config},

@@ -100,7 +100,11 @@ typedef struct {
 
 /* Boundary conditions at z = 0 and z = H (Sec. 3.1), each with its grid and transform:
  *   SSP_BC_DIRICHLET  u = 0;  z_n = n H/(Nz+1), n = 1..Nz (interior points);  orthonormal
- *                     DST-I, basis sin(l pi z/H), l = 1..Nz
+ *                     DST-I, basis sin(l pi z/H), l = 1..Nz.  Nz + 1 a power of two with
+ *                     2 (Nz + 1) in [128, 16384]: each DST-I is one FFT of length 2 (Nz + 1)
+ *                     over the odd extension of the data (else chirp-z FFTs of length
+ *                     >= 2 Nz - 1); such plans run the fused kernel as periodic direct
+ *                     plans do (below)
  *   SSP_BC_NEUMANN    d_z u = 0;  z_n = n H/(Nz-1), n = 0..Nz-1 (both boundaries on the
  *                     grid);  basis cos(l pi z/H), l = 0..Nz-1, through the orthonormal DCT-I
  *                     C applied to the grid values with the two boundary values scaled by
@@ -149,8 +153,9 @@ ssp_status ssp_plan_info(const ssp_plan *plan, double *sigma, double *k0, double
                          double *g, double *C, double *d0, double *d);
 int ssp_max_nz(void);
 
-/* Engine of the plan's fused march: layout actually used (0 or 1, see SSP_OPT_VARIANT),
- * threads per workgroup and the chirp-z FFT length P (either pointer may be NULL). */
+/* Engine of the plan's fused march: layout actually used (0, 1 or 2, see SSP_OPT_VARIANT),
+ * threads per workgroup and the FFT length P: chirp-z length, Nz for periodic direct plans,
+ * 2 (Nz + 1) for Dirichlet direct plans (any pointer may be NULL). */
 ssp_status ssp_plan_engine(const ssp_plan *plan, int *variant, int *threads, int *fft_length);
 
 /* Host-only Pade coefficients (Sec. 2; Alg. 1 first step) for sigma = k0 dr, order p and

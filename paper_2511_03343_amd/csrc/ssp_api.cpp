@@ -68,6 +68,7 @@ struct ssp_plan {
     // device tables
     float2 *d_k1 = nullptr, *d_k2 = nullptr, *d_dmod = nullptr, *d_post = nullptr, *d_pre = nullptr;
     float2 *d_k1i = nullptr, *d_k2i = nullptr, *d_postf = nullptr;  // only where they differ
+    float4 *d_mirror = nullptr;         // odd-extension image factors (direct sine transform)
     uint32_t *d_tw = nullptr;
     float4 *d_s = nullptr, *d_bmul = nullptr, *d_alpha = nullptr, *d_beta = nullptr;
     float4 *d_twist = nullptr;
@@ -164,6 +165,7 @@ void free_tables(ssp_plan *pl) {
     dev_free(pl->d_k1i);
     dev_free(pl->d_k2i);
     dev_free(pl->d_postf);
+    dev_free(pl->d_mirror);
     dev_free(pl->d_dmod);
     dev_free(pl->d_post);
     dev_free(pl->d_pre);
@@ -210,6 +212,8 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     if (!tab.k1i.empty()) HIP_TRY(upload(pl->d_k1i, tab.k1i));
     if (!tab.k2i.empty()) HIP_TRY(upload(pl->d_k2i, tab.k2i));
     if (!tab.postf.empty()) HIP_TRY(upload(pl->d_postf, tab.postf));
+    HIP_TRY(dev_alloc(&pl->d_mirror, tab.mirror.size() / 4));
+    if (!tab.mirror.empty()) HIP_TRY(upload(pl->d_mirror, tab.mirror));
     if (!tab.k1.empty()) HIP_TRY(upload(pl->d_k1, tab.k1));
     if (!tab.k2.empty()) HIP_TRY(upload(pl->d_k2, tab.k2));
     HIP_TRY(upload(pl->d_tw, tab.twiddle));
@@ -275,7 +279,8 @@ ssp::SolveDesc base_desc(const ssp_plan *pl) {
     for (int i = 0; i < 8; ++i) d.env[i] = pl->env[i];
     d.out_every = pl->out_every;
     d.variant = effective_variant(pl);
-    d.direct = pl->tab.direct ? 1 : 0;
+    d.direct = pl->tab.direct;
+    d.mirror = pl->d_mirror;
     return d;
 }
 
@@ -801,8 +806,9 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
             // plain form: one kernel per stage, one solve
             ssp_plan *pl = owner;
             if (pl->tab.direct)
-                return fail(SSP_E_UNIMPL, "the plain form runs chirp-z transforms only; periodic plans with a "
-                                          "power-of-two grid run the fused kernel");
+                return fail(SSP_E_UNIMPL, "the plain form runs chirp-z transforms only; plans with direct "
+                                          "transforms (periodic Nz or Dirichlet Nz + 1 a power of two) run "
+                                          "the fused kernel");
             if (!pl->d_plain) {
                 HIP_TRY(dev_alloc(&pl->d_plain, 2 * static_cast<size_t>(pl->N)));
                 HIP_TRY(hipMalloc(reinterpret_cast<void **>(&pl->d_plain_flags), ssp::plain_state_bytes()));
@@ -847,7 +853,7 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
                 if (G.family)
                     HIP_TRY(ssp::launch_march_family(owner->d_descs + G.start, G.end - G.start, gmax, gs));
                 else
-                    HIP_TRY(ssp::launch_march(sorted[G.start].P, sorted[G.start].variant, sorted[G.start].direct != 0,
+                    HIP_TRY(ssp::launch_march(sorted[G.start].P, sorted[G.start].variant, sorted[G.start].direct,
                                               owner->d_descs + G.start, G.end - G.start, gmax, gs));
                 for (int start = G.start; start < G.end;) {
                     int end = start;
@@ -855,7 +861,7 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
                         ++end;
                     int rows = 0;
                     for (int k = start; k < end; ++k) rows = std::max(rows, sorted[k].snap ? sorted[k].nout : 0);
-                    HIP_TRY(ssp::launch_output(sorted[start].P, sorted[start].direct != 0, owner->d_descs + start,
+                    HIP_TRY(ssp::launch_output(sorted[start].P, sorted[start].direct, owner->d_descs + start,
                                                end - start, rows, gs));
                     start = end;
                 }

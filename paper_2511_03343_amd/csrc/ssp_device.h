@@ -57,13 +57,15 @@ struct SolveDesc {
     int nout;                   // output rows available in snap / tl_out / fld_out
     int nsteps;                 // range steps of this solve in the launch
     int variant;                // engine layout of the march (host-side grouping only)
-    int direct;                 // 1: periodic plan with P = Nz, direct FFTs (host-side grouping)
+    int direct;                 // direct transform kind (0 chirp-z, 1 Fourier, 2 sine; host grouping)
+    const float4 *mirror;       // [N] double-float odd-extension image factors (direct sine)
 };
 
 // Launch the fused persistent march: one workgroup per descriptor, all with the same FFT
 // length P, each marching its own descriptor's nsteps (nsteps here: the largest, 0 = no
-// launch).  direct: periodic plans whose grid length is the FFT length (direct FFTs
-// instead of chirp-z cores; P <= 16384).  Returns hipSuccess or the launch error.
+// launch).  direct: the plans' direct transform kind (0: chirp-z cores; 1: periodic grid of
+// length P, FFTs; 2: Dirichlet grid of length P/2 - 1, the FFT of the odd extension;
+// P <= 16384 for both).  Returns hipSuccess or the launch error.
 // Scratch elements (complex) per solve behind SolveDesc::work: work, pot, wacc, xs.
 constexpr int kWorkPerSolve = 5;
 inline void set_work(SolveDesc &d, float2 *base) {
@@ -73,7 +75,7 @@ inline void set_work(SolveDesc &d, float2 *base) {
     d.xs = base + 3 * static_cast<size_t>(d.N);
 }
 
-hipError_t launch_march(int P, int variant, bool direct, const SolveDesc *d_descs, int nsolves, int nsteps,
+hipError_t launch_march(int P, int variant, int direct, const SolveDesc *d_descs, int nsolves, int nsteps,
                         hipStream_t stream);
 // Layout of the direct-transform march of length P (the autotuned layout of that length).
 int direct_variant(int P);
@@ -95,7 +97,7 @@ hipError_t launch_march_family(const SolveDesc *d_descs, int nsolves, int nsteps
 // starts at step n0 are the steps (n0/out_every + 1) out_every + row out_every; the step at
 // the start is recovered from the solve's statistics (step_index - steps_done), so stats
 // must be present whenever snapshots are.
-hipError_t launch_output(int P, bool direct, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream);
+hipError_t launch_output(int P, int direct, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream);
 
 // Batched transforms over B vectors of a plan's grid (tables from desc, one desc on the
 // device shared by the whole batch).
@@ -103,7 +105,7 @@ hipError_t launch_output(int P, bool direct, const SolveDesc *d_descs, int nsolv
 //           (orthonormal DST-I for Dirichlet boundaries)
 //   mode 1: physical -> modulated coefficient representation
 //   mode 2: modulated coefficient representation -> physical field with carrier at step[b]
-hipError_t launch_transform(int P, bool direct, int mode, const SolveDesc *d_desc, int B, const float2 *in,
+hipError_t launch_transform(int P, int direct, int mode, const SolveDesc *d_desc, int B, const float2 *in,
                             float2 *out, const long long *step, hipStream_t stream);
 
 // Plain form: one kernel per stage (start, Neumann half-term, finish, commit) for the single

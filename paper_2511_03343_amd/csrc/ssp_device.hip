@@ -578,9 +578,12 @@ using ECfg = Cfg<eng_key<P, V>()>;
 // lengths, the lower half otherwise (positions t + i T >= P/2 are always beyond N).
 template <int P, int V>
 constexpr int live_elems() { return eng_len<P>() == P ? ECfg<P, V>::RT / 2 : ECfg<P, V>::RT; }
-// ... and for the direct transform of a periodic grid of P points, all of them
-template <int P, int V, bool DIRECT>
-constexpr int live_of() { return DIRECT ? ECfg<P, V>::RT : live_elems<P, V>(); }
+// ... and for the direct transform of a periodic grid of P points, all of them.  DK is the
+// plan's transform kind: 0 chirp-z, 1 direct Fourier (periodic Nz = P), 2 direct sine
+// (Dirichlet Nz = P/2 - 1, lower half live as for chirp-z).
+constexpr int kDkChirp = 0, kDkFourier = 1, kDkSine = 2;
+template <int P, int V, int DK>
+constexpr int live_of() { return DK == kDkFourier ? ECfg<P, V>::RT : live_elems<P, V>(); }
 
 // The transform of a periodic plan whose grid length is itself an engine length: the
 // forward FFT (grid -> coefficients) or the unnormalised inverse FFT of the P points in
@@ -592,6 +595,33 @@ __device__ __forceinline__ void direct_core(float2 (&x)[Cfg<EK>::RT], const LdsB
     __syncthreads();
     if (fwd) fft<EK, false, 0>(x, L, tw);
     else fft<EK, true, 0>(x, L, tw);
+}
+
+// The orthonormal DST-I of a Dirichlet grid of N = P/2 - 1 points as the FFT of its odd
+// extension of length P (its own inverse).  On entry the thread holds the pre-modulated
+// values at its positions below P/2 (element n at position n - 1, zeros from position N
+// on); their odd images, times the plan's mirror factors, go through LDS to positions
+// P - 2 - m, position P - 1 is zero, and the full FFT returns the lower half of its output
+// (the upper half returned zero).  The opening barrier separates the image writes from the
+// previous transform's LDS reads; with two buffers the images use the one the FFT's first
+// exchange does not, with one the FFT's own write barrier follows the image reads.
+template <int EK>
+__device__ __forceinline__ void sine_core(float2 (&x)[Cfg<EK>::RT], const LdsBufs &L,
+                                          const Twiddles<EK> &tw, const float4 *mirror, int N) {
+    constexpr int P = Cfg<EK>::P, T = Cfg<EK>::T, RT = Cfg<EK>::RT;
+    __syncthreads();
+    float2 *mb = phase_buf<EK, 1>(L);
+    const int tid = opaque_tid();
+#pragma unroll
+    for (int i = 0; i < RT / 2; ++i) {
+        const int pos = tid + i * T;
+        if (pos < N) mb[P - 2 - pos] = cmul_df(x[i], ld4(mirror, pos));
+    }
+    if (tid == T - 1) mb[P - 1] = make_float2(0.f, 0.f);
+    __syncthreads();
+#pragma unroll
+    for (int i = RT / 2; i < RT; ++i) x[i] = mb[tid + i * T];
+    fft<EK, false, 0, false, true>(x, L, tw);
 }
 
 // One transform core for convolution length P (positions 0 .. eng_len-1 distributed as in
@@ -743,9 +773,9 @@ __device__ __forceinline__ float eddy_correction(const SolveDesc &d, float vm, f
 // A = v (.) dmod at the thread's positions (zero at positions >= N); v of global step n,
 // plus i eta when the plan has an absorbing layer (complex absorbing potential).
 // Written to registers (A) when the kernel keeps it there, else to the solve's pot array.
-template <int P, int V, bool IN_REGS, bool DIRECT = false>
+template <int P, int V, bool IN_REGS, int DK = kDkChirp>
 __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, float2 *A) {
-    constexpr int T = ECfg<P, V>::T, RL = live_of<P, V, DIRECT>();
+    constexpr int T = ECfg<P, V>::T, RL = live_of<P, V, DK>();
     const int N = d.N;
     long long row = 0;
     if (d.prof_mode == PROF_TABLE_STEPS) {
@@ -773,13 +803,13 @@ __device__ __forceinline__ void load_potential(const SolveDesc &d, long long n, 
 
 // ----------------------------------------------------------------------------- march
 // One workgroup marches one solve through nsteps range steps.
-template <int P, int V, bool DIRECT = false>
+template <int P, int V, int DK = kDkChirp>
 __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float4 *lds_raw, double *red) {
     constexpr int T = ECfg<P, V>::T, RT = ECfg<P, V>::RT;
     constexpr int EK = eng_key<P, V>();
     // elements that can hold data (the lower half for unsplit chirp-z lengths, all for the
     // direct transform); the others stay zero
-    constexpr int RL = live_of<P, V, DIRECT>();
+    constexpr int RL = live_of<P, V, DK>();
     // the Neumann multiplier stays in registers for up to 8 live elements per thread below
     // 1024 threads (those layouts run two waves per SIMD, so 256 registers per lane)
     constexpr bool kBInRegs = (RL <= 8) && (T < 1024);
@@ -808,7 +838,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     long long n = *d.step;
     // outputs of this launch: steps out_base, out_base + out_every, ... (row = slot)
     const long long out_base = d.out_every > 0 ? (n / d.out_every + 1) * d.out_every : 0;
-    if (d.prof_mode == PROF_TABLE_FIXED) load_potential<P, V, kAInRegs, DIRECT>(d, n + 1, A);
+    if (d.prof_mode == PROF_TABLE_FIXED) load_potential<P, V, kAInRegs, DK>(d, n + 1, A);
 
     long long terms = 0, done = 0;
     int max_used = 0, notconv = 0, status = kOK;
@@ -816,7 +846,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
 
     for (int s = 0; s < nsteps; ++s) {
         const long long nn = n + 1;
-        if (d.prof_mode != PROF_TABLE_FIXED) load_potential<P, V, kAInRegs, DIRECT>(d, nn, A);
+        if (d.prof_mode != PROF_TABLE_FIXED) load_potential<P, V, kAInRegs, DK>(d, nn, A);
         bool bad = false;
         for (int j = 0; j < p; ++j) {
             const float2 *cur = (j == 0) ? d.field : d.work;
@@ -849,7 +879,8 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
             for (int h = 0; h < 2 * nmax; ++h) {
                 // even h: coefficients -> grid (inverse direction); odd h: grid -> coefficients
                 const bool fwd = (h & 1) != 0;
-                if constexpr (DIRECT) direct_core<EK>(a, L, tw, fwd);
+                if constexpr (DK == kDkFourier) direct_core<EK>(a, L, tw, fwd);
+                else if constexpr (DK == kDkSine) sine_core<EK>(a, L, tw, d.mirror, d.N);
                 else dst_core<P, V, kKeepGlobal>(a, L, tw, d, d.xs, fwd ? d.k1 : d.k1i, fwd ? d.k2 : d.k2i);
                 if ((h & 1) == 0) {
 #pragma unroll
@@ -971,14 +1002,14 @@ __global__ __launch_bounds__((ECfg<P, V>::T), (ECfg<P, V>::MINW)) void k_march(c
     march_body<P, V>(descs[blockIdx.x], descs[blockIdx.x].nsteps, lds_raw, red);
 }
 
-// The same march for periodic plans whose grid length is an engine length (P = Nz): the
-// transforms are direct FFTs instead of chirp-z cores.
-template <int P, int V>
+// The same march with direct transforms instead of chirp-z cores (DK: periodic plans with
+// P = Nz, or Dirichlet plans with P = 2 (Nz + 1)).
+template <int P, int V, int DK>
 __global__ __launch_bounds__((ECfg<P, V>::T), (ECfg<P, V>::MINW)) void k_march_direct(
     const SolveDesc *__restrict__ descs, int nsteps) {
     __shared__ float4 lds_raw[lds_words<eng_key<P, V>()>()];
     __shared__ double red[2 * (ECfg<P, V>::T / 64)];
-    march_body<P, V, true>(descs[blockIdx.x], descs[blockIdx.x].nsteps, lds_raw, red);
+    march_body<P, V, DK>(descs[blockIdx.x], descs[blockIdx.x].nsteps, lds_raw, red);
 }
 
 // Solves of uneven length in one launch: every length that runs with 1024-thread workgroups
@@ -1001,7 +1032,7 @@ __global__ __launch_bounds__(kFamilyT) void k_march_family(const SolveDesc *__re
 }
 
 // ----------------------------------------------------------------------------- transforms
-template <int P, bool DIRECT>
+template <int P, int DK>
 __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_transform(const SolveDesc *__restrict__ desc, int mode,
                                                          const float2 *__restrict__ in, float2 *out,
                                                          const long long *__restrict__ step) {
@@ -1024,7 +1055,8 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_transform(const SolveDesc *
         }
         x[i] = v;
     }
-    if constexpr (DIRECT) direct_core<eng_key<P, 0>()>(x, L, tw, mode != 2);
+    if constexpr (DK == kDkFourier) direct_core<eng_key<P, 0>()>(x, L, tw, mode != 2);
+    else if constexpr (DK == kDkSine) sine_core<eng_key<P, 0>()>(x, L, tw, d.mirror, N);
     else dst_core<P, 0, false>(x, L, tw, d, nullptr, mode == 2 ? d.k1i : d.k1, mode == 2 ? d.k2i : d.k2);
     float2 car = make_float2(1.f, 0.f);
     if (mode == 2) car = carrier(d.sigma, step[blockIdx.x]);
@@ -1042,7 +1074,7 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_transform(const SolveDesc *
 // Output rows: blockIdx.x = solve * nout + row.  Snapshot (sine basis) -> physical field
 // with the carrier of its step -> field row (complex64, in place over the snapshot when
 // fld_out == snap) and TL row.
-template <int P, bool DIRECT>
+template <int P, int DK>
 __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_output(const SolveDesc *__restrict__ descs, int nout) {
     constexpr int T = ECfg<P, 0>::T, RT = ECfg<P, 0>::RT;
     SSP_LDS_DECL((eng_key<P, 0>()));
@@ -1063,7 +1095,8 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_output(const SolveDesc *__r
         const int pos = tid + i * T;
         x[i] = (pos < N) ? ld2(src, pos) : make_float2(0.f, 0.f);
     }
-    if constexpr (DIRECT) direct_core<eng_key<P, 0>()>(x, L, tw, false);
+    if constexpr (DK == kDkFourier) direct_core<eng_key<P, 0>()>(x, L, tw, false);
+    else if constexpr (DK == kDkSine) sine_core<eng_key<P, 0>()>(x, L, tw, d.mirror, N);
     else dst_core<P, 0, false>(x, L, tw, d, nullptr, d.k1i, d.k2i);
     const float2 car = carrier(d.sigma, n);
     const float lr = log10f(static_cast<float>(static_cast<double>(n) * d.dr));
@@ -1269,15 +1302,22 @@ hipError_t plain_march_P(const SolveDesc &hd, const SolveDesc *dd, int nsteps, f
 }
 
 template <int P>
-hipError_t launch_output_P(bool direct, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream) {
+hipError_t launch_output_P(int direct, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream) {
     if constexpr (P <= kMaxEngine) {
-        if (direct) {
-            hipLaunchKernelGGL((k_output<P, true>), dim3(nsolves * nout), dim3(ECfg<P, 0>::T), 0, stream,
+        if (direct == kDkFourier) {
+            hipLaunchKernelGGL((k_output<P, kDkFourier>), dim3(nsolves * nout), dim3(ECfg<P, 0>::T), 0, stream,
+                               d_descs, nout);
+            return hipGetLastError();
+        }
+        if (direct == kDkSine) {
+            hipLaunchKernelGGL((k_output<P, kDkSine>), dim3(nsolves * nout), dim3(ECfg<P, 0>::T), 0, stream,
                                d_descs, nout);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_output<P, false>), dim3(nsolves * nout), dim3(ECfg<P, 0>::T), 0, stream, d_descs, nout);
+    if (direct != kDkChirp) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_output<P, kDkChirp>), dim3(nsolves * nout), dim3(ECfg<P, 0>::T), 0, stream, d_descs,
+                       nout);
     return hipGetLastError();
 }
 
@@ -1300,31 +1340,44 @@ hipError_t launch_march_PV(int v, const SolveDesc *d_descs, int nsolves, int nst
 }
 
 template <int P>
-hipError_t launch_transform_P(bool direct, int mode, const SolveDesc *d_desc, int B, const float2 *in,
+hipError_t launch_transform_P(int direct, int mode, const SolveDesc *d_desc, int B, const float2 *in,
                               float2 *out, const long long *step, hipStream_t stream) {
     if constexpr (P <= kMaxEngine) {
-        if (direct) {
-            hipLaunchKernelGGL((k_transform<P, true>), dim3(B), dim3(ECfg<P, 0>::T), 0, stream, d_desc, mode,
-                               in, out, step);
+        if (direct == kDkFourier) {
+            hipLaunchKernelGGL((k_transform<P, kDkFourier>), dim3(B), dim3(ECfg<P, 0>::T), 0, stream, d_desc,
+                               mode, in, out, step);
+            return hipGetLastError();
+        }
+        if (direct == kDkSine) {
+            hipLaunchKernelGGL((k_transform<P, kDkSine>), dim3(B), dim3(ECfg<P, 0>::T), 0, stream, d_desc,
+                               mode, in, out, step);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_transform<P, false>), dim3(B), dim3(ECfg<P, 0>::T), 0, stream, d_desc, mode, in, out,
+    if (direct != kDkChirp) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_transform<P, kDkChirp>), dim3(B), dim3(ECfg<P, 0>::T), 0, stream, d_desc, mode, in, out,
                        step);
     return hipGetLastError();
 }
 
-// direct periodic marches run the autotuned layout of their length only
+// direct marches run the autotuned layout of their length only
 constexpr int tuned_variant(int P) {
     int lg = 0;
     while ((1 << lg) < P) ++lg;
     return kTunedVariant[lg - 7];
 }
 template <int P>
-hipError_t launch_march_direct_P(const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
+hipError_t launch_march_direct_P(int kind, const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
     if constexpr (P <= kMaxEngine) {
         constexpr int V = variant_exists(P, tuned_variant(P)) ? tuned_variant(P) : 0;
-        hipLaunchKernelGGL((k_march_direct<P, V>), dim3(nsolves), dim3(ECfg<P, V>::T), 0, stream, d_descs, nsteps);
+        if (kind == kDkFourier)
+            hipLaunchKernelGGL((k_march_direct<P, V, kDkFourier>), dim3(nsolves), dim3(ECfg<P, V>::T), 0, stream,
+                               d_descs, nsteps);
+        else if (kind == kDkSine)
+            hipLaunchKernelGGL((k_march_direct<P, V, kDkSine>), dim3(nsolves), dim3(ECfg<P, V>::T), 0, stream,
+                               d_descs, nsteps);
+        else
+            return hipErrorInvalidValue;
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;
@@ -1369,11 +1422,11 @@ bool fft_length_supported(int P) {
         default: return hipErrorInvalidValue; \
     }
 
-hipError_t launch_march(int P, int variant, bool direct, const SolveDesc *d_descs, int nsolves, int nsteps,
+hipError_t launch_march(int P, int variant, int direct, const SolveDesc *d_descs, int nsolves, int nsteps,
                         hipStream_t stream) {
     if (nsolves <= 0 || nsteps <= 0) return hipSuccess;
-    if (direct) {
-#define CALL_D(PP) launch_march_direct_P<PP>(d_descs, nsolves, nsteps, stream)
+    if (direct != kDkChirp) {
+#define CALL_D(PP) launch_march_direct_P<PP>(direct, d_descs, nsolves, nsteps, stream)
         SSP_DISPATCH_P(P, CALL_D)
 #undef CALL_D
     }
@@ -1387,7 +1440,7 @@ int direct_variant(int P) {
     return (P >= 128 && P <= kMaxEngine && variant_exists(P, tuned_variant(P))) ? tuned_variant(P) : 0;
 }
 
-hipError_t launch_output(int P, bool direct, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream) {
+hipError_t launch_output(int P, int direct, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream) {
     if (nsolves <= 0 || nout <= 0) return hipSuccess;
 #define CALL_O(PP) launch_output_P<PP>(direct, d_descs, nsolves, nout, stream)
     SSP_DISPATCH_P(P, CALL_O)
@@ -1404,7 +1457,7 @@ hipError_t plain_march(const SolveDesc &h_desc, const SolveDesc *d_desc, int nst
 
 size_t plain_state_bytes() { return sizeof(PlainState); }
 
-hipError_t launch_transform(int P, bool direct, int mode, const SolveDesc *d_desc, int B, const float2 *in,
+hipError_t launch_transform(int P, int direct, int mode, const SolveDesc *d_desc, int B, const float2 *in,
                             float2 *out, const long long *step, hipStream_t stream) {
     if (B <= 0) return hipSuccess;
 #define CALL_T(PP) launch_transform_P<PP>(direct, mode, d_desc, B, in, out, step, stream)

@@ -297,8 +297,12 @@ std::vector<float> window_spectrum(std::vector<cd> w, int P, bool split) {
 
 void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, DeviceTables &t) {
     const int N = nz;
-    const bool direct = bc == kBcPeriodic && N >= 128 && N <= kMaxEngineFFT && (N & (N - 1)) == 0;
-    const int P = direct ? N : chirp_fft_length(2 * nz - 1);
+    auto pow2 = [](long long v) { return v > 0 && (v & (v - 1)) == 0; };
+    int direct = kDirectNone;
+    if (bc == kBcPeriodic && N >= 128 && N <= kMaxEngineFFT && pow2(N)) direct = kDirectFourier;
+    if (bc == kBcDirichlet && 2 * (N + 1) >= 128 && 2 * (N + 1) <= kMaxEngineFFT && pow2(N + 1))
+        direct = kDirectSine;
+    const int P = direct == kDirectFourier ? N : direct == kDirectSine ? 2 * (N + 1) : chirp_fft_length(2 * nz - 1);
     t.nz = N;
     t.P = P;
     t.bc = bc;
@@ -327,7 +331,7 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
     t.k2.clear();
     t.k1i.clear();
     t.k2i.clear();
-    if (!direct) {
+    if (direct == kDirectNone) {
         std::vector<cd> K1(P, 0.0), K2(P, 0.0);
         for (long long d = 1 - N; d <= N - 1; ++d) K1[((d % P) + P) % P] = chirp(d);
         if (bc == kBcDirichlet) {
@@ -367,16 +371,35 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
     //   Fourier: pre_f = conj(c_n), post_f = conj(c_k)/(sqrt(N) P); pre_i = c_n,
     //            post_i = c_k/(sqrt(N) P); dmod = 1/(sqrt(N) P)
     //   Fourier, direct (N an engine length): pre = 1, post = 1/sqrt(N) both ways
+    //   sine, direct (P = 2(N+1)): with w^j = exp(-2 pi i j/P) and element n = m+1 at
+    //            position m, DST(x)_{q+1} = sqrt(2/(N+1)) (i/2) w^q FFT_P(z)_q where z holds
+    //            x_n w^n at position n-1 and its odd image -x_n w^{-n} at position P-1-n
+    //            (zeros at positions N and P-1): pre = w^{m+1}, post = sqrt(2/(N+1)) (i/2) w^m,
+    //            the image factor -w^{-2(m+1)} in the mirror table; the transform is its own
+    //            inverse
     const cd I(0, 1);
+    auto wpow = [&](long long j) {  // exp(-2 pi i j / P), j reduced exactly
+        const long long r = ((j % P) + P) % P;
+        const double ang = -2.0 * kPiD * static_cast<double>(r) / P;
+        return cd(std::cos(ang), std::sin(ang));
+    };
     std::vector<cd> dmod(N);
     t.pre.assign(2 * N, 0.f);
     t.post.assign(2 * N, 0.f);
     t.dmod.assign(2 * N, 0.f);
     t.postf.clear();
     if (bc != kBcDirichlet) t.postf.assign(2 * N, 0.f);
+    t.mirror.clear();
+    if (direct == kDirectSine) t.mirror.assign(4 * static_cast<size_t>(N), 0.f);
     for (int m = 0; m < N; ++m) {
         cd pre_f, post_i, post_f, pre_i;
-        if (bc == kBcDirichlet) {
+        if (direct == kDirectSine) {
+            pre_f = pre_i = wpow(m + 1);
+            post_f = post_i = std::sqrt(2.0 / (N + 1)) * 0.5 * I * wpow(m);
+            const cd img = -std::conj(wpow(2LL * (m + 1)));
+            split_df(img.real(), t.mirror[4 * m], t.mirror[4 * m + 2]);
+            split_df(img.imag(), t.mirror[4 * m + 1], t.mirror[4 * m + 3]);
+        } else if (bc == kBcDirichlet) {
             const double scale = 0.5 * std::sqrt(2.0 / (N + 1)) / P;
             const cd cb = std::conj(chirp(m + 1));
             pre_f = pre_i = cb;
@@ -389,7 +412,7 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
             post_f = cb * (e * scale);
             pre_i = cb * e;
             post_i = cb * scale;
-        } else if (!direct) {
+        } else if (direct == kDirectNone) {
             const double scale = 1.0 / (std::sqrt(static_cast<double>(N)) * P);
             const cd c = chirp(m);
             pre_f = std::conj(c);
@@ -403,9 +426,9 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
             post_f = post_i = scale;
         }
         // (the sine transform's product in the order of its original derivation)
-        dmod[m] = bc == kBcDirichlet ? std::conj(chirp(m + 1)) * std::conj(chirp(m + 1)) * I *
-                                           (0.5 * std::sqrt(2.0 / (N + 1)) / P)
-                                     : post_f * pre_i;
+        dmod[m] = (bc == kBcDirichlet && direct == kDirectNone)
+                      ? std::conj(chirp(m + 1)) * std::conj(chirp(m + 1)) * I * (0.5 * std::sqrt(2.0 / (N + 1)) / P)
+                      : post_f * pre_i;
         put_c(t.pre, m, pre_f);
         put_c(t.post, m, post_i);
         put_c(t.dmod, m, dmod[m]);

@@ -46,6 +46,9 @@ constexpr int kMaxEngineFFT = 16384;
 // Boundary conditions at z = 0 and z = H (Sec. 3.1) and their transforms.
 enum Boundary : int { kBcDirichlet = 0, kBcNeumann = 1, kBcPeriodic = 2 };
 
+// Kinds of direct transform (see DeviceTables::direct).
+enum DirectKind : int { kDirectNone = 0, kDirectFourier = 1, kDirectSine = 2 };
+
 // Grid of a boundary condition: z of position m (0-based) is (m + zoff) dz.
 struct GridSpec {
     int zoff;
@@ -55,10 +58,13 @@ GridSpec grid_spec(int bc, int nz, double depth);
 
 struct DeviceTables {
     int nz = 0, P = 0, bc = kBcDirichlet;
-    // periodic grid whose length is an engine FFT length (a power of two, 128 .. 16384):
-    // the transforms are direct FFTs of length P = nz, no chirp windows; pre = 1 and the
-    // modulations are 1/sqrt(nz)
-    bool direct = false;
+    // direct transforms (no chirp windows), where the grid allows them:
+    //   kDirectFourier: periodic grid whose length is an engine FFT length (a power of two,
+    //     128 .. 16384): FFTs of length P = nz; pre = 1 and the modulations are 1/sqrt(nz)
+    //   kDirectSine: Dirichlet grid with nz + 1 a power of two (P = 2(nz+1) in 128 .. 16384):
+    //     the DST-I as the FFT of the odd extension of length P, built in LDS with the
+    //     mirror multipliers below
+    int direct = kDirectNone;
     // chirp-z transform of length nz through a cyclic convolution of length P, with the
     // chirp c_d = exp(i pi d^2 / D) (D = 2(nz+1) sine, 2(nz-1) cosine, nz Fourier):
     // [P] complex FP32 spectra of the two chirp windows, Toeplitz c_d (d in [1-nz, nz-1])
@@ -75,6 +81,9 @@ struct DeviceTables {
     std::vector<float> postf;         // [nz] forward post-modulation, when it differs from post
     std::vector<float> dmod;          // [nz] complex FP32 post-modulation of one direction
                                       // times pre-modulation of the other (the same both ways)
+    // kDirectSine only: [nz] double-float complex -exp(4 pi i (m+1)/P), the factor between
+    // the stored value at position m and its odd-extension image at position P - 2 - m
+    std::vector<float> mirror;
     // exp(-2 pi i e / PE) for e = 0..PE/8, PE = the engine FFT length (P, or P/2 when split;
     // the first octant, the device rebuilds the other octants by symmetry): per entry
     // hi.re, hi.im (FP32 bit patterns) and the rounding remainders lo.re, lo.im packed as two

@@ -91,7 +91,7 @@ def test_eddy_with_absorber_vs_oracle(ssp, gpu, profile):
 
 
 def test_plain_form_equals_fused_bitwise_with_absorber(ssp, gpu):
-    s = W.munk_deep(nsteps=8, nz=511)
+    s = W.munk_deep(nsteps=8, nz=510)
     s.out_every = 4
     out = []
     for engine in (0, 1):
