@@ -45,8 +45,8 @@ PEAK_HBM = 8.0e12      # MI355X HBM3E (B/s)
 # shape and a fingerprint of the kernel sources and layout table: any change to them makes
 # the figure stale, and it is then reported as null.
 TRAFFIC = {
-    ("munk4096", 512, 100): {"fingerprint": "7d0c6b8ca77e2d04", "fetch": 44033918.0,
-                             "write": 4292012512.0},
+    ("munk4096", 512, 100): {"fingerprint": "32db84355030777f", "fetch": 44410880.0,
+                             "write": 4376460288.0},
 }
 
 
@@ -245,6 +245,9 @@ def run_device_batch(args, ssp, torch, stream, dev):
     ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
     ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_GRAPH, 1 if args.graph else 0)
     layout, threads, P = ssp.ssp_plan_engine(pl)
+    # direct transforms (no chirp-z): 1 periodic with P = Nz, 2 Dirichlet with P = 2 (Nz + 1)
+    direct = 1 if (s.bc == "periodic" and P == s.nz) else (
+        2 if (s.bc == "dirichlet" and P == 2 * (s.nz + 1)) else 0)
 
     zs = (W.source_depths(B, 20.0, 180.0) if args.workload == "homogeneous"
           else W.source_depths(B, 100.0, 3900.0) if args.workload == "modal8001"
@@ -307,9 +310,7 @@ def run_device_batch(args, ssp, torch, stream, dev):
             "traffic": measured_traffic(args.workload, B, args.chunk, args.bc)
             if args.absorber is None else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel": (f"k_march_direct<{P}, {layout}, 1>" if (s.bc == "periodic" and P == s.nz)
-                       else f"k_march_direct<{P}, {layout}, 2>"
-                       if (s.bc == "dirichlet" and P == 2 * (s.nz + 1))
+            "kernel": (f"k_march_direct<{P}, {layout}, {direct}>" if direct
                        else f"k_march<{P}, {layout}>") + f" ({threads} threads per workgroup)",
             "avg_launch_ms": 1e3 * sum(launch_s) / len(launch_s),
             "steps_per_launch": args.chunk,
@@ -322,7 +323,7 @@ def run_device_batch(args, ssp, torch, stream, dev):
         config["modal_starters"] = {"sources": B, "modes": int(len(kappa)), "seconds": starter_s,
                                     "note": "FP64 eigendecomposition on the device, outside the timed region"}
     plain = None
-    if args.plain_steps > 0:
+    if args.plain_steps > 0 and not direct:
         plain = plain_vs_fused(ssp, s, args.plain_steps)
         plain["fused_batched_over_plain"] = (updates / wall) / plain["plain_one_solve"]
     return updates, wall, roof, config, sorted(set(stats["status"])), plain, s.nz
