@@ -45,8 +45,8 @@ PEAK_HBM = 8.0e12      # MI355X HBM3E (B/s)
 # shape and a fingerprint of the kernel sources and layout table: any change to them makes
 # the figure stale, and it is then reported as null.
 TRAFFIC = {
-    ("munk4096", 512, 100): {"fingerprint": "32db84355030777f", "fetch": 44410880.0,
-                             "write": 4376460288.0},
+    ("munk4096", 512, 100): {"fingerprint": "fafcad885101ca37", "fetch": 43993920.0,
+                             "write": 4432542848.0},
 }
 
 
@@ -384,7 +384,8 @@ PEAK_FP16_MFMA = 2.5e15   # MI355X dense fp16/bf16 matrix peak (FLOP/s)
 
 def transform_rooflines(ssp, torch, stream, dev, reps=20):
     """Stand-alone batched transforms, each timed with events on its stream:
-    the chirp-z DST (FFT path, HBM-bound: 16 B per point read + written) at Nz = 4096 and
+    the FFT-path DST (HBM-bound: 16 B per point read + written), chirp-z at Nz = 4096 and
+    direct at Nz = 4095, and
     the dense DST on the matrix cores at Nz = 2048 (three fp16 products of 2 Nz^2 flops per
     real column)."""
     out = {}
@@ -401,17 +402,19 @@ def transform_rooflines(ssp, torch, stream, dev, reps=20):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3 / reps
 
-    nz, B = 4096, 4096
-    pl = ssp.ssp_plan_create(nz, 5000.0, 50.0, 1500.0, 25.0, 6, 48, 1e-10)
-    ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
-    x = torch.randn((B, nz), dtype=torch.complex64, device=dev)
-    y = torch.empty_like(x)
-    t = timed(lambda: ssp.ssp_dst_device(pl, B, x.data_ptr(), y.data_ptr()))
-    ssp.ssp_plan_destroy(pl)
-    gbs = 16.0 * nz * B / t
-    out["dst_fft"] = {"kernel": f"k_transform<{_fft_len(nz)}>", "nz": nz, "vectors": B,
-                      "bound": "hbm", "achieved": gbs / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                      "frac": gbs / PEAK_HBM, "ms_per_call": 1e3 * t}
+    # chirp-z at Nz = 4096; the direct sine transform (one FFT of length 2 (Nz + 1)) at 4095
+    for key, nz, kernel in (("dst_fft", 4096, f"k_transform<{_fft_len(4096)}, 0>"),
+                            ("dst_fft_direct", 4095, "k_transform<8192, 2>")):
+        B = 4096
+        pl = ssp.ssp_plan_create(nz, 5000.0, 50.0, 1500.0, 25.0, 6, 48, 1e-10)
+        ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
+        x = torch.randn((B, nz), dtype=torch.complex64, device=dev)
+        y = torch.empty_like(x)
+        t = timed(lambda: ssp.ssp_dst_device(pl, B, x.data_ptr(), y.data_ptr()))
+        ssp.ssp_plan_destroy(pl)
+        gbs = 16.0 * nz * B / t
+        out[key] = {"kernel": kernel, "nz": nz, "vectors": B, "bound": "hbm", "achieved": gbs / 1e9,
+                    "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": gbs / PEAK_HBM, "ms_per_call": 1e3 * t}
     nz, B = 2048, 1024
     pl = ssp.ssp_plan_create(nz, 5000.0, 50.0, 1500.0, 25.0, 6, 48, 1e-10)
     ssp.ssp_plan_set_stream(pl, stream.cuda_stream)

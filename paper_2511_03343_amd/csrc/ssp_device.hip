@@ -1032,41 +1032,55 @@ __global__ __launch_bounds__(kFamilyT) void k_march_family(const SolveDesc *__re
 }
 
 // ----------------------------------------------------------------------------- transforms
+// Persistent over the batch: workgroup g transforms vectors g, g + G, g + 2G, ... (G =
+// gridDim.x <= B), so the twiddles are set up once per workgroup, and the next vector's
+// input is loaded while the current one is transformed.  Each vector's in and out may be
+// the same memory: vector v's output is stored after its input was read, and no other
+// vector's input lies there.  Layout 0 (the most threads per workgroup) is used for every
+// length: it measured faster for stand-alone transforms than the march's tuned layouts.
 template <int P, int DK>
 __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_transform(const SolveDesc *__restrict__ desc, int mode,
-                                                         const float2 *__restrict__ in, float2 *out,
-                                                         const long long *__restrict__ step) {
+                                                         const float2 *in, float2 *out,
+                                                         const long long *__restrict__ step, int B) {
     constexpr int T = ECfg<P, 0>::T, RT = ECfg<P, 0>::RT;
     SSP_LDS_DECL((eng_key<P, 0>()));
     const SolveDesc &d = *desc;
     const int N = d.N;
     Twiddles<eng_key<P, 0>()> tw;
     init_twiddles<eng_key<P, 0>()>(tw, L.tw4, d.tw);
-    const float2 *vin = in + static_cast<size_t>(blockIdx.x) * N;
-    float2 *vout = out + static_cast<size_t>(blockIdx.x) * N;
-    float2 x[RT];
+    float2 xn[RT];
+    auto load = [&](int v) {
+        const float2 *vin = in + static_cast<size_t>(v) * N;
 #pragma unroll
-    for (int i = 0; i < RT; ++i) {
-        const int pos = opaque_tid() + i * T, m = pos;
-        float2 v = make_float2(0.f, 0.f);
-        if (pos < N) {
-            v = ld2(vin, m);
-            if (mode != 2) v = cmul(v, ld2(d.pre, m));
+        for (int i = 0; i < RT; ++i) {
+            const int pos = opaque_tid() + i * T;
+            xn[i] = pos < N ? ld2(vin, pos) : make_float2(0.f, 0.f);
         }
-        x[i] = v;
-    }
-    if constexpr (DK == kDkFourier) direct_core<eng_key<P, 0>()>(x, L, tw, mode != 2);
-    else if constexpr (DK == kDkSine) sine_core<eng_key<P, 0>()>(x, L, tw, d.mirror, N);
-    else dst_core<P, 0, false>(x, L, tw, d, nullptr, mode == 2 ? d.k1i : d.k1, mode == 2 ? d.k2i : d.k2);
-    float2 car = make_float2(1.f, 0.f);
-    if (mode == 2) car = carrier(d.sigma, step[blockIdx.x]);
+    };
+    load(blockIdx.x);
+    for (int v = blockIdx.x; v < B; v += gridDim.x) {  // uniform over the workgroup
+        float2 x[RT];
 #pragma unroll
-    for (int i = 0; i < RT; ++i) {
-        const int pos = opaque_tid() + i * T, m = pos;
-        if (pos < N) {
-            float2 v = cmul(x[i], mode == 1 ? ld2(d.dmod, m) : ld2(mode == 0 ? d.postf : d.post, m));
-            if (mode == 2) v = cmul(v, car);
-            st2(vout, m, v);
+        for (int i = 0; i < RT; ++i) {
+            const int pos = opaque_tid() + i * T;
+            x[i] = (mode != 2 && pos < N) ? cmul(xn[i], ld2(d.pre, pos)) : xn[i];
+        }
+        if (v + static_cast<int>(gridDim.x) < B) load(v + gridDim.x);
+        __syncthreads();  // the previous vector's last LDS reads are done
+        if constexpr (DK == kDkFourier) direct_core<eng_key<P, 0>()>(x, L, tw, mode != 2);
+        else if constexpr (DK == kDkSine) sine_core<eng_key<P, 0>()>(x, L, tw, d.mirror, N);
+        else dst_core<P, 0, false>(x, L, tw, d, nullptr, mode == 2 ? d.k1i : d.k1, mode == 2 ? d.k2i : d.k2);
+        float2 car = make_float2(1.f, 0.f);
+        if (mode == 2) car = carrier(d.sigma, step[v]);
+        float2 *vout = out + static_cast<size_t>(v) * N;
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+            const int pos = opaque_tid() + i * T;
+            if (pos < N) {
+                float2 y = cmul(x[i], mode == 1 ? ld2(d.dmod, pos) : ld2(mode == 0 ? d.postf : d.post, pos));
+                if (mode == 2) y = cmul(y, car);
+                st2(vout, pos, y);
+            }
         }
     }
 }
@@ -1342,21 +1356,27 @@ hipError_t launch_march_PV(int v, const SolveDesc *d_descs, int nsolves, int nst
 template <int P>
 hipError_t launch_transform_P(int direct, int mode, const SolveDesc *d_desc, int B, const float2 *in,
                               float2 *out, const long long *step, hipStream_t stream) {
+    // one resident workgroup per compute unit (the LDS of one transform fills most of it)
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int G = B < cus ? B : (cus > 0 ? cus : 1);
     if constexpr (P <= kMaxEngine) {
         if (direct == kDkFourier) {
-            hipLaunchKernelGGL((k_transform<P, kDkFourier>), dim3(B), dim3(ECfg<P, 0>::T), 0, stream, d_desc,
-                               mode, in, out, step);
+            hipLaunchKernelGGL((k_transform<P, kDkFourier>), dim3(G), dim3(ECfg<P, 0>::T), 0, stream, d_desc,
+                               mode, in, out, step, B);
             return hipGetLastError();
         }
         if (direct == kDkSine) {
-            hipLaunchKernelGGL((k_transform<P, kDkSine>), dim3(B), dim3(ECfg<P, 0>::T), 0, stream, d_desc,
-                               mode, in, out, step);
+            hipLaunchKernelGGL((k_transform<P, kDkSine>), dim3(G), dim3(ECfg<P, 0>::T), 0, stream, d_desc,
+                               mode, in, out, step, B);
             return hipGetLastError();
         }
     }
     if (direct != kDkChirp) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_transform<P, kDkChirp>), dim3(B), dim3(ECfg<P, 0>::T), 0, stream, d_desc, mode, in, out,
-                       step);
+    hipLaunchKernelGGL((k_transform<P, kDkChirp>), dim3(G), dim3(ECfg<P, 0>::T), 0, stream, d_desc, mode, in, out,
+                       step, B);
     return hipGetLastError();
 }
 
