@@ -5,6 +5,8 @@ of the data instead of the two chirp-z FFTs of the general length.  Bars as for 
 path: transforms relative L2 <= 2e-6 against the oracle's DST; marches relative L2 <= 1e-4
 at every output range and |dTL| <= 0.1 dB where TL < 120 dB; batch equivalence bitwise.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -144,3 +146,60 @@ def test_mixed_batch_equals_alone_bitwise(ssp, gpu):
             ssp.ssp_plan_destroy(pl)
     for a, b in zip(alone, fl):
         assert np.array_equal(a, b)
+
+
+def test_bench_launch_configuration_sampled(ssp, gpu):
+    # 512 solves at Nz = 4095 as `bench.py --nz 4095` times them: one plan on a dedicated
+    # stream, graph-recorded launches, TL rows on the device; sampled solves vs the oracle
+    torch = gpu
+    s = W.munk_deep(nz=4095)
+    B, nsteps = 512, 24
+    stream = torch.cuda.Stream()
+    pl = make_plan(ssp, s)
+    zs = W.source_depths(B, 50.0, 2000.0)
+    try:
+        assert ssp.ssp_plan_engine(pl)[2] == 8192
+        ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_GRAPH, 1)
+        psi = np.stack([W.gaussian_starter(s.nz, s.depth, s.freq, s.c0, z) for z in zs])
+        with torch.cuda.stream(stream):
+            d_psi = torch.from_numpy(psi.astype(np.complex64)).cuda()
+            steps = torch.zeros(B, dtype=torch.int64, device="cuda")
+            d_tl = torch.zeros((B, nsteps // s.out_every + 1, s.nz), dtype=torch.float32, device="cuda")
+            out = torch.empty_like(d_psi)
+        stream.synchronize()
+        ssp.ssp_to_sine(pl, B, d_psi.data_ptr(), d_psi.data_ptr())
+        ssp.ssp_march_device(pl, B, d_psi.data_ptr(), steps.data_ptr(), nsteps, d_tl.data_ptr())
+        ssp.ssp_from_sine(pl, B, d_psi.data_ptr(), steps.data_ptr(), out.data_ptr())
+        stream.synchronize()
+        tl = d_tl.cpu().numpy()
+        fld = out.cpu().numpy().astype(np.complex128)
+        assert steps.cpu().tolist() == [nsteps] * B
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    for b in (0, 257, 511):
+        s1 = dataclasses.replace(s, zs=float(zs[b]), nsteps=nsteps)
+        ref = oracle_march(s1)
+        mask = ref.tl < 120.0
+        dtl = np.abs(tl[b, :ref.tl.shape[0]].astype(np.float64) - ref.tl)[mask]
+        err = np.linalg.norm(fld[b] - ref.final) / np.linalg.norm(ref.final)
+        _report(f"direct sine bench config b={b}", relL2=f"{err:.3e}", max_dTL=f"{dtl.max():.3e}")
+        assert err <= REL_L2 and dtl.max() <= DTL
+
+
+def test_munk_long_range(ssp, gpu):
+    # 600 steps (15 km) at Nz = 4095: error growth over range stays within the bar
+    s = W.munk_deep(nsteps=600, nz=4095)
+    s.out_every = 150
+    pl = make_plan(ssp, s)
+    try:
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert st == ref.status
+    err = np.linalg.norm(fld - ref.field, axis=1) / np.linalg.norm(ref.field, axis=1)
+    mask = ref.tl < 120.0
+    dtl = np.abs(tl.astype(np.float64) - ref.tl)[mask]
+    _report("direct sine munk long", relL2=" ".join(f"{e:.2e}" for e in err), max_dTL=f"{dtl.max():.3e}")
+    assert err.max() <= REL_L2 and dtl.max() <= DTL
