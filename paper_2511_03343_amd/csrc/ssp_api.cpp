@@ -69,6 +69,7 @@ struct ssp_plan {
     float2 *d_k1 = nullptr, *d_k2 = nullptr, *d_dmod = nullptr, *d_post = nullptr, *d_pre = nullptr;
     float2 *d_k1i = nullptr, *d_k2i = nullptr, *d_postf = nullptr;  // only where they differ
     float4 *d_mirror = nullptr;         // odd-extension image factors (direct sine transform)
+    const float4 *d_twl = nullptr;      // shared last-pass twiddles of 1024-thread engines (not owned)
     uint32_t *d_tw = nullptr;
     float4 *d_s = nullptr, *d_bmul = nullptr, *d_alpha = nullptr, *d_beta = nullptr;
     float4 *d_twist = nullptr;
@@ -217,6 +218,7 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     if (!tab.k1.empty()) HIP_TRY(upload(pl->d_k1, tab.k1));
     if (!tab.k2.empty()) HIP_TRY(upload(pl->d_k2, tab.k2));
     HIP_TRY(upload(pl->d_tw, tab.twiddle));
+    HIP_TRY(ssp::last_twiddles(P, pl->d_tw, &pl->d_twl));
     HIP_TRY(upload(pl->d_dmod, tab.dmod));
     HIP_TRY(upload(pl->d_post, tab.post));
     HIP_TRY(upload(pl->d_pre, tab.pre));
@@ -251,6 +253,7 @@ ssp::SolveDesc base_desc(const ssp_plan *pl) {
     d.k1i = pl->d_k1i ? pl->d_k1i : pl->d_k1;
     d.k2i = pl->d_k2i ? pl->d_k2i : pl->d_k2;
     d.tw = pl->d_tw;
+    d.twl = pl->d_twl;
     d.dmod = pl->d_dmod;
     d.post = pl->d_post;
     d.pre = pl->d_pre;

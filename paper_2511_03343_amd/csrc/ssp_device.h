@@ -27,6 +27,8 @@ struct SolveDesc {
     const float2 *k1i, *k2i;    // [P] the same for the inverse direction (== k1, k2 for the
                                 //     sine and cosine transforms, their own inverses)
     const uint32_t *tw;         // first-octant twiddle table (see DeviceTables::twiddle)
+    const float4 *twl;          // last-pass twiddles of the split-transform engine,
+                                //     [RT-1][1024] (see last_twiddles), else null
     const float2 *dmod, *post;  // [N] folded modulation; inverse post-modulation
     const float2 *pre;          // [N] forward pre-modulation (grid values -> chirp-z input)
     const float2 *postf;        // [N] forward post-modulation (stand-alone transform)
@@ -116,5 +118,15 @@ hipError_t plain_march(const SolveDesc &h_desc, const SolveDesc *d_desc, int nst
 size_t plain_state_bytes();
 
 bool fft_length_supported(int P);
+
+// Last-pass twiddles w^{r t} (r = 1 .. RT-1, thread t) of the engine that serves split
+// transforms (P above the largest single-workgroup FFT: two halves of 16384 points, 1024
+// threads per workgroup), as double-float float4 (hi.re, hi.im, lo.re, lo.im).  That engine
+// reads them from this table instead of holding them in registers.  The table lives in
+// device memory of the current device for the life of the process; the first call per
+// device fills it from the first-octant table d_tw of the engine length (a kernel on the
+// null stream, waited for), later calls return it.  *out is null for unsplit lengths.
+// Thread-safe.
+hipError_t last_twiddles(int P, const uint32_t *d_tw, const float4 **out);
 
 }  // namespace ssp

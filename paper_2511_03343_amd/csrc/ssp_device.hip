@@ -35,6 +35,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 namespace ssp {
 namespace {
 
@@ -247,8 +249,10 @@ __device__ __forceinline__ int opaque_tid() {
 // passes (elements per thread).  Variant 0 is the default layout; variant 1 exists where a
 // second layout fits the register and LDS budgets, and the autotuner picks per length.
 constexpr int kVarShift = 20;
+constexpr int kSplitKey = 1 << 28;  // the engine serves a split transform (two halves)
 constexpr int key_len(int K) { return K & ((1 << kVarShift) - 1); }
-constexpr int key_var(int K) { return K >> kVarShift; }
+constexpr int key_var(int K) { return (K >> kVarShift) & 0xff; }
+constexpr bool key_split(int K) { return (K & kSplitKey) != 0; }
 constexpr int threads_v0(int P) { return P <= 512 ? 64 : (P == 1024 ? 128 : (P <= 4096 ? 256 : 1024)); }
 constexpr int threads_v1(int P) {
     return P == 1024 ? 64 : (P == 2048 ? 128 : (P == 4096 ? 512 : (P == 8192 ? 512 : threads_v0(P))));
@@ -320,12 +324,18 @@ constexpr int mid_tab_len() { return mid_tab_from<P, Cfg<P>::RT>(); }
 template <int P, int Ns>
 constexpr int mid_tab_offset() { return mid_tab_len<P>() - mid_tab_from<P, Ns>(); }
 
-// Twiddles of the last pass (w_P^{r t}, r = 1..RT-1): per thread, held in registers.
+// Twiddles of the last pass (w_P^{r t}, r = 1..RT-1): per thread, held in registers, except
+// in the engine of split transforms (1024 threads, 128 registers per lane, which the second
+// half's state leaves short): it reads them from a device table ([r-1][t], coalesced, shared
+// by every workgroup, so it stays in L2), loaded before the barrier that precedes their use.
+// (Unsplit 1024-thread engines measured faster with register twiddles and a few spills.)
 template <int P>
 struct Twiddles {
-    static constexpr int NTW = Cfg<P>::RT - 1;
+    static constexpr bool kRegs = !key_split(P);
+    static constexpr int NTW = kRegs ? Cfg<P>::RT - 1 : 1;
     float2 h[NTW];   // FP32 nearest value
     uint32_t l[NTW]; // remainder as two bf16 (re high, im low)
+    const float4 *tab;
 };
 
 // w_P^e (forward sign), e in [0, P), from the first-octant table in global memory:
@@ -375,10 +385,16 @@ __device__ __forceinline__ void init_mid_table(float4 *t4, const uint32_t *tab) 
 // All twiddles of a launch: the middle-pass table (LDS, ends with a barrier) and the
 // thread's last-pass twiddles (registers).
 template <int P>
-__device__ __forceinline__ void init_twiddles(Twiddles<P> &tw, float4 *t4, const uint32_t *tab) {
+__device__ __forceinline__ void init_twiddles(Twiddles<P> &tw, float4 *t4, const uint32_t *tab,
+                                              const float4 *last) {
     const int tid = threadIdx.x;
+    if constexpr (Twiddles<P>::kRegs) {
 #pragma unroll
-    for (int r = 1; r < Cfg<P>::RT; ++r) fetch_twiddle<P>(tab, r * tid, tw.h[r - 1], tw.l[r - 1]);
+        for (int r = 1; r < Cfg<P>::RT; ++r) fetch_twiddle<P>(tab, r * tid, tw.h[r - 1], tw.l[r - 1]);
+        tw.tab = nullptr;
+    } else {
+        tw.tab = last;
+    }
     init_mid_table<P, Cfg<P>::RT>(t4, tab);
     __syncthreads();
 }
@@ -408,9 +424,11 @@ __device__ __forceinline__ void before_write() {
 
 // middle passes: read phase PH (padding SHR), write phase PH + 1 (padding mid_shift(Ns));
 // Ns = current stride until it reaches T
+template <int P>
+constexpr int last_tab_regs() { return Twiddles<P>::kRegs ? 1 : Cfg<P>::RT - 1; }
 template <int P, bool INV, int Ns, int PH, int SHR>
 __device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBufs &L,
-                                           const Twiddles<P> &tw) {
+                                           const Twiddles<P> &tw, float4 (&wl)[last_tab_regs<P>()]) {
     constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
     if constexpr (Ns < T) {
         constexpr int R = mid_radix<P, Ns>();
@@ -464,8 +482,15 @@ __device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBuf
                 for (int r = 0; r < R; ++r) out[lps<SHW>(base + r * Ns)] = v[r];
             }
         }
+        if constexpr (!Twiddles<P>::kRegs && Ns * R >= T) {
+            // the last pass's table twiddles, loaded before its barrier so that their latency
+            // overlaps the wait
+            const int t3 = opaque_tid();
+#pragma unroll
+            for (int r = 1; r < RT; ++r) wl[r - 1] = ld4(tw.tab, (r - 1) * T + t3);
+        }
         __syncthreads();
-        mid_passes<P, INV, Ns * R, PH + 1, SHW>(x, L, tw);
+        mid_passes<P, INV, Ns * R, PH + 1, SHW>(x, L, tw, wl);
     }
 }
 
@@ -499,16 +524,22 @@ __device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, c
         for (int r = 0; r < RT; ++r) out[r] = x[r];
     }
     __syncthreads();
-    mid_passes<P, INV, RT, PH, kShFirst>(x, L, tw);
+    static_assert(Twiddles<P>::kRegs || RT < T, "table twiddles are loaded by the last middle pass");
+    float4 wl[last_tab_regs<P>()];
+    mid_passes<P, INV, RT, PH, kShFirst>(x, L, tw, wl);
     // last pass: Ns = T, butterfly j = t, twiddles w_P^{r t}, outputs at t + r T
     {
         constexpr int SHL = last_shift_from<P, RT, kShFirst>();
         const float2 *in = phase_buf<P, PH + fft_phases<P>() - 1>(L) + lps<SHL>(opaque_tid());
 #pragma unroll
         for (int r = 0; r < RT; ++r) x[r] = in[r * lpcs(SHL, T)];
+        if constexpr (Twiddles<P>::kRegs) {
 #pragma unroll
-        for (int r = 1; r < RT; ++r)
-            x[r] = twmul<INV>(x[r], tw.h[r - 1], tw.l[r - 1]);
+            for (int r = 1; r < RT; ++r) x[r] = twmul<INV>(x[r], tw.h[r - 1], tw.l[r - 1]);
+        } else {
+#pragma unroll
+            for (int r = 1; r < RT; ++r) x[r] = INV ? cmul_df_conj(x[r], wl[r - 1]) : cmul_df(x[r], wl[r - 1]);
+        }
         if constexpr (HALF_OUT && RT >= 2) DftHalfOut<RT, INV>::run(x);
         else Dft<RT, INV>::run(x);
     }
@@ -569,7 +600,8 @@ template <int P>
 constexpr int eng_len() { return P > kMaxEngine ? P / 2 : P; }
 template <int P, int V>
 constexpr int eng_key() {
-    return eng_len<P>() | ((variant_exists(eng_len<P>(), V) ? V : 0) << kVarShift);
+    return eng_len<P>() | ((variant_exists(eng_len<P>(), V) ? V : 0) << kVarShift) |
+           (P > kMaxEngine ? kSplitKey : 0);
 }
 template <int P, int V>
 using ECfg = Cfg<eng_key<P, V>()>;
@@ -827,7 +859,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     const int tid = threadIdx.x;
     const int N = d.N, p = d.p, nmax = d.nmax;
     Twiddles<EK> tw;
-    init_twiddles<EK>(tw, L.tw4, d.tw);
+    init_twiddles<EK>(tw, L.tw4, d.tw, d.twl);
 
     // The state u is not held in registers: d.field holds the state at the start of the
     // step (the recovery point if the step diverges) and d.work the state between Pade
@@ -1047,7 +1079,7 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_transform(const SolveDesc *
     const SolveDesc &d = *desc;
     const int N = d.N;
     Twiddles<eng_key<P, 0>()> tw;
-    init_twiddles<eng_key<P, 0>()>(tw, L.tw4, d.tw);
+    init_twiddles<eng_key<P, 0>()>(tw, L.tw4, d.tw, d.twl);
     float2 xn[RT];
     auto load = [&](int v) {
         const float2 *vin = in + static_cast<size_t>(v) * N;
@@ -1097,7 +1129,7 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_output(const SolveDesc *__r
     if (row >= d.nout || !d.snap || !d.stats || d.out_every <= 0) return;  // uniform
     const int N = d.N, tid = threadIdx.x;
     Twiddles<eng_key<P, 0>()> tw;
-    init_twiddles<eng_key<P, 0>()>(tw, L.tw4, d.tw);
+    init_twiddles<eng_key<P, 0>()>(tw, L.tw4, d.tw, d.twl);
     // the march that wrote the snapshots started at step step_index - steps_done
     const long long n0 = d.stats->step_index - d.stats->steps_done;
     const long long n = (n0 / d.out_every + 1) * d.out_every + static_cast<long long>(row) * d.out_every;
@@ -1177,7 +1209,7 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_plain_half(const SolveDesc 
     const SolveDesc &d = *desc;
     if (ps->halt || ps->done) return;  // uniform: the series has stopped
     Twiddles<eng_key<P, 0>()> tw;
-    init_twiddles<eng_key<P, 0>()>(tw, L.tw4, d.tw);
+    init_twiddles<eng_key<P, 0>()>(tw, L.tw4, d.tw, d.twl);
     const int N = d.N;
     float2 x[RT];
 #pragma unroll
@@ -1380,6 +1412,24 @@ hipError_t launch_transform_P(int direct, int mode, const SolveDesc *d_desc, int
     return hipGetLastError();
 }
 
+// Last-pass twiddle table of the split-transform engine (one per device) and the kernel
+// that fills it from the first-octant table: block r-1 holds w^{r t}.
+constexpr int kSplitEK = eng_key<2 * kMaxEngine, 0>();
+constexpr int kTwlSplit = (Cfg<kSplitEK>::RT - 1) * Cfg<kSplitEK>::T;
+static_assert(!Twiddles<kSplitEK>::kRegs && Cfg<kSplitEK>::T == 1024, "split engine reads a table");
+__device__ float4 g_twl_split[kTwlSplit];
+
+template <int EK>
+__global__ __launch_bounds__(Cfg<EK>::T) void k_last_twiddles(const uint32_t *__restrict__ tab,
+                                                              float4 *__restrict__ out) {
+    constexpr int T = Cfg<EK>::T;
+    const int t = threadIdx.x, r = blockIdx.x + 1;
+    float2 h;
+    uint32_t l;
+    fetch_twiddle<EK>(tab, r * t, h, l);
+    out[blockIdx.x * T + t] = make_float4(h.x, h.y, __uint_as_float(l & 0xffff0000u), __uint_as_float(l << 16));
+}
+
 // direct marches run the autotuned layout of their length only
 constexpr int tuned_variant(int P) {
     int lg = 0;
@@ -1426,6 +1476,34 @@ hipError_t launch_march_family(const SolveDesc *d_descs, int nsolves, int nsteps
 bool fft_length_supported(int P) {
     return P == 128 || P == 256 || P == 512 || P == 1024 || P == 2048 || P == 4096 || P == 8192 ||
            P == 16384 || P == 32768;
+}
+
+hipError_t last_twiddles(int P, const uint32_t *d_tw, const float4 **out) {
+    *out = nullptr;
+    if (P <= kMaxEngine) return hipSuccess;
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static const float4 *tables[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!tables[dev]) {
+        // the symbol's device address on this device (the host-side name is not one)
+        void *addr = nullptr;
+        e = hipGetSymbolAddress(&addr, HIP_SYMBOL(g_twl_split));
+        if (e != hipSuccess) return e;
+        float4 *dst = static_cast<float4 *>(addr);
+        hipLaunchKernelGGL((k_last_twiddles<kSplitEK>), dim3(Cfg<kSplitEK>::RT - 1), dim3(Cfg<kSplitEK>::T), 0,
+                           nullptr, d_tw, dst);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) return e;
+        tables[dev] = dst;
+    }
+    *out = tables[dev];
+    return hipSuccess;
 }
 
 #define SSP_DISPATCH_P(P, CALL) \
