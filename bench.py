@@ -402,6 +402,21 @@ def transform_rooflines(ssp, torch, stream, dev, reps=20):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3 / reps
 
+    # achievable HBM bandwidth: a plain device copy of 1 GiB (read + write), the reference
+    # beside the datasheet peak for the FFT-path fractions below
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    with torch.cuda.stream(stream):
+        a.fill_(1.0)
+
+    def copy_once():
+        with torch.cuda.stream(stream):  # on the stream the events are recorded on
+            b.copy_(a)
+    tc = timed(copy_once)
+    copy_gbs = 2.0 * a.numel() * 4 / tc
+    del a, b
+    out["hbm_copy"] = {"kernel": "torch copy_ (1 GiB)", "achieved": copy_gbs / 1e9, "peak": PEAK_HBM / 1e9,
+                       "unit": "GB/s", "frac": copy_gbs / PEAK_HBM}
     # chirp-z at Nz = 4096; the direct sine transform (one FFT of length 2 (Nz + 1)) at 4095
     for key, nz, kernel in (("dst_fft", 4096, f"k_transform<{_fft_len(4096)}, 0>"),
                             ("dst_fft_direct", 4095, "k_transform<8192, 2>")):
@@ -414,7 +429,8 @@ def transform_rooflines(ssp, torch, stream, dev, reps=20):
         ssp.ssp_plan_destroy(pl)
         gbs = 16.0 * nz * B / t
         out[key] = {"kernel": kernel, "nz": nz, "vectors": B, "bound": "hbm", "achieved": gbs / 1e9,
-                    "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": gbs / PEAK_HBM, "ms_per_call": 1e3 * t}
+                    "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": gbs / PEAK_HBM,
+                    "frac_of_copy": gbs / copy_gbs, "ms_per_call": 1e3 * t}
     nz, B = 2048, 1024
     pl = ssp.ssp_plan_create(nz, 5000.0, 50.0, 1500.0, 25.0, 6, 48, 1e-10)
     ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
