@@ -131,6 +131,10 @@ enum { SSP_BC_DIRICHLET = 0, SSP_BC_NEUMANN = 1, SSP_BC_PERIODIC = 2 };
  *   neumann_max  largest Neumann index M >= 0 (0: the m = 0 term only, Sec. 4.1 "M = 0")
  *   tol          > 0; a series stops at the first m >= 1 with ||term_m|| <= tol ||w^(m)||
  * The environment defaults to c = c0 (v = 0) until ssp_set_profile* is called.
+ * Tables are uploaded synchronously.  The first plan on a device whose FFT length exceeds
+ * the largest single-workgroup FFT (Nz > 8192 for chirp-z plans) also fills a shared
+ * twiddle table on that device: one small kernel on the null stream, waited for (so do not
+ * create such a plan while a stream capture that forbids null-stream work is in progress).
  * Errors: SSP_E_INVAL, SSP_E_UNSTABLE, SSP_E_UNIMPL (Nz too large), SSP_E_NOMEM,
  * SSP_E_DEVICE.  *out is set to NULL on error. */
 ssp_status ssp_plan_create(int Nz, double H, double f, double c0, double dr, int pade_order,
