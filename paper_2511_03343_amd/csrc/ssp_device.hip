@@ -1065,11 +1065,12 @@ __global__ __launch_bounds__(kFamilyT) void k_march_family(const SolveDesc *__re
 
 // ----------------------------------------------------------------------------- transforms
 // Persistent over the batch: workgroup g transforms vectors g, g + G, g + 2G, ... (G =
-// gridDim.x <= B), so the twiddles are set up once per workgroup, and the next vector's
-// input is loaded while the current one is transformed.  Each vector's in and out may be
-// the same memory: vector v's output is stored after its input was read, and no other
-// vector's input lies there.  Layout 0 (the most threads per workgroup) is used for every
-// length: it measured faster for stand-alone transforms than the march's tuned layouts.
+// gridDim.x <= B, the workgroups that can be resident at once), so the twiddles are set up
+// once per workgroup, and the next vector's input is loaded while the current one is
+// transformed.  Each vector's in and out may be the same memory: vector v's output is
+// stored after its input was read, and no other vector's input lies there.  Layout 0 (the
+// most threads per workgroup) is used for every length: it measured faster for stand-alone
+// transforms than the march's tuned layouts.
 template <int P, int DK>
 __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_transform(const SolveDesc *__restrict__ desc, int mode,
                                                          const float2 *in, float2 *out,
@@ -1385,31 +1386,40 @@ hipError_t launch_march_PV(int v, const SolveDesc *d_descs, int nsolves, int nst
     return launch_march_P<P, 0>(d_descs, nsolves, nsteps, stream);
 }
 
+// Grid of a persistent launch over B items: as many workgroups as can be resident at once
+// (compute units x the kernel's occupancy per compute unit), at most B.
+template <typename K>
+hipError_t persistent_grid(K kernel, int threads, int B, int *grid) {
+    int dev = 0, cus = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0);
+    if (e != hipSuccess) return e;
+    const long long g = static_cast<long long>(cus > 0 ? cus : 1) * (per > 0 ? per : 1);
+    *grid = B < g ? B : static_cast<int>(g);
+    return hipSuccess;
+}
+
+template <int P, int DK>
+hipError_t launch_transform_PK(int mode, const SolveDesc *d_desc, int B, const float2 *in, float2 *out,
+                               const long long *step, hipStream_t stream) {
+    constexpr int T = ECfg<P, 0>::T;
+    int G = 0;
+    const hipError_t e = persistent_grid(k_transform<P, DK>, T, B, &G);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_transform<P, DK>), dim3(G), dim3(T), 0, stream, d_desc, mode, in, out, step, B);
+    return hipGetLastError();
+}
+
 template <int P>
 hipError_t launch_transform_P(int direct, int mode, const SolveDesc *d_desc, int B, const float2 *in,
                               float2 *out, const long long *step, hipStream_t stream) {
-    // one resident workgroup per compute unit (the LDS of one transform fills most of it)
-    int dev = 0, cus = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return e;
-    const int G = B < cus ? B : (cus > 0 ? cus : 1);
     if constexpr (P <= kMaxEngine) {
-        if (direct == kDkFourier) {
-            hipLaunchKernelGGL((k_transform<P, kDkFourier>), dim3(G), dim3(ECfg<P, 0>::T), 0, stream, d_desc,
-                               mode, in, out, step, B);
-            return hipGetLastError();
-        }
-        if (direct == kDkSine) {
-            hipLaunchKernelGGL((k_transform<P, kDkSine>), dim3(G), dim3(ECfg<P, 0>::T), 0, stream, d_desc,
-                               mode, in, out, step, B);
-            return hipGetLastError();
-        }
+        if (direct == kDkFourier) return launch_transform_PK<P, kDkFourier>(mode, d_desc, B, in, out, step, stream);
+        if (direct == kDkSine) return launch_transform_PK<P, kDkSine>(mode, d_desc, B, in, out, step, stream);
     }
     if (direct != kDkChirp) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_transform<P, kDkChirp>), dim3(G), dim3(ECfg<P, 0>::T), 0, stream, d_desc, mode, in, out,
-                       step, B);
-    return hipGetLastError();
+    return launch_transform_PK<P, kDkChirp>(mode, d_desc, B, in, out, step, stream);
 }
 
 // Last-pass twiddle table of the split-transform engine (one per device) and the kernel
