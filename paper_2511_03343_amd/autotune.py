@@ -74,9 +74,9 @@ def time_layout(ssp, torch, P: int, variant: int, batch: int, steps: int, reps: 
     return best, out
 
 
-def write_header(choice: dict) -> None:
+def write_header(choice: dict, path: str = HEADER) -> None:
     vals = ", ".join(str(choice.get(P, 0)) for P in LENGTHS)
-    with open(HEADER, "w") as f:
+    with open(path, "w") as f:
         f.write("// ssp_tuned.h - engine layout of the fused march kernel per FFT length, chosen by\n"
                 "// paper_2511_03343_amd/autotune.py (written by that script; do not edit by hand).\n"
                 "#pragma once\n\n"
@@ -89,6 +89,7 @@ def write_header(choice: dict) -> None:
 def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--write", action="store_true", help="write csrc/ssp_tuned.h")
+    ap.add_argument("--out", default=HEADER, help="where --write puts the header (default: csrc/ssp_tuned.h)")
     ap.add_argument("--steps", type=int, default=12)
     ap.add_argument("--reps", type=int, default=2)
     args = ap.parse_args()
@@ -119,8 +120,8 @@ def main() -> None:
         report.append(row)
         print(json.dumps(row), flush=True)
     if args.write:
-        write_header(choice)
-        print(f"wrote {HEADER}", flush=True)
+        write_header(choice, args.out)
+        print(f"wrote {args.out}", flush=True)
 
 
 if __name__ == "__main__":

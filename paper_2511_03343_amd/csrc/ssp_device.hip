@@ -331,7 +331,8 @@ constexpr int mid_tab_offset() { return mid_tab_len<P>() - mid_tab_from<P, Ns>()
 // (Unsplit 1024-thread engines measured faster with register twiddles and a few spills.)
 template <int P>
 struct Twiddles {
-    static constexpr bool kRegs = !key_split(P);
+    static constexpr bool kRegs = !key_split(P) && key_var(P) != 2;
+    static constexpr bool kPrefetch = key_split(P);  // table twiddles loaded ahead of the barrier
     static constexpr int NTW = kRegs ? Cfg<P>::RT - 1 : 1;
     float2 h[NTW];   // FP32 nearest value
     uint32_t l[NTW]; // remainder as two bf16 (re high, im low)
@@ -425,7 +426,7 @@ __device__ __forceinline__ void before_write() {
 // middle passes: read phase PH (padding SHR), write phase PH + 1 (padding mid_shift(Ns));
 // Ns = current stride until it reaches T
 template <int P>
-constexpr int last_tab_regs() { return Twiddles<P>::kRegs ? 1 : Cfg<P>::RT - 1; }
+constexpr int last_tab_regs() { return Twiddles<P>::kPrefetch ? Cfg<P>::RT - 1 : 1; }
 template <int P, bool INV, int Ns, int PH, int SHR>
 __device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBufs &L,
                                            const Twiddles<P> &tw, float4 (&wl)[last_tab_regs<P>()]) {
@@ -482,7 +483,7 @@ __device__ __forceinline__ void mid_passes(float2 (&x)[Cfg<P>::RT], const LdsBuf
                 for (int r = 0; r < R; ++r) out[lps<SHW>(base + r * Ns)] = v[r];
             }
         }
-        if constexpr (!Twiddles<P>::kRegs && Ns * R >= T) {
+        if constexpr (Twiddles<P>::kPrefetch && Ns * R >= T) {
             // the last pass's table twiddles, loaded before its barrier so that their latency
             // overlaps the wait
             const int t3 = opaque_tid();
@@ -536,9 +537,16 @@ __device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, c
         if constexpr (Twiddles<P>::kRegs) {
 #pragma unroll
             for (int r = 1; r < RT; ++r) x[r] = twmul<INV>(x[r], tw.h[r - 1], tw.l[r - 1]);
-        } else {
+        } else if constexpr (Twiddles<P>::kPrefetch) {
 #pragma unroll
             for (int r = 1; r < RT; ++r) x[r] = INV ? cmul_df_conj(x[r], wl[r - 1]) : cmul_df(x[r], wl[r - 1]);
+        } else {
+            const int t3 = opaque_tid();
+#pragma unroll
+            for (int r = 1; r < RT; ++r) {
+                const float4 w = ld4(tw.tab, (r - 1) * T + t3);
+                x[r] = INV ? cmul_df_conj(x[r], w) : cmul_df(x[r], w);
+            }
         }
         if constexpr (HALF_OUT && RT >= 2) DftHalfOut<RT, INV>::run(x);
         else Dft<RT, INV>::run(x);
@@ -1422,12 +1430,18 @@ hipError_t launch_transform_P(int direct, int mode, const SolveDesc *d_desc, int
     return launch_transform_PK<P, kDkChirp>(mode, d_desc, B, in, out, step, stream);
 }
 
-// Last-pass twiddle table of the split-transform engine (one per device) and the kernel
-// that fills it from the first-octant table: block r-1 holds w^{r t}.
+// Last-pass twiddle tables of the engines that read them (the split-transform engine and
+// the layout-2 engines of 4096 and 8192; one per engine and device) and the kernel that
+// fills one from the first-octant table: block r-1 holds w^{r t}.
 constexpr int kSplitEK = eng_key<2 * kMaxEngine, 0>();
-constexpr int kTwlSplit = (Cfg<kSplitEK>::RT - 1) * Cfg<kSplitEK>::T;
-static_assert(!Twiddles<kSplitEK>::kRegs && Cfg<kSplitEK>::T == 1024, "split engine reads a table");
-__device__ float4 g_twl_split[kTwlSplit];
+constexpr int kV2EK4096 = eng_key<4096, 2>(), kV2EK8192 = eng_key<8192, 2>();
+template <int EK>
+constexpr int twl_len() { return (Cfg<EK>::RT - 1) * Cfg<EK>::T; }
+static_assert(!Twiddles<kSplitEK>::kRegs && !Twiddles<kV2EK4096>::kRegs && !Twiddles<kV2EK8192>::kRegs,
+              "engines that read a table");
+__device__ float4 g_twl_split[twl_len<kSplitEK>()];
+__device__ float4 g_twl_v2_4096[twl_len<kV2EK4096>()];
+__device__ float4 g_twl_v2_8192[twl_len<kV2EK8192>()];
 
 template <int EK>
 __global__ __launch_bounds__(Cfg<EK>::T) void k_last_twiddles(const uint32_t *__restrict__ tab,
@@ -1490,29 +1504,39 @@ bool fft_length_supported(int P) {
 
 hipError_t last_twiddles(int P, const uint32_t *d_tw, const float4 **out) {
     *out = nullptr;
-    if (P <= kMaxEngine) return hipSuccess;
+    const int which = P > kMaxEngine ? 0 : P == 8192 ? 1 : P == 4096 ? 2 : -1;
+    if (which < 0) return hipSuccess;
     constexpr int kMaxDevices = 64;
     static std::mutex mu;
-    static const float4 *tables[kMaxDevices] = {};
+    static const float4 *tables[kMaxDevices][3] = {};
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
     std::lock_guard<std::mutex> lock(mu);
-    if (!tables[dev]) {
+    if (!tables[dev][which]) {
         // the symbol's device address on this device (the host-side name is not one)
         void *addr = nullptr;
-        e = hipGetSymbolAddress(&addr, HIP_SYMBOL(g_twl_split));
+        e = which == 0 ? hipGetSymbolAddress(&addr, HIP_SYMBOL(g_twl_split))
+            : which == 1 ? hipGetSymbolAddress(&addr, HIP_SYMBOL(g_twl_v2_8192))
+                         : hipGetSymbolAddress(&addr, HIP_SYMBOL(g_twl_v2_4096));
         if (e != hipSuccess) return e;
         float4 *dst = static_cast<float4 *>(addr);
-        hipLaunchKernelGGL((k_last_twiddles<kSplitEK>), dim3(Cfg<kSplitEK>::RT - 1), dim3(Cfg<kSplitEK>::T), 0,
-                           nullptr, d_tw, dst);
+        if (which == 0)
+            hipLaunchKernelGGL((k_last_twiddles<kSplitEK>), dim3(Cfg<kSplitEK>::RT - 1), dim3(Cfg<kSplitEK>::T), 0,
+                               nullptr, d_tw, dst);
+        else if (which == 1)
+            hipLaunchKernelGGL((k_last_twiddles<kV2EK8192>), dim3(Cfg<kV2EK8192>::RT - 1), dim3(Cfg<kV2EK8192>::T),
+                               0, nullptr, d_tw, dst);
+        else
+            hipLaunchKernelGGL((k_last_twiddles<kV2EK4096>), dim3(Cfg<kV2EK4096>::RT - 1), dim3(Cfg<kV2EK4096>::T),
+                               0, nullptr, d_tw, dst);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess) return e;
-        tables[dev] = dst;
+        tables[dev][which] = dst;
     }
-    *out = tables[dev];
+    *out = tables[dev][which];
     return hipSuccess;
 }
 
