@@ -854,8 +854,10 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     // 1024 threads (those layouts run two waves per SIMD, so 256 registers per lane)
     constexpr bool kBInRegs = (RL <= 8) && (T < 1024);
     constexpr int EB = kBInRegs ? RL : 1;
-    // ... and so does the potential A = v (.) dmod; otherwise both come from L2
-    constexpr bool kAInRegs = kBInRegs;
+    // ... and so does the potential A = v (.) dmod, also in the layouts of two workgroups
+    // per compute unit (16 live elements, registers to spare once their twiddles come from a
+    // table); otherwise it comes from L2
+    constexpr bool kAInRegs = kBInRegs || (ECfg<P, V>::SINGLE && RL <= 16);
     constexpr int EA = kAInRegs ? RL : 1;
     // the series sum w_j stays in registers up to 8 elements per thread or below 1024
     // threads (else in d.wacc)
