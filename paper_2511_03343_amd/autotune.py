@@ -34,8 +34,10 @@ def _engine_threads(P: int, v: int) -> int:
     """Thread counts of the layouts (the same rule as the kernels)."""
     PE = P // 2 if P > 16384 else P
     t0 = 64 if PE <= 512 else (128 if PE == 1024 else (256 if PE <= 4096 else 1024))
+    if P > 16384:  # the split engine has one layout
+        return t0
     t1 = {1024: 64, 2048: 128, 4096: 512, 8192: 512}.get(PE, t0)
-    t2 = {4096: 128, 8192: 256}.get(PE, t0)
+    t2 = {4096: 128, 8192: 256, 16384: 512}.get(PE, t0)
     return (t0, t1, t2)[v]
 
 

@@ -259,7 +259,9 @@ constexpr int threads_v1(int P) {
 }
 // variant 2: 32 elements per thread with a single LDS buffer, so that two workgroups share
 // a compute unit and cover each other's barriers
-constexpr int threads_v2(int P) { return P == 4096 ? 128 : (P == 8192 ? 256 : threads_v0(P)); }
+constexpr int threads_v2(int P) {
+    return P == 4096 ? 128 : (P == 8192 ? 256 : (P == 16384 ? 512 : threads_v0(P)));
+}
 constexpr int threads_for(int P, int V) {
     return V == 2 ? threads_v2(P) : (V == 1 ? threads_v1(P) : threads_v0(P));
 }
@@ -1390,7 +1392,7 @@ hipError_t launch_march_PV(int v, const SolveDesc *d_descs, int nsolves, int nst
     if constexpr (variant_exists(eng_len<P>(), 1)) {
         if (v == 1) return launch_march_P<P, 1>(d_descs, nsolves, nsteps, stream);
     }
-    if constexpr (variant_exists(eng_len<P>(), 2)) {
+    if constexpr (P <= kMaxEngine && variant_exists(eng_len<P>(), 2)) {  // split lengths: layout 0 only
         if (v == 2) return launch_march_P<P, 2>(d_descs, nsolves, nsteps, stream);
     }
     return launch_march_P<P, 0>(d_descs, nsolves, nsteps, stream);
@@ -1436,14 +1438,16 @@ hipError_t launch_transform_P(int direct, int mode, const SolveDesc *d_desc, int
 // the layout-2 engines of 4096 and 8192; one per engine and device) and the kernel that
 // fills one from the first-octant table: block r-1 holds w^{r t}.
 constexpr int kSplitEK = eng_key<2 * kMaxEngine, 0>();
-constexpr int kV2EK4096 = eng_key<4096, 2>(), kV2EK8192 = eng_key<8192, 2>();
+constexpr int kV2EK4096 = eng_key<4096, 2>(), kV2EK8192 = eng_key<8192, 2>(), kV2EK16384 = eng_key<16384, 2>();
 template <int EK>
 constexpr int twl_len() { return (Cfg<EK>::RT - 1) * Cfg<EK>::T; }
-static_assert(!Twiddles<kSplitEK>::kRegs && !Twiddles<kV2EK4096>::kRegs && !Twiddles<kV2EK8192>::kRegs,
+static_assert(!Twiddles<kSplitEK>::kRegs && !Twiddles<kV2EK4096>::kRegs && !Twiddles<kV2EK8192>::kRegs &&
+                  !Twiddles<kV2EK16384>::kRegs,
               "engines that read a table");
 __device__ float4 g_twl_split[twl_len<kSplitEK>()];
 __device__ float4 g_twl_v2_4096[twl_len<kV2EK4096>()];
 __device__ float4 g_twl_v2_8192[twl_len<kV2EK8192>()];
+__device__ float4 g_twl_v2_16384[twl_len<kV2EK16384>()];
 
 template <int EK>
 __global__ __launch_bounds__(Cfg<EK>::T) void k_last_twiddles(const uint32_t *__restrict__ tab,
@@ -1485,7 +1489,8 @@ hipError_t launch_march_direct_P(int kind, const SolveDesc *d_descs, int nsolves
 bool march_family_member(int P) { return P == 8192 || P == 16384 || P == 32768; }
 
 bool engine_variant_exists(int P, int variant) {
-    return variant >= 0 && variant <= 2 && variant_exists(P > kMaxEngine ? P / 2 : P, variant);
+    if (P > kMaxEngine) return variant == 0;  // the split engine has one layout
+    return variant >= 0 && variant <= 2 && variant_exists(P, variant);
 }
 
 int engine_threads(int P, int variant) {
@@ -1506,11 +1511,11 @@ bool fft_length_supported(int P) {
 
 hipError_t last_twiddles(int P, const uint32_t *d_tw, const float4 **out) {
     *out = nullptr;
-    const int which = P > kMaxEngine ? 0 : P == 8192 ? 1 : P == 4096 ? 2 : -1;
+    const int which = P > kMaxEngine ? 0 : P == 8192 ? 1 : P == 4096 ? 2 : P == 16384 ? 3 : -1;
     if (which < 0) return hipSuccess;
     constexpr int kMaxDevices = 64;
     static std::mutex mu;
-    static const float4 *tables[kMaxDevices][3] = {};
+    static const float4 *tables[kMaxDevices][4] = {};
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -1519,9 +1524,10 @@ hipError_t last_twiddles(int P, const uint32_t *d_tw, const float4 **out) {
     if (!tables[dev][which]) {
         // the symbol's device address on this device (the host-side name is not one)
         void *addr = nullptr;
-        e = which == 0 ? hipGetSymbolAddress(&addr, HIP_SYMBOL(g_twl_split))
+        e = which == 0   ? hipGetSymbolAddress(&addr, HIP_SYMBOL(g_twl_split))
             : which == 1 ? hipGetSymbolAddress(&addr, HIP_SYMBOL(g_twl_v2_8192))
-                         : hipGetSymbolAddress(&addr, HIP_SYMBOL(g_twl_v2_4096));
+            : which == 2 ? hipGetSymbolAddress(&addr, HIP_SYMBOL(g_twl_v2_4096))
+                         : hipGetSymbolAddress(&addr, HIP_SYMBOL(g_twl_v2_16384));
         if (e != hipSuccess) return e;
         float4 *dst = static_cast<float4 *>(addr);
         if (which == 0)
@@ -1530,9 +1536,12 @@ hipError_t last_twiddles(int P, const uint32_t *d_tw, const float4 **out) {
         else if (which == 1)
             hipLaunchKernelGGL((k_last_twiddles<kV2EK8192>), dim3(Cfg<kV2EK8192>::RT - 1), dim3(Cfg<kV2EK8192>::T),
                                0, nullptr, d_tw, dst);
-        else
+        else if (which == 2)
             hipLaunchKernelGGL((k_last_twiddles<kV2EK4096>), dim3(Cfg<kV2EK4096>::RT - 1), dim3(Cfg<kV2EK4096>::T),
                                0, nullptr, d_tw, dst);
+        else
+            hipLaunchKernelGGL((k_last_twiddles<kV2EK16384>), dim3(Cfg<kV2EK16384>::RT - 1),
+                               dim3(Cfg<kV2EK16384>::T), 0, nullptr, d_tw, dst);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess) return e;

@@ -4,5 +4,5 @@
 
 namespace ssp {
 // kTunedVariant[log2(P) - 7] for P = 128 ... 32768
-constexpr int kTunedVariant[9] = {0, 0, 0, 0, 1, 0, 2, 0, 0};
+constexpr int kTunedVariant[9] = {0, 0, 0, 0, 1, 2, 2, 2, 0};
 }  // namespace ssp

@@ -399,7 +399,7 @@ def test_plain_form_equals_fused_bitwise(ssp, gpu, nz, env):
 
 # every engine layout of the lengths that have several (FFT lengths 1024 ... 8192; a layout
 # a length does not have falls back to layout 0)
-@pytest.mark.parametrize("nz", [510, 1000, 2046, 4096])
+@pytest.mark.parametrize("nz", [510, 1000, 2046, 4096, 6000])
 @pytest.mark.parametrize("variant", [0, 1, 2])
 def test_engine_layouts_vs_oracle(ssp, gpu, nz, variant):
     s = W.munk_deep(nsteps=16, nz=nz)
