@@ -45,8 +45,8 @@ PEAK_HBM = 8.0e12      # MI355X HBM3E (B/s)
 # shape and a fingerprint of the kernel sources and layout table: any change to them makes
 # the figure stale, and it is then reported as null.
 TRAFFIC = {
-    ("munk4096", 512, 100): {"fingerprint": "efbb69b8dc15e619", "fetch": 44315264.0,
-                             "write": 4284585456.0},
+    ("munk4096", 4096, 512, 100): {"fingerprint": "528f050cc1a9b81d", "fetch": 2586548864.0,
+                                   "write": 9365851104.0},
 }
 
 
@@ -59,8 +59,8 @@ def source_fingerprint():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, batch, chunk, bc="dirichlet"):
-    t = TRAFFIC.get((workload, batch, chunk)) if bc == "dirichlet" else None
+def measured_traffic(workload, nz, batch, chunk, bc="dirichlet"):
+    t = TRAFFIC.get((workload, nz, batch, chunk)) if bc == "dirichlet" else None
     if t is None or t["fingerprint"] != source_fingerprint():
         return None
     return t["fetch"] + t["write"]
@@ -307,7 +307,7 @@ def run_device_batch(args, ssp, torch, stream, dev):
     ssp.ssp_plan_destroy(pl)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
-            "traffic": measured_traffic(args.workload, B, args.chunk, args.bc)
+            "traffic": measured_traffic(args.workload, s.nz, B, args.chunk, args.bc)
             if args.absorber is None else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": (f"k_march_direct<{P}, {layout}, {direct}>" if direct

@@ -70,8 +70,10 @@ enum {
                               calls with the same arguments; needs a non-null stream.
                               0 (default): plain launches */
     SSP_OPT_VARIANT = 6    /* engine layout of the fused march kernel: -1 (default) = the
-                              layout the autotuner chose for this FFT length; 0, 1 or 2 = that
-                              layout (falls back to 0 where the length has no such layout).
+                              layout the autotuner chose for this FFT length and transform
+                              kind (chirp-z, direct Fourier, direct sine); 0, 1 or 2 = that
+                              layout (falls back to 0 where the length has no such layout;
+                              split lengths, P > 16384, have layout 0 only).
                               Layouts differ in rounding only; a solve's results do not
                               depend on what it is batched with. */
 };
@@ -114,8 +116,8 @@ typedef struct {
  *                     e^{-2 pi i l n/Nz}/sqrt(Nz)), basis e^{2 pi i l' z/H}, l' = l for
  *                     l <= Nz/2 and l - Nz above.  Nz a power of two in [128, 16384]: the
  *                     transforms are direct FFTs of length Nz (else chirp-z ones of length
- *                     >= 2 Nz - 1); such plans run the fused kernel in its autotuned layout
- *                     only (SSP_OPT_VARIANT is ignored, SSP_OPT_ENGINE = 1 gives SSP_E_UNIMPL)
+ *                     >= 2 Nz - 1); such plans run the fused kernel only
+ *                     (SSP_OPT_ENGINE = 1 gives SSP_E_UNIMPL)
  * Every basis function is an eigenfunction of d_z^2 (eigenvalue -kappa_l^2, kappa_l = l pi/H
  * or 2 pi l'/H), which makes the isovelocity operator of every Pade term diagonal.  The
  * coefficient-space field kept on the device ("sine basis" below) is that of the plan's

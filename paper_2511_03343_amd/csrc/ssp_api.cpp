@@ -233,11 +233,13 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     return SSP_OK;
 }
 
-// Engine layout of the plan's march: the option if set, else the autotuned choice.
+// Engine layout of the plan's march: the option if set, else the autotuned choice (per
+// transform kind).
 int effective_variant(const ssp_plan *pl) {
-    if (pl->tab.direct) return ssp::direct_variant(pl->P);  // one layout per direct length
     int v = pl->variant_opt;
-    if (v < 0) {
+    if (v < 0 && pl->tab.direct) {
+        v = ssp::direct_variant(pl->P, pl->tab.direct);
+    } else if (v < 0) {
         int lg = 0;
         while ((1 << lg) < pl->P) ++lg;
         const int idx = lg - 7;

@@ -79,8 +79,8 @@ inline void set_work(SolveDesc &d, float2 *base) {
 
 hipError_t launch_march(int P, int variant, int direct, const SolveDesc *d_descs, int nsolves, int nsteps,
                         hipStream_t stream);
-// Layout of the direct-transform march of length P (the autotuned layout of that length).
-int direct_variant(int P);
+// Autotuned layout of the direct-transform march of length P and kind (1 Fourier, 2 sine).
+int direct_variant(int P, int kind);
 
 // Engine layouts of the march kernel: variant 0 is the default; variants 1 and 2 (where they
 // exist) use other thread counts, i.e. other radices for the first and last FFT passes

@@ -1460,25 +1460,30 @@ __global__ __launch_bounds__(Cfg<EK>::T) void k_last_twiddles(const uint32_t *__
     out[blockIdx.x * T + t] = make_float4(h.x, h.y, __uint_as_float(l & 0xffff0000u), __uint_as_float(l << 16));
 }
 
-// direct marches run the autotuned layout of their length only
-constexpr int tuned_variant(int P) {
-    int lg = 0;
-    while ((1 << lg) < P) ++lg;
-    return kTunedVariant[lg - 7];
+// direct marches: every layout of the length (the plan picks one; see direct_variant)
+template <int P, int V>
+hipError_t launch_march_direct_PV(int kind, const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
+    if (kind == kDkFourier)
+        hipLaunchKernelGGL((k_march_direct<P, V, kDkFourier>), dim3(nsolves), dim3(ECfg<P, V>::T), 0, stream,
+                           d_descs, nsteps);
+    else if (kind == kDkSine)
+        hipLaunchKernelGGL((k_march_direct<P, V, kDkSine>), dim3(nsolves), dim3(ECfg<P, V>::T), 0, stream,
+                           d_descs, nsteps);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 template <int P>
-hipError_t launch_march_direct_P(int kind, const SolveDesc *d_descs, int nsolves, int nsteps, hipStream_t stream) {
+hipError_t launch_march_direct_P(int kind, int v, const SolveDesc *d_descs, int nsolves, int nsteps,
+                                 hipStream_t stream) {
     if constexpr (P <= kMaxEngine) {
-        constexpr int V = variant_exists(P, tuned_variant(P)) ? tuned_variant(P) : 0;
-        if (kind == kDkFourier)
-            hipLaunchKernelGGL((k_march_direct<P, V, kDkFourier>), dim3(nsolves), dim3(ECfg<P, V>::T), 0, stream,
-                               d_descs, nsteps);
-        else if (kind == kDkSine)
-            hipLaunchKernelGGL((k_march_direct<P, V, kDkSine>), dim3(nsolves), dim3(ECfg<P, V>::T), 0, stream,
-                               d_descs, nsteps);
-        else
-            return hipErrorInvalidValue;
-        return hipGetLastError();
+        if constexpr (variant_exists(P, 1)) {
+            if (v == 1) return launch_march_direct_PV<P, 1>(kind, d_descs, nsolves, nsteps, stream);
+        }
+        if constexpr (variant_exists(P, 2)) {
+            if (v == 2) return launch_march_direct_PV<P, 2>(kind, d_descs, nsolves, nsteps, stream);
+        }
+        return launch_march_direct_PV<P, 0>(kind, d_descs, nsolves, nsteps, stream);
     } else {
         return hipErrorInvalidValue;
     }
@@ -1568,19 +1573,21 @@ hipError_t last_twiddles(int P, const uint32_t *d_tw, const float4 **out) {
 hipError_t launch_march(int P, int variant, int direct, const SolveDesc *d_descs, int nsolves, int nsteps,
                         hipStream_t stream) {
     if (nsolves <= 0 || nsteps <= 0) return hipSuccess;
+    const int v = engine_variant_exists(P, variant) ? variant : 0;
     if (direct != kDkChirp) {
-#define CALL_D(PP) launch_march_direct_P<PP>(direct, d_descs, nsolves, nsteps, stream)
+#define CALL_D(PP) launch_march_direct_P<PP>(direct, v, d_descs, nsolves, nsteps, stream)
         SSP_DISPATCH_P(P, CALL_D)
 #undef CALL_D
     }
-    const int v = engine_variant_exists(P, variant) ? variant : 0;
 #define CALL_M(PP) launch_march_PV<PP>(v, d_descs, nsolves, nsteps, stream)
     SSP_DISPATCH_P(P, CALL_M)
 #undef CALL_M
 }
 
-int direct_variant(int P) {
-    return (P >= 128 && P <= kMaxEngine && variant_exists(P, tuned_variant(P))) ? tuned_variant(P) : 0;
+int direct_variant(int P, int kind) {
+    if (P < 128 || P > kMaxEngine || (kind != kDkFourier && kind != kDkSine)) return 0;
+    const int v = kTunedDirect[kind - 1][__builtin_ctz(P) - 7];
+    return variant_exists(P, v) ? v : 0;
 }
 
 hipError_t launch_output(int P, int direct, const SolveDesc *d_descs, int nsolves, int nout, hipStream_t stream) {

@@ -288,6 +288,24 @@ def test_periodic_direct_fft_lengths_vs_oracle(ssp, gpu, nz, nsteps):
     compare(f"periodic direct nz={nz}", fld, tl, ref)
 
 
+@pytest.mark.parametrize("nz", [1024, 2048, 4096, 8192])
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_periodic_direct_layouts_vs_oracle(ssp, gpu, nz, variant):
+    # every engine layout of the direct Fourier march (a layout the length does not have
+    # falls back to layout 0)
+    s = with_bc(W.munk_deep(nsteps=12, nz=nz), "periodic")
+    s.out_every = 4
+    pl = make_plan(ssp, s)
+    try:
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, variant)
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert st == ref.status
+    compare(f"periodic direct layout {variant} nz={nz}", fld, tl, ref)
+
+
 def test_periodic_direct_rejects_the_plain_form(ssp, gpu):
     s = with_bc(W.munk_deep(nsteps=2, nz=1024), "periodic")
     pl = make_plan(ssp, s)

@@ -203,3 +203,22 @@ def test_munk_long_range(ssp, gpu):
     dtl = np.abs(tl.astype(np.float64) - ref.tl)[mask]
     _report("direct sine munk long", relL2=" ".join(f"{e:.2e}" for e in err), max_dTL=f"{dtl.max():.3e}")
     assert err.max() <= REL_L2 and dtl.max() <= DTL
+
+
+@pytest.mark.parametrize("nz", [1023, 2047, 4095, 8191])
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_layouts_vs_oracle(ssp, gpu, nz, variant):
+    # every engine layout of the direct sine march (a layout the length does not have falls
+    # back to layout 0)
+    s = W.munk_deep(nsteps=12, nz=nz)
+    s.out_every = 4
+    pl = make_plan(ssp, s)
+    try:
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, variant)
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert st == ref.status
+    err = np.linalg.norm(fld - ref.field, axis=1) / np.linalg.norm(ref.field, axis=1)
+    assert err.max() <= REL_L2
