@@ -258,7 +258,8 @@ constexpr int threads_v1(int P) {
     return P == 1024 ? 64 : (P == 2048 ? 128 : (P == 4096 ? 512 : (P == 8192 ? 512 : threads_v0(P))));
 }
 // variant 2: 32 elements per thread with a single LDS buffer, so that two workgroups share
-// a compute unit and cover each other's barriers
+// a compute unit and cover each other's barriers (at 16384 one workgroup of 512 threads,
+// one FFT pass fewer than variant 0)
 constexpr int threads_v2(int P) {
     return P == 4096 ? 128 : (P == 8192 ? 256 : (P == 16384 ? 512 : threads_v0(P)));
 }
@@ -327,10 +328,13 @@ template <int P, int Ns>
 constexpr int mid_tab_offset() { return mid_tab_len<P>() - mid_tab_from<P, Ns>(); }
 
 // Twiddles of the last pass (w_P^{r t}, r = 1..RT-1): per thread, held in registers, except
-// in the engine of split transforms (1024 threads, 128 registers per lane, which the second
-// half's state leaves short): it reads them from a device table ([r-1][t], coalesced, shared
-// by every workgroup, so it stays in L2), loaded before the barrier that precedes their use.
-// (Unsplit 1024-thread engines measured faster with register twiddles and a few spills.)
+// where registers are short: the engine of split transforms (1024 threads, 128 registers
+// per lane, which the second half's state leaves short) and the layout-2 engines (31
+// twiddles per thread, 93 registers) read them from a device table ([r-1][t], coalesced,
+// shared by every workgroup, so it stays in L2).  The split engine loads them before the
+// barrier that precedes their use; layout 2 at their use (the other workgroup on the compute
+// unit covers the latency).  (The unsplit 1024-thread engines measured faster with register
+// twiddles and a few spills.)
 template <int P>
 struct Twiddles {
     static constexpr bool kRegs = !key_split(P) && key_var(P) != 2;
