@@ -227,6 +227,29 @@ def test_eddy_range_dependent(ssp, gpu, profile):
     compare(f"eddy {profile}", fld, tl, ref)
 
 
+@pytest.mark.parametrize("nz,nsteps", [(2046, 24), (4096, 20), (6000, 16)])
+@pytest.mark.parametrize("profile", ["table", "analytic"])
+def test_eddy_in_two_workgroup_layouts(ssp, gpu, nz, nsteps, profile):
+    # FFT lengths 4096 ... 16384 run layout 2 (the potential held in registers and reloaded
+    # every step of a range-dependent environment); the eddy (r0 = 1.5 km) is crossed
+    s = W.munk_eddy(nsteps=nsteps, nz=nz, neumann_max=24)
+    s.dr = 250.0 / 3.0
+    s.out_every = 4
+    s.eddy = W.Eddy(r0=1500.0, rr=1000.0)
+    pl = make_plan(ssp, s, profile=profile)
+    try:
+        assert ssp.ssp_plan_engine(pl)[0] == 2
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert st == ref.status
+    # (series that end within rounding of the tolerance may stop a term apart in FP32 and
+    # FP64 arithmetic: the term counts are reported, the fields compared)
+    _report(f"eddy layout 2 terms nz={nz}", gpu=stats["neumann_terms"], oracle=int(ref.iterations.sum()))
+    compare(f"eddy layout 2 {profile} nz={nz}", fld, tl, ref)
+
+
 @pytest.mark.parametrize("profile", ["table", "analytic"])
 def test_eddy_full_size_start(ssp, gpu, profile):
     # Munk + eddy at its full size (200 Hz, Nz = 16384, [8/8], Neumann <= 12, dr = 20 m):
