@@ -140,7 +140,7 @@ def test_homogeneous_waveguide(ssp, gpu, bc):
 
 
 @pytest.mark.parametrize("bc", BCS)
-@pytest.mark.parametrize("nz,nsteps", [(3, 40), (127, 200), (1000, 100), (4096, 24), (9000, 12)])
+@pytest.mark.parametrize("nz,nsteps", [(3, 40), (127, 200), (1000, 100), (4096, 24), (6000, 12), (9000, 12)])
 def test_munk_vs_oracle(ssp, gpu, bc, nz, nsteps):
     s = with_bc(W.munk_deep(nsteps=nsteps, nz=nz), bc)
     psi0 = s.starter() if nz >= 16 else W.random_field(nz, 21)
