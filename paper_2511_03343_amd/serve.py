@@ -112,13 +112,24 @@ def plan_device_bytes(nz: int, pade_order: int, out_rows: int) -> int:
     return tables + state + staging
 
 
-class LibBackend:
-    """The HIP library: one plan per admitted request."""
+# Engine layouts for the serving mix, by FFT length (SSP_OPT_VARIANT).  The library's tuned
+# layouts are chosen on uniform batches of one length, where the two-workgroup layout 2 is
+# fastest at 4096 and 8192; in an over-subscribed mix of lengths the one-workgroup layouts
+# measured faster (the Poisson stream of the serving benchmark: 1.78e8 against 1.61e8 field
+# updates/s, p50 latency 23.4 against 28.8 s).  A plan's layout is fixed when it is created,
+# so a request's result does not depend on what it is batched with.
+SERVING_LAYOUTS = {4096: 0, 8192: 1}
 
-    def __init__(self, stream_ptr: Optional[int] = None):
+
+class LibBackend:
+    """The HIP library: one plan per admitted request (layouts: FFT length -> engine layout
+    for the plans it creates, the library's tuned layout for other lengths)."""
+
+    def __init__(self, stream_ptr: Optional[int] = None, layouts: Optional[dict] = None):
         from . import ssp
         self.ssp = ssp
         self.stream = stream_ptr
+        self.layouts = SERVING_LAYOUTS if layouts is None else layouts
 
     def create(self, r: ServeRequest):
         s = self.ssp
@@ -127,6 +138,9 @@ class LibBackend:
             if self.stream is not None:
                 s.ssp_plan_set_stream(pl, self.stream)
             s.ssp_plan_set_option(pl, s.SSP_OPT_OUT_EVERY, r.out_every)
+            fft_len = s.ssp_plan_engine(pl)[2]
+            if fft_len in self.layouts:
+                s.ssp_plan_set_option(pl, s.SSP_OPT_VARIANT, self.layouts[fft_len])
             if r.c_table is not None:
                 s.ssp_set_profile(pl, 0, -1, r.c_table)
             else:
