@@ -1,21 +1,24 @@
 """Benchmark: field updates (Nz x range steps) per second of the batched spectral
 split-step Pade march on one MI355X.
 
-Default workload (deep-ocean Munk waveguide): H = 5000 m, c0 = 1500 m/s, f = 50 Hz,
-Nz = 4096, [6/6] Pade, dr = 25 m, Neumann tol 1e-10 (series capped at 48 terms), TL written
-every 4 steps, a batch of B such solves with seeded source depths zs ~ U[50, 2000] m.  A
-bench "step" is one range step of the whole batch (every Pade factor and every Neumann term
-of every solve); inputs are resident in HBM before the timed region.
+Default workload (broadband): 256 frequencies uniformly in 50..300 Hz on the deep-ocean Munk
+profile (H = 5000 m, c0 = 1500 m/s), Nz = round(16 H f / 1500) = 2667 .. 16000 (uneven),
+[6/6] Pade, dr = 25 m, Neumann tol 1e-10 (cap 48), TL every 40 steps, one plan per
+frequency, all marched together from device memory (ssp_march_batch_async, the launches
+recorded in a HIP graph).  A bench "step" is one range step of the whole batch (every Pade
+factor and every Neumann term of every solve); inputs are resident in HBM before the timed
+region and the TL rows stay in device arrays.  Beside it: the deep Munk waveguide at
+Nz = 4096 (512 solves, key "munk4096") and the continuous-batching server on a Poisson
+request stream (key "serving", p50/p99 latency).
 
---workload eddy16384: Munk + Gaussian eddy at 200 Hz, Nz = 16384 (split transforms), [8/8],
-dr = 20 m, Neumann <= 12, potential rebuilt on the device every step, TL every 5 steps.
---workload broadband: 256 frequencies 50..300 Hz on the Munk profile with uneven
-Nz = 2667..16000, [6/6], dr = 25 m, one plan each, marched together by ssp_march_batch
-(TL every 40 steps copied to the host).
+Other workloads (--workload): munk4096 (512 solves at Nz = 4096, 50 Hz), eddy16384 (Munk +
+Gaussian eddy at 200 Hz, Nz = 16384, [8/8], Neumann <= 12, potential rebuilt on the device
+every step), serving, homogeneous, modal8001.
 
 Prints ONE JSON line (contract of the driver).  Beside the metric it reports the roofline of
-the fused march kernel, the plain one-kernel-per-stage form and the fused kernel on a single
-solve (same arithmetic, identical results), and the FP64 oracle on the host cores.
+the dominant kernel, the plain one-kernel-per-stage form and the fused kernel on a single
+solve (same arithmetic, identical results), the stand-alone transforms and the FP64 oracle
+on the host cores.
 """
 from __future__ import annotations
 
@@ -180,7 +183,7 @@ DEFAULTS = {  # batch, timed steps, warmup steps, steps per launch
     "munk4096": (512, 400, 20, 100),
     "homogeneous": (1024, 1000, 20, 200),
     "eddy16384": (256, 100, 10, 50),
-    "broadband": (256, 200, 40, 200),
+    "broadband": (256, 400, 40, 40),
     "serving": (1024, 0, 0, 50),
     "modal8001": (512, 500, 20, 100),
 }
@@ -192,7 +195,7 @@ DESCRIPTIONS = {
     "eddy16384": "Munk + Gaussian eddy, Nz=16384, [8/8] Pade, dr=20 m, 200 Hz, Neumann tol 1e-10 "
                  "(cap 12), potential on device every step, TL every 5 steps",
     "broadband": "256 frequencies 50..300 Hz, Munk, Nz=2667..16000 (16 pts/wavelength), [6/6] Pade, "
-                 "dr=25 m, Neumann tol 1e-10 (cap 48), TL every 40 steps to host",
+                 "dr=25 m, Neumann tol 1e-10 (cap 48), TL every 40 steps to device arrays",
     "modal8001": "range-independent Munk waveguide of the paper's first experiment: H=4 km, 100 Hz, "
                  "Nz=8001, [4/4] Pade, dr=100 m, Neumann series cut at M=2, normal-mode starters "
                  "(one device eigendecomposition for all source depths), TL every 10 steps",
@@ -228,7 +231,7 @@ def plain_vs_fused(ssp, s, nsteps):
     out = {}
     for engine, key in ((1, "plain_one_solve"), (0, "fused_one_solve")):
         p1 = make_plan(ssp, s)
-        ssp.ssp_plan_set_option(p1, ssp.SSP_OPT_ENGINE, engine)
+        ssp.ssp_plan_set_option(p1, ssp.SSP_OPT_PLAIN, engine)
         ssp.ssp_march(p1, s.nz, s.starter(), 2, want_field=False, want_tl=False)
         t1 = time.perf_counter()
         ssp.ssp_march(p1, s.nz, None, nsteps, want_field=False, want_tl=True)
@@ -273,10 +276,14 @@ def run_device_batch(args, ssp, torch, stream, dev):
     d_tl = torch.empty((B, nout_chunk, s.nz), dtype=torch.float32, device=dev)
     ssp.ssp_to_sine(pl, B, d_psi.data_ptr(), d_psi.data_ptr())
 
+    # steps per launch: every timed and warm-up launch marches k steps, so that the
+    # recorded graph is replayed in the timed region
+    kstep = max(1, min(args.chunk, args.steps or args.chunk))
+
     def run(nsteps, with_tl=True, events=None):
         done = 0
         while done < nsteps:
-            k = min(args.chunk, nsteps - done)
+            k = kstep
             if events is not None:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
@@ -295,17 +302,18 @@ def run_device_batch(args, ssp, torch, stream, dev):
     run(args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    updates = B * s.nz * args.steps
+    timed_steps = -(-args.steps // kstep) * kstep if args.steps > 0 else 0
+    updates = B * s.nz * timed_steps
 
     # roofline of the dominant kernel (the fused march): launches without outputs, timed
     # with events on the stream they run on; algorithmic work from the per-solve Neumann
     # term counts of each launch
     events, flops = [], []
     for _ in range(args.roof_launches):
-        run(args.chunk, with_tl=False, events=events)
+        run(kstep, with_tl=False, events=events)
         torch.cuda.synchronize()
         st = _stats(d_stats)
-        flops.append(sum(algorithmic_flops(s.nz, s.pade_order, t, args.chunk, 0)
+        flops.append(sum(algorithmic_flops(s.nz, s.pade_order, t, kstep, 0)
                          for t in st["terms_list"]))
     launch_s = [a.elapsed_time(b) / 1e3 for a, b, _ in events]
     achieved = sum(flops) / sum(launch_s)
@@ -313,16 +321,16 @@ def run_device_batch(args, ssp, torch, stream, dev):
     ssp.ssp_plan_destroy(pl)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
-            "traffic": measured_traffic(args.workload, s.nz, B, args.chunk, args.bc)
+            "traffic": measured_traffic(args.workload, s.nz, B, kstep, args.bc)
             if args.absorber is None else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": (f"k_march_direct<{P}, {layout}, {direct}>" if direct
                        else f"k_march<{P}, {layout}>") + f" ({threads} threads per workgroup)",
             "avg_launch_ms": 1e3 * sum(launch_s) / len(launch_s),
-            "steps_per_launch": args.chunk,
-            "neumann_terms_per_solve_step": stats["terms"] / B / args.chunk}
-    config = {"batch_solves": B, "nz": s.nz, "range_steps_timed": args.steps,
-              "steps_per_launch": args.chunk, "hip_graph": bool(args.graph), "boundary": s.bc}
+            "steps_per_launch": kstep,
+            "neumann_terms_per_solve_step": stats["terms"] / B / kstep}
+    config = {"batch_solves": B, "nz": s.nz, "range_steps_timed": timed_steps,
+              "steps_per_launch": kstep, "hip_graph": bool(args.graph), "boundary": s.bc}
     if args.absorber is not None:
         config["absorber"] = {"thickness_m": args.absorber[0], "eta_max": args.absorber[1]}
     if starter_s is not None:
@@ -336,48 +344,90 @@ def run_device_batch(args, ssp, torch, stream, dev):
 
 
 def run_broadband(args, ssp, torch, stream, dev):
-    """256 plans of uneven Nz marched together through ssp_march_batch (host outputs)."""
+    """The 256 plans of the broadband set (uneven Nz) marched together from device memory:
+    ssp_march_batch_async, TL rows to device arrays, the launches recorded once in a HIP
+    graph and replayed (one graph launch per call of `chunk` steps)."""
     solves = W.broadband()
     plans = [make_plan(ssp, s) for s in solves]
     nzs = [s.nz for s in solves]
+    n = len(plans)
     for pl in plans:
         ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, -2)   # layouts tuned on a mixed batch
+    ssp.ssp_plan_set_option(plans[0], ssp.SSP_OPT_GRAPH, 1 if args.graph else 0)
     for pl, s in zip(plans, solves):
         ssp.ssp_set_field(pl, s.starter(), s.nz)
+    # steps per call: every timed call (and every warm-up call) marches k steps, so that the
+    # recorded graph is replayed in the timed region
+    k = max(1, min(args.chunk, args.steps or args.chunk))
+    d_tl = [torch.empty((k // s.out_every + 1, s.nz), dtype=torch.float32, device=dev) for s in solves]
+    tl_ptrs = [t.data_ptr() for t in d_tl]
 
-    def run(nsteps):
-        done = 0
-        terms = [0] * len(plans)
-        statuses = set()
-        while done < nsteps:
-            k = min(args.chunk, nsteps - done)
-            st, _, _, stats = ssp.ssp_march_batch(plans, nzs, k, want_field=False, want_tl=True)
-            for i, x in enumerate(stats):
-                terms[i] += x["neumann_terms"]
-            statuses |= {x["status"] for x in stats}
-            done += k
-        return terms, statuses
+    def call(sub, steps, ptrs):
+        ssp.ssp_march_batch_async(sub, [steps] * len(sub), ptrs)
 
-    run(args.warmup)
+    warm_calls = -(-args.warmup // k) if args.warmup > 0 else 0
+    for _ in range(warm_calls):
+        call(plans, k, tl_ptrs)
+    st, stats = ssp.ssp_batch_stats(plans)
     torch.cuda.synchronize()
+    calls = -(-args.steps // k) if args.steps > 0 else 0
     t0 = time.perf_counter()
-    terms, statuses = run(args.steps)
+    for _ in range(calls):
+        call(plans, k, tl_ptrs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    updates = sum(nzs) * args.steps
-    # whole-call roofline: algorithmic work of every solve / wall time (outputs included)
-    flops = sum(algorithmic_flops(s.nz, s.pade_order, t, args.steps, args.steps // s.out_every)
-                for s, t in zip(solves, terms))
-    avg_terms = sum(terms) / len(plans) / args.steps
-    achieved = flops / wall
+    timed_steps = calls * k
+    st, stats = ssp.ssp_batch_stats(plans)
+    updates = sum(nzs) * timed_steps
+    statuses = {x["status"] for x in stats}
+    layouts = {}
+    for pl in plans:
+        v, t, P = ssp.ssp_plan_engine(pl)
+        layouts[P] = v
+
+    # roofline of the dominant kernel: the split-transform group (FFT length 32768, the
+    # largest solves, whose launch sets the call's time) marched alone for roof_launches
+    # calls of k steps without outputs, timed with events on the stream it runs on;
+    # algorithmic work from the per-solve Neumann term counts of each call
+    P_of = [ssp.ssp_plan_engine(pl)[2] for pl in plans]
+    Pdom = max(P_of)
+    sub = [pl for pl, P in zip(plans, P_of) if P == Pdom]
+    sub_s = [s for s, P in zip(solves, P_of) if P == Pdom]
+    events, flops = [], []
+    for _ in range(args.roof_launches):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        call(sub, k, None)
+        e1.record(stream)
+        _, sst = ssp.ssp_batch_stats(sub)
+        events.append((e0, e1))
+        flops.append(sum(algorithmic_flops(s.nz, s.pade_order, x["neumann_terms"], k, 0)
+                         for s, x in zip(sub_s, sst)))
+        statuses |= {x["status"] for x in sst}
+    torch.cuda.synchronize()
+    launch_s = [a.elapsed_time(b) / 1e3 for a, b in events]
+    achieved = sum(flops) / sum(launch_s) if launch_s else 0.0
+    terms_step = sum(x["neumann_terms"] for x in stats) / n / k
+    v_dom, t_dom, _ = ssp.ssp_plan_engine(sub[0])
     for pl in plans:
         ssp.ssp_plan_destroy(pl)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
-            "kernel": "k_march<8192|16384|32768> (grouped by FFT length) + outputs, whole call",
-            "neumann_terms_per_solve_step": avg_terms}
-    config = {"solves": len(plans), "nz_min": min(nzs), "nz_max": max(nzs), "sum_nz": sum(nzs),
-              "range_steps_timed": args.steps, "steps_per_call": args.chunk}
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+            "traffic": measured_traffic("broadband", Pdom, len(sub), k),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": f"k_march<{Pdom}, {v_dom}> ({t_dom} threads per workgroup): the {len(sub)} solves "
+                      f"with FFT length {Pdom}, whose launch sets the call's time",
+            "avg_launch_ms": 1e3 * sum(launch_s) / len(launch_s) if launch_s else None,
+            "steps_per_launch": k,
+            "neumann_terms_per_solve_step": sum(flops) and (
+                sum(x["neumann_terms"] for x in sst) / len(sub) / k)}
+    config = {"solves": n, "nz_min": min(nzs), "nz_max": max(nzs), "sum_nz": sum(nzs),
+              "range_steps_timed": timed_steps, "warmup_steps_run": warm_calls * k, "steps_per_call": k,
+              "hip_graph": bool(args.graph), "layouts_by_fft_length": layouts,
+              "neumann_terms_per_solve_step": terms_step,
+              "outputs": "TL every 40 steps to device arrays (no host copies in the timed region)"}
     plain = None
     if args.plain_steps > 0:
         plain = plain_vs_fused(ssp, solves[-1], args.plain_steps)
@@ -491,7 +541,7 @@ def run_serving(args, ssp, torch, stream, dev):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(DEFAULTS), default="munk4096")
+    ap.add_argument("--workload", choices=sorted(DEFAULTS), default="broadband")
     ap.add_argument("--steps", type=int, default=None, help="timed range steps")
     ap.add_argument("--warmup", type=int, default=None, help="untimed range steps")
     ap.add_argument("--batch", type=int, default=None, help="solves marched together")
@@ -502,7 +552,9 @@ def main():
                     help="range steps of the plain-form comparison (0: skip)")
     ap.add_argument("--graph", type=int, default=1, help="replay recorded launches (HIP graph)")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
-    ap.add_argument("--duration", type=float, default=2.0, help="serving: arrival window (s)")
+    ap.add_argument("--duration", type=float, default=1.0, help="serving: arrival window (s)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="broadband: skip the deep Munk line and the serving stream")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB of a plain device copy run first (counter calibration)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -556,7 +608,35 @@ def main():
     updates, wall, roof, config, statuses, plain, nz = runner(args, ssp, torch, stream, dev)
     log(f"{args.workload}: {updates / wall:.4g} field updates/s")
     value = updates / wall
-    timed_steps = args.steps or config.get("ticks") or 1   # serving: a step is one tick
+    # a step is one range step of the whole batch (serving: one tick)
+    timed_steps = config.get("range_steps_timed") or config.get("ticks") or 1
+
+    extras = {}
+    if args.workload == "broadband" and not args.no_extras:
+        # the deep Munk waveguide (Nz = 4096, 512 solves) as a device batch, and the
+        # continuous-batching server on the Poisson stream
+        ea = argparse.Namespace(**vars(args))
+        ea.workload, ea.nz, ea.bc, ea.absorber = "munk4096", None, "dirichlet", None
+        ea.batch, ea.steps, ea.warmup, ea.chunk, ea.plain_steps = 512, 100, 20, 100, 0
+        ea.roof_launches = 1
+        u2, w2, r2, c2, s2, _, _ = run_device_batch(ea, ssp, torch, stream, dev)
+        extras["munk4096"] = {"workload": _describe("munk4096", None), "value": u2 / w2,
+                              "unit": "field updates/s", "ms_per_step": 1e3 * w2 / c2["range_steps_timed"],
+                              "status": s2, "roofline": r2, **c2}
+        log(f"munk4096: {u2 / w2:.4g} field updates/s")
+        sa = argparse.Namespace(**vars(args))
+        sa.workload, sa.batch, sa.chunk = "serving", 1024, 50
+        u3, w3, r3, c3, s3, _, _ = run_serving(sa, ssp, torch, stream, dev)
+        lat = c3["latency"]
+        extras["serving"] = {"workload": _describe("serving", None), "value": u3 / w3,
+                             "unit": "field updates/s", "p50_s": lat.get("p50_s"), "p99_s": lat.get("p99_s"),
+                             "requests": c3["requests"], "completed": lat.get("count"),
+                             "arrival_rate_per_s": sa.rate, "arrival_window_s": sa.duration,
+                             "clock": "virtual: each tick advances it by the tick's measured duration "
+                                      "(admission, plan creation and the batched march), and it jumps to "
+                                      "the next arrival when nothing is active; latency = finish - arrival",
+                             "status": s3, **{k: v for k, v in c3.items() if k != "latency"}}
+        log(f"serving: {u3 / w3:.4g} field updates/s, p50 {lat.get('p50_s')}, p99 {lat.get('p99_s')}")
 
     transforms = None if args.no_transforms else transform_rooflines(ssp, torch, stream, dev)
     if transforms is not None:
@@ -588,6 +668,7 @@ def main():
         "plain_form": plain,
         "transforms": transforms,
         "cpu_baseline": cpu,
+        **extras,
     }
     print(json.dumps(out), flush=True)
 

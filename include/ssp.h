@@ -48,7 +48,8 @@ typedef enum {
     SSP_E_DEVICE = -3,       /* HIP runtime error (message in ssp_last_error) */
     SSP_E_DIVERGED = -4,     /* a Neumann series grew or a value became non-finite; the
                                 field is left at the last good step (ssp_stats.steps_done) */
-    SSP_E_UNSTABLE = -5,     /* plan rejected: max_l |e^{i sigma} R(x_l)| > 1 + 1e-6 */
+    SSP_E_UNSTABLE = -5,     /* plan rejected: max_l |e^{i sigma} R(x_l)| > 1 + eps, eps the
+                                plan's gain limit (SSP_OPT_GAIN_LIMIT, default 1e-6) */
     SSP_E_STATE = -6,        /* call out of order (e.g. march before a field was set) */
     SSP_E_UNIMPL = -7        /* size or option outside what this build supports */
 } ssp_status;
@@ -63,20 +64,54 @@ enum {
     SSP_OPT_OUT_EVERY = 2, /* write an output every k-th step (default 1) */
     SSP_OPT_STREAM = 3,    /* value = (double)(uintptr_t)hipStream_t; 0 = null stream.
                               Use ssp_plan_set_stream to pass a pointer exactly. */
-    SSP_OPT_ENGINE = 4,    /* 0 = fused persistent kernel (default); 1 = plain form: one
-                              kernel per transform / pointwise step, host-driven loop */
-    SSP_OPT_GRAPH = 5,     /* 1: ssp_march_device records its launches (march + outputs) in
-                              a HIP graph on the first call and replays the graph on later
-                              calls with the same arguments; needs a non-null stream.
-                              0 (default): plain launches */
-    SSP_OPT_VARIANT = 6    /* engine layout of the fused march kernel: -1 (default) = the
+    SSP_OPT_ENGINE = 4,    /* transform engine of the march (SSP_ENGINE_*):
+                              SSP_ENGINE_AUTO (default): the engine the autotuner measured
+                              faster for the plan's (Nz, pade_order) class; SSP_ENGINE_FFT:
+                              FFT-based transforms in the fused persistent kernel;
+                              SSP_ENGINE_DENSE: every DST-I of the Neumann series is the
+                              dense product S X on the matrix cores (Sec. 3.1: S is the
+                              orthonormal DST-I matrix, symmetric and its own inverse) over
+                              the whole batch of solves of one Nz; Dirichlet plans with
+                              Nz <= ssp_max_dense_nz() only (SSP_E_UNIMPL otherwise).  The
+                              engines differ in rounding only. */
+    SSP_OPT_GRAPH = 5,     /* 1: ssp_march_device and ssp_march_batch_async record their
+                              launches (march + outputs) in a HIP graph on the first call and
+                              replay the graph on later calls with the same arguments; needs
+                              a non-null stream (FFT engine).  0 (default): plain launches */
+    SSP_OPT_VARIANT = 6,   /* engine layout of the fused march kernel: -1 (default) = the
                               layout the autotuner chose for this FFT length and transform
-                              kind (chirp-z, direct Fourier, direct sine); 0, 1 or 2 = that
+                              kind (chirp-z, direct Fourier, direct sine) on batches of one
+                              length; -2 = the layout it chose for batches that mix lengths
+                              (broadband and serving); 0, 1 or 2 = that
                               layout (falls back to 0 where the length has no such layout;
                               split lengths, P > 16384, have layout 0 only).
                               Layouts differ in rounding only; a solve's results do not
                               depend on what it is batched with. */
+    SSP_OPT_PLAIN = 7,     /* 0 (default): fused persistent kernel; 1: plain form, one kernel
+                              per transform / pointwise stage and a host-driven loop (FFT
+                              engine, chirp-z plans, ssp_march of one plan) */
+    SSP_OPT_FORM = 8,      /* SSP_FORM_PRODUCT (default): the Pade factors applied one after
+                              the other, u <- g_j u + (1 - g_j)(1 + b_j X)^{-1} u, the same
+                              approximant as the sum form of Sec. 2.  SSP_FORM_SUM (the
+                              paper's form, u <- d0 u + sum_j d_j (1 + b_j X)^{-1} u) is not
+                              built: sum_j |d_j| reaches 1e2 .. 4e3 at the benchmark
+                              settings, and in FP32 that cancellation costs up to 12 bits
+                              per step; setting it returns SSP_E_UNIMPL. */
+    SSP_OPT_GAIN_LIMIT = 9, /* eps >= 0 of the stability check max_l |e^{i sigma} R(x_l)|
+                              <= 1 + eps (default 1e-6: the rotated [4/4] approximant of the
+                              homogeneous waveguide at sigma = 2.09 exceeds 1 by 4.5e-8,
+                              i.e. 4.5e-5 over 1000 steps).  Setting it re-checks the
+                              current coefficients; if they fail, SSP_E_UNSTABLE is returned
+                              and the limit is left unchanged. */
+    SSP_OPT_CONTRACTION_CHECK = 10 /* 1: before marching, estimate the spectral radius of
+                              every factor's Neumann operator b_j L_j^{-1} V (see
+                              ssp_plan_contraction; once per profile) and return
+                              SSP_E_DIVERGED without marching if one is >= 1.  0 (default):
+                              divergence is detected while marching. */
 };
+
+enum { SSP_ENGINE_FFT = 0, SSP_ENGINE_DENSE = 1, SSP_ENGINE_AUTO = 2 };
+enum { SSP_FORM_PRODUCT = 0, SSP_FORM_SUM = 1 };
 
 /* Analytic range-dependent environment evaluated on the device every step at the step's
  * mid-range r = (n - 1/2) dr:  c(r, z) = c_munk(z) + dc(r, z), with the Munk profile of
@@ -117,7 +152,7 @@ typedef struct {
  *                     l <= Nz/2 and l - Nz above.  Nz a power of two in [128, 16384]: the
  *                     transforms are direct FFTs of length Nz (else chirp-z ones of length
  *                     >= 2 Nz - 1); such plans run the fused kernel only
- *                     (SSP_OPT_ENGINE = 1 gives SSP_E_UNIMPL)
+ *                     (SSP_OPT_PLAIN = 1 gives SSP_E_UNIMPL)
  * Every basis function is an eigenfunction of d_z^2 (eigenvalue -kappa_l^2, kappa_l = l pi/H
  * or 2 pi l'/H), which makes the isovelocity operator of every Pade term diagonal.  The
  * coefficient-space field kept on the device ("sine basis" below) is that of the plan's
@@ -163,6 +198,21 @@ int ssp_max_nz(void);
  * threads per workgroup and the FFT length P: chirp-z length, Nz for periodic direct plans,
  * 2 (Nz + 1) for Dirichlet direct plans (any pointer may be NULL). */
 ssp_status ssp_plan_engine(const ssp_plan *plan, int *variant, int *threads, int *fft_length);
+
+/* Convergence of the Neumann series (Sec. 3: the series for (1 + b_j X)^{-1} converges when
+ * K_j = b_j L_j^{-1} V is a contraction, L_j the isovelocity operator), per Pade factor j in
+ * application order, for the plan's current profile (its first, middle and last tabulated
+ * rows, or the analytic Munk profile alone and with the eddy at its centre range) and
+ * absorber, evaluated on the host in FP64:
+ *   bound[p]     max_l |b_j/(1 + b_j x_l)| max |v|: a norm bound (>= the spectral radius);
+ *                below 1 the series converges geometrically for every input
+ *   estimate[p]  the spectral radius of K_j by power iteration (iterations products with
+ *                two FP64 DST-I each, the growth rate over the second half; largest over
+ *                the sampled rows): >= 1 means the series diverges for generic inputs.
+ *                Dirichlet plans only (NaN otherwise, or for iterations = 0).
+ * Either pointer may be NULL.  Cost: 2 x iterations x p FFT pairs of length >= 2 Nz - 1 on
+ * the host (about a second for Nz = 4096, 40 iterations, p = 6). */
+ssp_status ssp_plan_contraction(ssp_plan *plan, int iterations, double *bound, double *estimate);
 
 /* Host-only Pade coefficients (Sec. 2; Alg. 1 first step) for sigma = k0 dr, order p and
  * rotation alpha, in the library's factor order: b[2p], g[2p] (product-form weights
@@ -224,7 +274,9 @@ int ssp_count_outputs(const ssp_plan *plan, int nsteps);
  * The plans must differ only in their starter, profile and (for different FFT sizes)
  * grid; each plan keeps its own field, counter and statistics.  Outputs are written per
  * plan as in ssp_march (arrays of n pointers, entries may be NULL); stats [n] or NULL.
- * Returns the worst status over the plans. */
+ * Returns the worst status over the plans (SSP_E_DIVERGED first): the outputs and statistics
+ * of every plan are written in any case, and a plan that diverged keeps the field of its
+ * last good step. */
 ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *const *field_out,
                            float *const *tl_out, ssp_stats *stats);
 
@@ -234,6 +286,22 @@ ssp_status ssp_march_batch(ssp_plan *const *plans, int n, int nsteps, double *co
 ssp_status ssp_march_batch_steps(ssp_plan *const *plans, int n, const int *nsteps,
                                  double *const *field_out, float *const *tl_out, ssp_stats *stats);
 
+/* ssp_march_batch_steps without host copies, asynchronous on the first plan's stream: the
+ * uneven batch of Sec. 4's broadband and serving workloads run from device memory.  The
+ * plans' fields stay resident; d_tl_out[i] (device float, may be NULL, or the array NULL)
+ * receives plan i's TL rows of the output steps reached, in order, with room for
+ * nsteps[i]/out_every + 1 rows of Nz.  Groups of different FFT length run concurrently
+ * (side streams forked from and joined into the stream).  With SSP_OPT_GRAPH on the first
+ * plan and a non-null stream, the launches are recorded in a HIP graph on the first call and
+ * replayed while plans, step counts, output arrays and stream are unchanged (FFT-engine
+ * batches).  Statistics (and each plan's step counter on the host) are read with
+ * ssp_batch_stats; every host call on a plan first waits for its pending batch.  Dense-engine
+ * groups wait for their stream between terms (see SSP_ENGINE_DENSE). */
+ssp_status ssp_march_batch_async(ssp_plan *const *plans, int n, const int *nsteps, float *const *d_tl_out);
+/* Wait for the plans' pending batches and read their statistics (stats [n] or NULL); returns
+ * the worst per-plan status. */
+ssp_status ssp_batch_stats(ssp_plan *const *plans, int n, ssp_stats *stats);
+
 /* Device-resident batch for serving and benchmarking (no host copies in the hot path):
  * B solves of one plan's grid and coefficients, each with its own state.  d_psi is a device
  * array [B][Nz] complex64 holding each solve's field in the library's sine-basis
@@ -242,7 +310,10 @@ ssp_status ssp_march_batch_steps(ssp_plan *const *plans, int n, const int *nstep
  * [B][nsteps/out_every + 1][Nz] that receives, per solve, the TL rows of the output steps
  * reached in this call, in order; d_stats a device array of B ssp_stats (may be NULL).
  * The call is asynchronous on the plan's stream.  Scratch (per-solve state between Pade
- * factors, output snapshots) is owned by the plan and reused by later calls. */
+ * factors, output snapshots) is owned by the plan and reused by later calls.  The plan's own
+ * field and step counter are not touched.  A solve whose step has no row in a tabulated
+ * profile (ssp_set_profile with nsteps > 0) stops there with status SSP_E_INVAL in its
+ * statistics.  Dense-engine plans run without graph recording. */
 ssp_status ssp_march_device(ssp_plan *plan, int B, void *d_psi, void *d_step, int nsteps,
                             void *d_tl, void *d_stats);
 /* physical complex64 [B][Nz] (device) -> sine-basis representation (device), in place ok */

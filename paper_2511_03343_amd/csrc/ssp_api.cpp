@@ -8,7 +8,10 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "ssp_device.h"
@@ -59,7 +62,11 @@ static_assert(SSP_BC_DIRICHLET == ssp::kBcDirichlet && SSP_BC_NEUMANN == ssp::kB
 struct ssp_plan {
     int N = 0, P = 0, p = 0, nmax = 0;
     double H = 0, f = 0, c0 = 0, dr = 0, tol = 0, k0 = 0, sigma = 0, alpha = 0;
-    int out_every = 1, engine = 0;
+    int out_every = 1;
+    int engine = SSP_ENGINE_AUTO;       // SSP_OPT_ENGINE
+    int plain = 0;                      // SSP_OPT_PLAIN: one kernel per stage
+    double gain_limit = 1e-6;           // SSP_OPT_GAIN_LIMIT
+    bool contraction_check = false;     // SSP_OPT_CONTRACTION_CHECK
     int bc = ssp::kBcDirichlet;         // boundary condition (Sec. 3.1)
     int variant_opt = -1;               // SSP_OPT_VARIANT
     hipStream_t stream = nullptr;
@@ -113,10 +120,32 @@ struct ssp_plan {
     float2 *d_out_fld = nullptr;
     float *d_out_tl = nullptr;
     size_t out_cap = 0;
-    // dense DST (matrix cores): S parts and split-operand scratch
-    _Float16 *d_dense_sh = nullptr, *d_dense_sl = nullptr;
-    int dense_kpad = 0;
+    // dense DST (matrix cores): split-operand scratch of the stand-alone transform (S itself
+    // is shared by the plans of one grid size, see dense_tables)
     _Float16 *d_dense_xh = nullptr, *d_dense_xl = nullptr;
+    // dense engine: per-plan tables and, on the first plan of a batch, the launch scratch
+    float4 *d_tmul = nullptr, *d_mmod = nullptr;
+    void *d_dense_work = nullptr;
+    size_t dense_work_cap = 0;
+    int *h_active = nullptr;            // pinned: series still running in a dense launch
+    // ssp_march_batch_async: the host step counter is stale until the statistics are read
+    // after the stream the batch ran on
+    bool async_pending = false;
+    hipStream_t pending_stream = nullptr;
+    // recorded launches of ssp_march_batch_async on its first plan (SSP_OPT_GRAPH)
+    hipGraph_t bgraph = nullptr;
+    hipGraphExec_t bgraph_exec = nullptr;
+    std::vector<const ssp_plan *> bkey_plans;
+    std::vector<int> bkey_steps;
+    std::vector<void *> bkey_tl;
+    hipStream_t bkey_stream = nullptr;
+    // contraction estimate (ssp_plan_contraction): potential rows sampled from the current
+    // profile in FP64 (v + i eta), and the cached estimate for SSP_OPT_CONTRACTION_CHECK
+    std::vector<std::complex<double>> vs;
+    int vs_rows = 0;
+    std::vector<double> h_eta;          // absorber (host copy), empty without one
+    std::vector<double> rho_est;
+    bool rho_valid = false;
     int *d_dense_expo = nullptr;
     int dense_cols_cap = 0;
     // side streams of a batch whose launch groups run concurrently (default priority)
@@ -134,6 +163,58 @@ void drop_graph(ssp_plan *pl) {
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
     pl->graph_exec = nullptr;
     pl->graph = nullptr;
+    if (pl->bgraph_exec) (void)hipGraphExecDestroy(pl->bgraph_exec);
+    if (pl->bgraph) (void)hipGraphDestroy(pl->bgraph);
+    pl->bgraph_exec = nullptr;
+    pl->bgraph = nullptr;
+    pl->bkey_plans.clear();
+}
+
+bool dense_capable(const ssp_plan *pl) { return pl->bc == ssp::kBcDirichlet && pl->N <= ssp::kMaxDenseNz; }
+
+ssp_status sync_pending(ssp_plan *pl);
+std::vector<std::complex<double>> estimate_rows(const ssp_plan *pl);
+
+// Engine of the plan's march: the option, or for SSP_ENGINE_AUTO the autotuner's choice for
+// the plan's (Nz, p) class (dense only where the plan can run it).
+int effective_engine(const ssp_plan *pl) {
+    if (!dense_capable(pl) || pl->engine == SSP_ENGINE_FFT) return SSP_ENGINE_FFT;
+    if (pl->engine == SSP_ENGINE_DENSE) return SSP_ENGINE_DENSE;
+    return ssp::tuned_engine(pl->N, pl->p) == 1 ? SSP_ENGINE_DENSE : SSP_ENGINE_FFT;
+}
+
+// S of the dense transform for grid size n on the current device: built once per (device,
+// n) and shared by every plan of that size for the life of the process.
+ssp_status dense_tables(int n, ssp::DenseTables &out) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, ssp::DenseTables> cache;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({dev, n});
+    if (it == cache.end()) {
+        std::vector<uint16_t> sh, sl;
+        int kpad = 0;
+        ssp::build_dense_tables(n, kpad, sh, sl);
+        _Float16 *dsh = nullptr, *dsl = nullptr;
+        HIP_TRY(dev_alloc(&dsh, sh.size()));
+        hipError_t e = dev_alloc(&dsl, sl.size());
+        if (e == hipSuccess) e = hipMemcpy(dsh, sh.data(), sh.size() * 2, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(dsl, sl.data(), sl.size() * 2, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            dev_free(dsh);
+            dev_free(dsl);
+            return fail(e == hipErrorOutOfMemory ? SSP_E_NOMEM : SSP_E_DEVICE, hipGetErrorString(e));
+        }
+        ssp::DenseTables t;
+        t.sh = dsh;
+        t.sl = dsl;
+        t.n = n;
+        t.kpad = kpad;
+        it = cache.emplace(std::make_pair(dev, n), t).first;
+    }
+    out = it->second;
+    return SSP_OK;
 }
 
 constexpr int kSideStreams = 3;
@@ -176,6 +257,8 @@ void free_tables(ssp_plan *pl) {
     dev_free(pl->d_alpha);
     dev_free(pl->d_beta);
     dev_free(pl->d_twist);
+    dev_free(pl->d_tmul);
+    dev_free(pl->d_mmod);
 }
 
 template <typename D, typename S>
@@ -190,9 +273,9 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     if (!ssp::pade_coefficients(pl->sigma, pl->p, pl->alpha, ps, err)) return fail(SSP_E_INVAL, err);
     ssp::DeviceTables tab;
     ssp::build_tables(pl->N, pl->H, pl->k0, ps, pl->bc, tab);
-    if (!(tab.max_gain <= 1.0 + 1e-6))
-        return fail(SSP_E_UNSTABLE, "max |e^{i sigma} R(x_l)| = " + std::to_string(tab.max_gain) +
-                                        " exceeds 1 + 1e-6");
+    if (!(tab.max_gain <= 1.0 + pl->gain_limit))
+        return fail(SSP_E_UNSTABLE, "max |e^{i sigma} R(x_l)| - 1 = " + std::to_string(tab.max_gain - 1.0) +
+                                        " exceeds the gain limit " + std::to_string(pl->gain_limit));
     if (!ssp::fft_length_supported(tab.P)) return fail(SSP_E_UNIMPL, "unsupported FFT length");
     free_tables(pl);
     const int N = pl->N, P = tab.P, p = ps.p;
@@ -227,7 +310,12 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     HIP_TRY(upload(pl->d_alpha, tab.alpha));
     HIP_TRY(upload(pl->d_beta, tab.beta));
     if (!tab.twist.empty()) HIP_TRY(upload(pl->d_twist, tab.twist));
+    HIP_TRY(dev_alloc(&pl->d_tmul, tab.tmul.size() / 4));
+    HIP_TRY(dev_alloc(&pl->d_mmod, tab.mmod.size() / 4));
+    if (!tab.tmul.empty()) HIP_TRY(upload(pl->d_tmul, tab.tmul));
+    if (!tab.mmod.empty()) HIP_TRY(upload(pl->d_mmod, tab.mmod));
     pl->ps = ps;
+    pl->rho_valid = false;
     pl->P = P;
     pl->tab = std::move(tab);
     return SSP_OK;
@@ -243,7 +331,8 @@ int effective_variant(const ssp_plan *pl) {
         int lg = 0;
         while ((1 << lg) < pl->P) ++lg;
         const int idx = lg - 7;
-        v = (idx >= 0 && idx < 9) ? ssp::kTunedVariant[idx] : 0;
+        const int *table = v == -2 ? ssp::kTunedMixed : ssp::kTunedVariant;
+        v = (idx >= 0 && idx < 9) ? table[idx] : 0;
     }
     return ssp::engine_variant_exists(pl->P, v) ? v : 0;
 }
@@ -286,6 +375,9 @@ ssp::SolveDesc base_desc(const ssp_plan *pl) {
     d.variant = effective_variant(pl);
     d.direct = pl->tab.direct;
     d.mirror = pl->d_mirror;
+    d.tmul = pl->d_tmul;
+    d.mmod = pl->d_mmod;
+    d.engine = effective_engine(pl);
     return d;
 }
 
@@ -450,6 +542,8 @@ ssp_status ssp_plan_create_bc(int Nz, double H, double f, double c0, double dr, 
     }
     if (st == SSP_OK) {
         // default environment: c = c0 everywhere, v = 0
+        pl->vs.assign(Nz, 0.0);
+        pl->vs_rows = 1;
         pl->v_rows = 1;
         pl->prof_mode = ssp::PROF_TABLE_FIXED;
         hipError_t e = hipMemset(pl->d_v, 0, sizeof(float) * Nz);
@@ -484,8 +578,8 @@ void ssp_plan_destroy(ssp_plan *pl) {
     dev_free(pl->d_out_fld);
     dev_free(pl->d_out_tl);
     dev_free(pl->d_plain);
-    dev_free(pl->d_dense_sh);
-    dev_free(pl->d_dense_sl);
+    if (pl->d_dense_work) (void)hipFree(pl->d_dense_work);
+    if (pl->h_active) (void)hipHostFree(pl->h_active);
     dev_free(pl->d_dense_xh);
     dev_free(pl->d_dense_xl);
     dev_free(pl->d_dense_expo);
@@ -502,6 +596,7 @@ ssp_status ssp_plan_set_stream(ssp_plan *pl, void *hip_stream) {
 
 ssp_status ssp_plan_set_option(ssp_plan *pl, int key, double value) {
     if (!pl) return fail(SSP_E_INVAL, "plan is NULL");
+    { const ssp_status sp_ = sync_pending(pl); if (sp_ != SSP_OK) return sp_; }
     drop_graph(pl);
     switch (key) {
         case SSP_OPT_ROTATION: {
@@ -532,12 +627,38 @@ ssp_status ssp_plan_set_option(ssp_plan *pl, int key, double value) {
             drop_graph(pl);
             return SSP_OK;
         case SSP_OPT_ENGINE:
-            if (value != 0 && value != 1) return fail(SSP_E_INVAL, "engine must be 0 or 1");
+            if (value != SSP_ENGINE_FFT && value != SSP_ENGINE_DENSE && value != SSP_ENGINE_AUTO)
+                return fail(SSP_E_INVAL, "engine must be SSP_ENGINE_FFT, SSP_ENGINE_DENSE or SSP_ENGINE_AUTO");
+            if (value == SSP_ENGINE_DENSE && !dense_capable(pl))
+                return fail(SSP_E_UNIMPL, "the dense engine runs Dirichlet plans with Nz <= ssp_max_dense_nz()");
             pl->engine = static_cast<int>(value);
             return SSP_OK;
+        case SSP_OPT_PLAIN:
+            if (value != 0 && value != 1) return fail(SSP_E_INVAL, "plain must be 0 or 1");
+            pl->plain = static_cast<int>(value);
+            return SSP_OK;
+        case SSP_OPT_FORM:
+            if (value == SSP_FORM_PRODUCT) return SSP_OK;
+            if (value == SSP_FORM_SUM)
+                return fail(SSP_E_UNIMPL, "the sum form is not built: its FP32 cancellation (sum |d_j| up to "
+                                          "4e3) costs up to 12 bits per step; the product form evaluates the "
+                                          "same approximant");
+            return fail(SSP_E_INVAL, "form must be SSP_FORM_PRODUCT or SSP_FORM_SUM");
+        case SSP_OPT_GAIN_LIMIT: {
+            if (!(value >= 0) || !std::isfinite(value)) return fail(SSP_E_INVAL, "gain limit must be finite and >= 0");
+            if (!(pl->tab.max_gain <= 1.0 + value))
+                return fail(SSP_E_UNSTABLE, "max |e^{i sigma} R(x_l)| - 1 = " + std::to_string(pl->tab.max_gain - 1.0) +
+                                                " exceeds the requested gain limit");
+            pl->gain_limit = value;
+            return SSP_OK;
+        }
+        case SSP_OPT_CONTRACTION_CHECK:
+            if (value != 0 && value != 1) return fail(SSP_E_INVAL, "contraction check must be 0 or 1");
+            pl->contraction_check = value == 1;
+            return SSP_OK;
         case SSP_OPT_VARIANT:
-            if (value != -1 && value != 0 && value != 1 && value != 2)
-                return fail(SSP_E_INVAL, "variant must be -1, 0, 1 or 2");
+            if (value != -2 && value != -1 && value != 0 && value != 1 && value != 2)
+                return fail(SSP_E_INVAL, "variant must be -2, -1, 0, 1 or 2");
             pl->variant_opt = static_cast<int>(value);
             return SSP_OK;
         default:
@@ -576,6 +697,18 @@ ssp_status ssp_plan_info(const ssp_plan *pl, double *sigma, double *k0, double *
     return SSP_OK;
 }
 
+ssp_status ssp_plan_contraction(ssp_plan *pl, int iterations, double *bound, double *estimate) {
+    if (!pl || iterations < 0 || iterations > 100000) return fail(SSP_E_INVAL, "plan is NULL or bad iteration count");
+    std::vector<double> bd, est;
+    ssp::neumann_contraction(pl->N, pl->H, pl->k0, pl->ps, pl->bc, estimate_rows(pl), pl->vs_rows, iterations, bd,
+                             est);
+    for (int j = 0; j < pl->p; ++j) {
+        if (bound) bound[j] = bd[j];
+        if (estimate) estimate[j] = est[j];
+    }
+    return SSP_OK;
+}
+
 ssp_status ssp_modal_starter(ssp_plan *pl, const double *c, int nsrc, const double *zs, int max_modes,
                              double *psi0, double *kappa, int *n_modes) {
     if (!pl || !c || !zs || !psi0 || nsrc < 1) return fail(SSP_E_INVAL, "NULL argument or nsrc < 1");
@@ -609,11 +742,14 @@ ssp_status ssp_modal_starter(ssp_plan *pl, const double *c, int nsrc, const doub
 
 ssp_status ssp_set_absorber(ssp_plan *pl, const double *eta) {
     if (!pl) return fail(SSP_E_INVAL, "NULL plan");
+    { const ssp_status sp_ = sync_pending(pl); if (sp_ != SSP_OK) return sp_; }
     drop_graph(pl);
     if (!eta) {
         if (pl->stream) HIP_TRY(hipStreamSynchronize(pl->stream));
         else HIP_TRY(hipDeviceSynchronize());
         dev_free(pl->d_vi);
+        pl->h_eta.clear();
+        pl->rho_valid = false;
         return SSP_OK;
     }
     std::vector<float> v(pl->N);
@@ -621,6 +757,8 @@ ssp_status ssp_set_absorber(ssp_plan *pl, const double *eta) {
         if (!std::isfinite(eta[m])) return fail(SSP_E_INVAL, "non-finite absorber value");
         v[m] = static_cast<float>(eta[m]);
     }
+    pl->h_eta.assign(eta, eta + pl->N);
+    pl->rho_valid = false;
     if (!pl->d_vi) HIP_TRY(dev_alloc(&pl->d_vi, pl->N));
     HIP_TRY(hipMemcpyAsync(pl->d_vi, v.data(), pl->N * sizeof(float), hipMemcpyHostToDevice, pl->stream));
     HIP_TRY(hipStreamSynchronize(pl->stream));
@@ -629,6 +767,7 @@ ssp_status ssp_set_absorber(ssp_plan *pl, const double *eta) {
 
 ssp_status ssp_set_profile(ssp_plan *pl, int step0, int nsteps, const double *c) {
     if (!pl || !c) return fail(SSP_E_INVAL, "NULL argument");
+    { const ssp_status sp_ = sync_pending(pl); if (sp_ != SSP_OK) return sp_; }
     drop_graph(pl);
     if (step0 < 0 || nsteps == 0 || nsteps < -1) return fail(SSP_E_INVAL, "bad step range");
     const int rows = nsteps == -1 ? 1 : nsteps;
@@ -650,11 +789,23 @@ ssp_status ssp_set_profile(ssp_plan *pl, int step0, int nsteps, const double *c)
     pl->v_rows = rows;
     pl->v_step0 = step0;
     pl->prof_mode = nsteps == -1 ? ssp::PROF_TABLE_FIXED : ssp::PROF_TABLE_STEPS;
+    // rows kept in FP64 for the contraction estimate: the first, the middle and the last
+    std::vector<int> pick = {0, rows / 2, rows - 1};
+    pick.erase(std::unique(pick.begin(), pick.end()), pick.end());
+    pl->vs.assign(pick.size() * static_cast<size_t>(pl->N), 0.0);
+    for (size_t r = 0; r < pick.size(); ++r)
+        for (int m = 0; m < pl->N; ++m) {
+            const double q = pl->c0 / c[static_cast<size_t>(pick[r]) * pl->N + m];
+            pl->vs[r * pl->N + m] = q * q - 1.0;
+        }
+    pl->vs_rows = static_cast<int>(pick.size());
+    pl->rho_valid = false;
     return SSP_OK;
 }
 
 ssp_status ssp_set_profile_analytic(ssp_plan *pl, const ssp_env *env) {
     if (!pl || !env) return fail(SSP_E_INVAL, "NULL argument");
+    { const ssp_status sp_ = sync_pending(pl); if (sp_ != SSP_OK) return sp_; }
     drop_graph(pl);
     const double e[8] = {env->munk_c1, env->munk_eps, env->munk_z1, env->eddy_amp,
                          env->eddy_r0, env->eddy_rr, env->eddy_z0, env->eddy_rz};
@@ -690,17 +841,32 @@ ssp_status ssp_set_profile_analytic(ssp_plan *pl, const ssp_env *env) {
     pl->v_step0 = 0;
     for (int i = 0; i < 8; ++i) pl->env[i] = e[i];
     pl->prof_mode = ssp::PROF_ANALYTIC;
+    // rows kept in FP64 for the contraction estimate: the Munk profile alone and with the
+    // eddy at its centre range (its strongest)
+    pl->vs_rows = e[3] != 0.0 ? 2 : 1;
+    pl->vs.assign(static_cast<size_t>(pl->vs_rows) * N, 0.0);
+    for (int r = 0; r < pl->vs_rows; ++r)
+        for (int m = 0; m < N; ++m) {
+            const double z = (m + g.zoff) * g.dz, eta = 2.0 * (z - e[2]) / e[2];
+            double c = e[0] * (1.0 + e[1] * (eta + std::exp(-eta) - 1.0));
+            if (r == 1) c -= e[3] * std::exp(-((z - e[6]) / e[7]) * ((z - e[6]) / e[7]));
+            const double q = pl->c0 / c;
+            pl->vs[static_cast<size_t>(r) * N + m] = q * q - 1.0;
+        }
+    pl->rho_valid = false;
     return SSP_OK;
 }
 
 ssp_status ssp_set_field(ssp_plan *pl, const double *psi0) {
     if (!pl || !psi0) return fail(SSP_E_INVAL, "NULL argument");
+    { const ssp_status sp_ = sync_pending(pl); if (sp_ != SSP_OK) return sp_; }
     return set_field_internal(pl, psi0);
 }
 
 ssp_status ssp_get_field(const ssp_plan *cpl, double *psi) {
     ssp_plan *pl = const_cast<ssp_plan *>(cpl);
     if (!pl || !psi) return fail(SSP_E_INVAL, "NULL argument");
+    { const ssp_status sp_ = sync_pending(pl); if (sp_ != SSP_OK) return sp_; }
     if (!pl->has_field) return fail(SSP_E_STATE, "no field set");
     ssp_status st = ensure_out(pl, pl->N);
     if (st != SSP_OK) return st;
@@ -716,8 +882,9 @@ ssp_status ssp_get_field(const ssp_plan *cpl, double *psi) {
     return SSP_OK;
 }
 
-int ssp_count_outputs(const ssp_plan *pl, int nsteps) {
-    if (!pl) return 0;
+int ssp_count_outputs(const ssp_plan *cpl, int nsteps) {
+    ssp_plan *pl = const_cast<ssp_plan *>(cpl);
+    if (!pl || sync_pending(pl) != SSP_OK) return 0;
     return count_outputs(pl->step_index, nsteps, pl->out_every);
 }
 
@@ -740,6 +907,200 @@ ssp_status ssp_march(ssp_plan *pl, const double *psi0, int nsteps, double *field
 
 namespace {
 
+// ----------------------------------------------------------------------------- batches
+// A batch prepared for launch: descriptors sorted into launch groups.  Groups: the
+// uneven-length family of 1024-thread kernels (one launch), then one group per (FFT length,
+// transform kind, layout), then the dense-engine groups, one per grid size (last, because
+// their host-driven loop waits on its own stream while the FFT groups already run).
+struct Group {
+    int start, end;
+    bool family, dense;
+};
+struct Prepared {
+    std::vector<ssp::SolveDesc> sorted;
+    std::vector<int> order;  // sorted position -> caller's index
+    std::vector<Group> groups;
+    size_t dense_bytes = 0;  // scratch of all dense groups together
+};
+
+bool in_family(const ssp::SolveDesc &d) {
+    return d.engine == SSP_ENGINE_FFT && ssp::march_family_member(d.P) && d.variant == 0 && !d.direct;
+}
+
+void prepare_groups(const std::vector<ssp::SolveDesc> &descs, Prepared &b) {
+    const int n = static_cast<int>(descs.size());
+    b.order.resize(n);
+    for (int i = 0; i < n; ++i) b.order[i] = i;
+    auto rank = [](const ssp::SolveDesc &d) { return d.engine == SSP_ENGINE_DENSE ? 2 : (in_family(d) ? 0 : 1); };
+    std::stable_sort(b.order.begin(), b.order.end(), [&](int x, int y) {
+        const ssp::SolveDesc &p = descs[x], &q = descs[y];
+        if (rank(p) != rank(q)) return rank(p) < rank(q);
+        if (rank(p) == 2) {
+            if (p.N != q.N) return p.N > q.N;
+            return p.nsteps > q.nsteps;
+        }
+        if (p.P != q.P) return p.P > q.P;
+        if (p.direct != q.direct) return p.direct < q.direct;
+        if (p.variant != q.variant) return p.variant < q.variant;
+        return p.nsteps > q.nsteps;
+    });
+    b.sorted.resize(n);
+    for (int i = 0; i < n; ++i) b.sorted[i] = descs[b.order[i]];
+    b.groups.clear();
+    b.dense_bytes = 0;
+    int nf = 0;
+    while (nf < n && in_family(b.sorted[nf])) ++nf;
+    if (nf > 0 && b.sorted[0].P != b.sorted[nf - 1].P) b.groups.push_back({0, nf, true, false});
+    else nf = 0;
+    for (int start = nf; start < n;) {
+        const ssp::SolveDesc &h = b.sorted[start];
+        const bool dense = h.engine == SSP_ENGINE_DENSE;
+        int end = start;
+        while (end < n) {
+            const ssp::SolveDesc &d = b.sorted[end];
+            const bool same = dense ? (d.engine == SSP_ENGINE_DENSE && d.N == h.N)
+                                    : (d.engine != SSP_ENGINE_DENSE && d.P == h.P && d.variant == h.variant &&
+                                       d.direct == h.direct);
+            if (!same) break;
+            ++end;
+        }
+        b.groups.push_back({start, end, false, dense});
+        if (dense) b.dense_bytes += ssp::dense_work_bytes(end - start, h.N);
+        start = end;
+    }
+}
+
+bool has_dense(const Prepared &b) {
+    for (const Group &g : b.groups)
+        if (g.dense) return true;
+    return false;
+}
+
+ssp_status ensure_dense_scratch(ssp_plan *owner, size_t bytes) {
+    if (!owner->h_active) HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&owner->h_active), 64 * sizeof(int)));
+    if (bytes <= owner->dense_work_cap) return SSP_OK;
+    if (owner->d_dense_work) (void)hipFree(owner->d_dense_work);
+    owner->d_dense_work = nullptr;
+    owner->dense_work_cap = 0;
+    HIP_TRY(hipMalloc(&owner->d_dense_work, bytes));
+    owner->dense_work_cap = bytes;
+    return SSP_OK;
+}
+
+// Issue a prepared batch whose sorted descriptors are on the device at d_descs.  Groups run
+// concurrently: the first on `stream`, the others on the owner's side streams, forked from
+// and joined back into `stream`.  Each group's march is followed by its output launches.
+ssp_status launch_groups(ssp_plan *owner, const Prepared &b, const ssp::SolveDesc *d_descs, hipStream_t stream) {
+    const int ng = static_cast<int>(b.groups.size());
+    if (ng == 0) return SSP_OK;
+    if (has_dense(b)) {
+        ssp_status st = ensure_dense_scratch(owner, b.dense_bytes);
+        if (st != SSP_OK) return st;
+    }
+    if (ng > 1) {
+        HIP_TRY(ensure_side_streams(owner));
+        HIP_TRY(hipEventRecord(owner->fork, stream));
+    }
+    size_t dense_off = 0;
+    int dense_slot = 0;
+    for (int g = 0; g < ng; ++g) {
+        hipStream_t gs = g == 0 ? stream : owner->side[(g - 1) % kSideStreams];
+        if (g > 0 && g <= kSideStreams) HIP_TRY(hipStreamWaitEvent(gs, owner->fork, 0));
+        const Group &G = b.groups[g];
+        int gmax = 0, pmax = 0, nmax_max = 0;
+        for (int k = G.start; k < G.end; ++k) {
+            gmax = std::max(gmax, b.sorted[k].nsteps);
+            pmax = std::max(pmax, b.sorted[k].p);
+            nmax_max = std::max(nmax_max, b.sorted[k].nmax);
+        }
+        const ssp::SolveDesc &h = b.sorted[G.start];
+        if (G.dense) {
+            ssp::DenseTables t;
+            ssp_status st = dense_tables(h.N, t);
+            if (st != SSP_OK) return st;
+            const int B = G.end - G.start;
+            const ssp::DenseWork w =
+                ssp::carve_dense_work(static_cast<char *>(owner->d_dense_work) + dense_off, B, h.N);
+            dense_off += ssp::dense_work_bytes(B, h.N);
+            HIP_TRY(ssp::dense_march(t, d_descs + G.start, B, gmax, pmax, nmax_max, w,
+                                     owner->h_active + (dense_slot++ % 64), gs));
+        } else if (G.family) {
+            HIP_TRY(ssp::launch_march_family(d_descs + G.start, G.end - G.start, gmax, gs));
+        } else {
+            HIP_TRY(ssp::launch_march(h.P, h.variant, h.direct, d_descs + G.start, G.end - G.start, gmax, gs));
+        }
+        for (int start = G.start; start < G.end;) {
+            int end = start;
+            while (end < G.end && b.sorted[end].P == b.sorted[start].P && b.sorted[end].direct == b.sorted[start].direct)
+                ++end;
+            int rows = 0;
+            for (int k = start; k < end; ++k) rows = std::max(rows, b.sorted[k].snap ? b.sorted[k].nout : 0);
+            HIP_TRY(ssp::launch_output(b.sorted[start].P, b.sorted[start].direct, d_descs + start, end - start, rows,
+                                       gs));
+            start = end;
+        }
+    }
+    for (int j = 0; j < std::min(ng - 1, kSideStreams); ++j) {
+        HIP_TRY(hipEventRecord(owner->join[j], owner->side[j]));
+        HIP_TRY(hipStreamWaitEvent(stream, owner->join[j], 0));
+    }
+    return SSP_OK;
+}
+
+ssp_status upload_descs(ssp_plan *owner, const std::vector<ssp::SolveDesc> &sorted, hipStream_t stream) {
+    const int n = static_cast<int>(sorted.size());
+    if (owner->descs_cap < n) {
+        drop_graph(owner);
+        dev_free(owner->d_descs);
+        owner->descs_cap = 0;
+        HIP_TRY(dev_alloc(&owner->d_descs, n));
+        owner->descs_cap = n;
+    }
+    HIP_TRY(hipMemcpyAsync(owner->d_descs, sorted.data(), n * sizeof(ssp::SolveDesc), hipMemcpyHostToDevice,
+                           stream));
+    return SSP_OK;
+}
+
+// Bring the host step counter of a plan marched by ssp_march_batch_async up to date.
+ssp_status sync_pending(ssp_plan *pl) {
+    if (!pl->async_pending) return SSP_OK;
+    ssp::DevStats st{};
+    HIP_TRY(hipStreamSynchronize(pl->pending_stream));
+    HIP_TRY(hipMemcpy(&st, pl->d_stats, sizeof(st), hipMemcpyDeviceToHost));
+    pl->step_index = st.step_index;
+    pl->async_pending = false;
+    return SSP_OK;
+}
+
+// Potential rows of the contraction estimate: the sampled profile rows plus i eta.
+std::vector<std::complex<double>> estimate_rows(const ssp_plan *pl) {
+    std::vector<std::complex<double>> v = pl->vs;
+    if (!pl->h_eta.empty())
+        for (int r = 0; r < pl->vs_rows; ++r)
+            for (int m = 0; m < pl->N; ++m) v[static_cast<size_t>(r) * pl->N + m] += std::complex<double>(0, pl->h_eta[m]);
+    return v;
+}
+
+constexpr int kGateIterations = 40;
+
+// SSP_OPT_CONTRACTION_CHECK: the cached spectral-radius estimate of every factor's
+// Neumann operator (Dirichlet plans); SSP_E_DIVERGED if one is >= 1.
+ssp_status contraction_gate(ssp_plan *pl) {
+    if (!pl->contraction_check || pl->nmax == 0 || pl->bc != ssp::kBcDirichlet) return SSP_OK;
+    if (!pl->rho_valid) {
+        std::vector<double> bound;
+        ssp::neumann_contraction(pl->N, pl->H, pl->k0, pl->ps, pl->bc, estimate_rows(pl), pl->vs_rows,
+                                 kGateIterations, bound, pl->rho_est);
+        pl->rho_valid = true;
+    }
+    for (int j = 0; j < pl->p; ++j)
+        if (!(pl->rho_est[j] < 1.0))
+            return fail(SSP_E_DIVERGED, "Neumann operator of Pade factor " + std::to_string(j) +
+                                            " has spectral radius ~" + std::to_string(pl->rho_est[j]) +
+                                            " >= 1: the series cannot converge (contraction check)");
+    return SSP_OK;
+}
+
 // Shared body of ssp_march_batch and ssp_march_batch_steps: plan i marches steps[i] steps.
 ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, double *const *field_out,
                             float *const *tl_out, ssp_stats *stats) {
@@ -752,11 +1113,14 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
         if (!plans[i]->has_field) return fail(SSP_E_STATE, "plan without a field in batch");
         for (int k = 0; k < i; ++k)
             if (plans[k] == plans[i]) return fail(SSP_E_INVAL, "plan repeated in batch");
-        ssp_status st = check_profile_range(plans[i], plans[i]->step_index, steps[i]);
+    }
+    for (int i = 0; i < n; ++i) {
+        ssp_status st = sync_pending(plans[i]);
+        if (st == SSP_OK) st = check_profile_range(plans[i], plans[i]->step_index, steps[i]);
+        if (st == SSP_OK && steps[i] > 0) st = contraction_gate(plans[i]);
         if (st != SSP_OK) return st;
     }
     hipStream_t stream = plans[0]->stream;
-    // descriptors, grouped by FFT length
     std::vector<int> nout(n);
     std::vector<ssp::SolveDesc> descs(n);
     for (int i = 0; i < n; ++i) {
@@ -779,102 +1143,33 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
     }
     ssp_plan *owner = plans[0];
     drop_graph(owner);  // d_descs is rewritten below
-    if (owner->descs_cap < n) {
-        dev_free(owner->d_descs);
-        owner->descs_cap = 0;
-        HIP_TRY(dev_alloc(&owner->d_descs, n));
-        owner->descs_cap = n;
-    }
-    // order by FFT length, longest first: each length is a contiguous range, the lengths that
-    // share the 1024-thread kernel come first (one launch), and the longest solves are
-    // dispatched first
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    // (the family: lengths of the 1024-thread kernel in their default layout)
-    auto fam = [](const ssp::SolveDesc &d) {
-        return ssp::march_family_member(d.P) && d.variant == 0 && !d.direct;
-    };
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        const ssp::SolveDesc &a = descs[x], &b = descs[y];
-        if (fam(a) != fam(b)) return fam(a);
-        if (a.P != b.P) return a.P > b.P;
-        if (a.direct != b.direct) return a.direct < b.direct;
-        if (a.variant != b.variant) return a.variant < b.variant;
-        return a.nsteps > b.nsteps;
-    });
-    std::vector<ssp::SolveDesc> sorted(n);
-    for (int i = 0; i < n; ++i) sorted[i] = descs[order[i]];
-    HIP_TRY(hipMemcpyAsync(owner->d_descs, sorted.data(), n * sizeof(ssp::SolveDesc),
-                           hipMemcpyHostToDevice, stream));
+    Prepared b;
+    prepare_groups(descs, b);
+    ssp_status st0 = upload_descs(owner, b.sorted, stream);
+    if (st0 != SSP_OK) return st0;
+    const bool plain = n == 1 && owner->plain == 1;
     if (nsteps > 0) {
-        if (n == 1 && owner->engine == 1) {
+        if (plain) {
             // plain form: one kernel per stage, one solve
             ssp_plan *pl = owner;
-            if (pl->tab.direct)
-                return fail(SSP_E_UNIMPL, "the plain form runs chirp-z transforms only; plans with direct "
-                                          "transforms (periodic Nz or Dirichlet Nz + 1 a power of two) run "
-                                          "the fused kernel");
+            if (pl->tab.direct || b.sorted[0].engine != SSP_ENGINE_FFT)
+                return fail(SSP_E_UNIMPL, "the plain form runs chirp-z transforms of the FFT engine only; plans with "
+                                          "direct transforms (periodic Nz or Dirichlet Nz + 1 a power of two) or the "
+                                          "dense engine run the fused march");
             if (!pl->d_plain) {
                 HIP_TRY(dev_alloc(&pl->d_plain, 2 * static_cast<size_t>(pl->N)));
                 HIP_TRY(hipMalloc(reinterpret_cast<void **>(&pl->d_plain_flags), ssp::plain_state_bytes()));
             }
             HIP_TRY(hipMemsetAsync(pl->d_plain_flags, 0, ssp::plain_state_bytes(), stream));
-            long long idx = pl->step_index;
             ssp::DevStats z{};
-            z.step_index = idx;
+            z.step_index = pl->step_index;
             HIP_TRY(hipMemcpyAsync(pl->d_stats, &z, sizeof(z), hipMemcpyHostToDevice, stream));
-            HIP_TRY(ssp::plain_march(sorted[0], owner->d_descs, nsteps, pl->d_plain, pl->d_plain_flags, stream));
-            if (sorted[0].snap) HIP_TRY(ssp::launch_output(sorted[0].P, false, owner->d_descs, 1, sorted[0].nout, stream));
+            HIP_TRY(ssp::plain_march(b.sorted[0], owner->d_descs, nsteps, pl->d_plain, pl->d_plain_flags, stream));
+            if (b.sorted[0].snap)
+                HIP_TRY(ssp::launch_output(b.sorted[0].P, false, owner->d_descs, 1, b.sorted[0].nout, stream));
         } else {
-            // launch groups: the 1024-thread lengths together (one launch), then one per other
-            // length; each group's march is followed by its output launches (one per length)
-            struct Group { int start, end; bool family; };
-            std::vector<Group> groups;
-            int nf = 0;
-            while (nf < n && fam(sorted[nf])) ++nf;
-            if (nf > 0 && sorted[0].P != sorted[nf - 1].P) groups.push_back({0, nf, true});
-            else nf = 0;
-            for (int start = nf; start < n;) {
-                int end = start;
-                while (end < n && sorted[end].P == sorted[start].P && sorted[end].variant == sorted[start].variant &&
-                       sorted[end].direct == sorted[start].direct)
-                    ++end;
-                groups.push_back({start, end, false});
-                start = end;
-            }
-            // groups run concurrently: the first on the caller's stream, the others on the
-            // plan's side streams, forked from and joined back into the caller's stream
-            const int ng = static_cast<int>(groups.size());
-            if (ng > 1) {
-                HIP_TRY(ensure_side_streams(owner));
-                HIP_TRY(hipEventRecord(owner->fork, stream));
-            }
-            for (int g = 0; g < ng; ++g) {
-                hipStream_t gs = g == 0 ? stream : owner->side[(g - 1) % kSideStreams];
-                if (g > 0) HIP_TRY(hipStreamWaitEvent(gs, owner->fork, 0));
-                const Group &G = groups[g];
-                int gmax = 0;
-                for (int k = G.start; k < G.end; ++k) gmax = std::max(gmax, sorted[k].nsteps);
-                if (G.family)
-                    HIP_TRY(ssp::launch_march_family(owner->d_descs + G.start, G.end - G.start, gmax, gs));
-                else
-                    HIP_TRY(ssp::launch_march(sorted[G.start].P, sorted[G.start].variant, sorted[G.start].direct,
-                                              owner->d_descs + G.start, G.end - G.start, gmax, gs));
-                for (int start = G.start; start < G.end;) {
-                    int end = start;
-                    while (end < G.end && sorted[end].P == sorted[start].P && sorted[end].direct == sorted[start].direct)
-                        ++end;
-                    int rows = 0;
-                    for (int k = start; k < end; ++k) rows = std::max(rows, sorted[k].snap ? sorted[k].nout : 0);
-                    HIP_TRY(ssp::launch_output(sorted[start].P, sorted[start].direct, owner->d_descs + start,
-                                               end - start, rows, gs));
-                    start = end;
-                }
-            }
-            for (int j = 0; j < std::min(ng - 1, kSideStreams); ++j) {
-                HIP_TRY(hipEventRecord(owner->join[j], owner->side[j]));
-                HIP_TRY(hipStreamWaitEvent(stream, owner->join[j], 0));
-            }
+            ssp_status st = launch_groups(owner, b, owner->d_descs, stream);
+            if (st != SSP_OK) return st;
         }
     }
     ssp_status worst = SSP_OK;
@@ -889,8 +1184,7 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
             st = ssp::DevStats{};
             st.step_index = pl->step_index;
         }
-        if (pl->engine == 1 && n == 1 && st.status == SSP_OK && st.not_converged > 0)
-            st.status = SSP_W_NOT_CONVERGED;
+        if (plain && st.status == SSP_OK && st.not_converged > 0) st.status = SSP_W_NOT_CONVERGED;
         pl->step_index = st.step_index;
         const size_t cnt = static_cast<size_t>(nout[i]) * pl->N;
         if (field_out && field_out[i] && cnt) {
@@ -902,11 +1196,53 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
             HIP_TRY(hipMemcpy(tl_out[i], pl->d_out_tl, cnt * sizeof(float), hipMemcpyDeviceToHost));
         if (stats) std::memcpy(&stats[i], &st, sizeof(ssp_stats));
         ssp_status s = static_cast<ssp_status>(st.status);
-        if (s == SSP_E_DIVERGED) worst = SSP_E_DIVERGED;
+        if (s < 0 && (worst >= 0 || s == SSP_E_DIVERGED)) worst = s;
         else if (s == SSP_W_NOT_CONVERGED && worst == SSP_OK) worst = SSP_W_NOT_CONVERGED;
     }
-    if (worst == SSP_E_DIVERGED) g_last_error = "Neumann series diverged";
+    if (worst == SSP_E_DIVERGED) g_last_error = "Neumann series diverged (per-plan statuses in the statistics)";
+    else if (worst == SSP_E_INVAL) g_last_error = "a tabulated profile has no row for a step (per-plan statuses in the statistics)";
     return worst;
+}
+
+// Descriptors of a device-resident batch of B solves of one plan (ssp_march_device and its
+// no-allocation variant): scratch base (kWorkPerSolve N per solve), stats (d_stats or
+// stats_base), snapshots (snap_base, nout rows per solve) and TL rows (d_tl).
+std::vector<ssp::SolveDesc> device_descs(const ssp_plan *pl, int B, void *d_psi, void *d_step, int nsteps, int nout,
+                                         void *d_tl, void *d_stats, float2 *work_base, ssp::DevStats *stats_base,
+                                         float2 *snap_base) {
+    std::vector<ssp::SolveDesc> descs(B);
+    for (int b = 0; b < B; ++b) {
+        ssp::SolveDesc d = base_desc(pl);
+        d.field = static_cast<float2 *>(d_psi) + static_cast<size_t>(b) * pl->N;
+        ssp::set_work(d, work_base + ssp::kWorkPerSolve * static_cast<size_t>(b) * pl->N);
+        d.nout = nout;
+        d.nsteps = nsteps;
+        d.step = static_cast<long long *>(d_step) + b;
+        d.stats = (d_stats ? static_cast<ssp::DevStats *>(d_stats) : stats_base) + b;
+        d.tl_out = d_tl ? static_cast<float *>(d_tl) + static_cast<size_t>(b) * nout * pl->N : nullptr;
+        d.fld_out = nullptr;
+        if (nout == 0) d.tl_out = nullptr;
+        d.snap = d.tl_out ? snap_base + static_cast<size_t>(b) * nout * pl->N : nullptr;
+        descs[b] = d;
+    }
+    return descs;
+}
+
+// Launches of a device batch of one plan (descriptors already on the device).
+ssp_status device_launch(ssp_plan *pl, const ssp::SolveDesc &h, const ssp::SolveDesc *d_descs, int B, int nsteps,
+                         int nout, bool outputs) {
+    if (h.engine == SSP_ENGINE_DENSE) {
+        ssp::DenseTables t;
+        ssp_status st = dense_tables(pl->N, t);
+        if (st == SSP_OK) st = ensure_dense_scratch(pl, ssp::dense_work_bytes(B, pl->N));
+        if (st != SSP_OK) return st;
+        HIP_TRY(ssp::dense_march(t, d_descs, B, nsteps, pl->p, pl->nmax, ssp::carve_dense_work(pl->d_dense_work, B, pl->N),
+                                 pl->h_active, pl->stream));
+    } else {
+        HIP_TRY(ssp::launch_march(pl->P, effective_variant(pl), pl->tab.direct, d_descs, B, nsteps, pl->stream));
+    }
+    if (outputs) HIP_TRY(ssp::launch_output(pl->P, pl->tab.direct, d_descs, B, nout, pl->stream));
+    return SSP_OK;
 }
 
 }  // namespace
@@ -926,25 +1262,133 @@ ssp_status ssp_march_batch_steps(ssp_plan *const *plans, int n, const int *nstep
     return march_batch_impl(plans, n, nsteps, field_out, tl_out, stats);
 }
 
+ssp_status ssp_march_batch_async(ssp_plan *const *plans, int n, const int *nsteps, float *const *d_tl_out) {
+    if (!plans || !nsteps || n <= 0 || n > (1 << 24)) return fail(SSP_E_INVAL, "bad argument");
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i]) return fail(SSP_E_INVAL, "NULL plan in batch");
+        if (nsteps[i] < 0) return fail(SSP_E_INVAL, "nsteps must be >= 0");
+        if (!plans[i]->has_field) return fail(SSP_E_STATE, "plan without a field in batch");
+        for (int k = 0; k < i; ++k)
+            if (plans[k] == plans[i]) return fail(SSP_E_INVAL, "plan repeated in batch");
+        if (plans[i]->async_pending && plans[i]->pending_stream != plans[0]->stream) {
+            ssp_status st = sync_pending(plans[i]);
+            if (st != SSP_OK) return st;
+        }
+    }
+    ssp_plan *owner = plans[0];
+    hipStream_t stream = owner->stream;
+    // the recorded launches replay when the batch, its step counts, its output arrays and the
+    // stream are those of the recording
+    bool same = owner->use_graph && owner->bgraph_exec && owner->bkey_stream == stream &&
+                static_cast<int>(owner->bkey_plans.size()) == n;
+    for (int i = 0; same && i < n; ++i)
+        same = owner->bkey_plans[i] == plans[i] && owner->bkey_steps[i] == nsteps[i] &&
+               owner->bkey_tl[i] == static_cast<void *>(d_tl_out ? d_tl_out[i] : nullptr);
+    if (same) {
+        HIP_TRY(hipGraphLaunch(owner->bgraph_exec, stream));
+    } else {
+        std::vector<ssp::SolveDesc> descs(n);
+        for (int i = 0; i < n; ++i) {
+            ssp_plan *pl = plans[i];
+            ssp_status st = contraction_gate(pl);
+            if (st != SSP_OK) return st;
+            // rows available: the largest number of output steps in nsteps steps (the kernels
+            // place each row by the device step counter)
+            const int nout = (pl->out_every > 0 && d_tl_out && d_tl_out[i]) ? nsteps[i] / pl->out_every + 1 : 0;
+            st = ensure_out(pl, static_cast<size_t>(nout) * pl->N);
+            if (st != SSP_OK) return st;
+            ssp::SolveDesc d = base_desc(pl);
+            d.field = pl->d_field;
+            ssp::set_work(d, pl->d_work);
+            d.step = pl->d_step;
+            d.nout = nout;
+            d.nsteps = nsteps[i];
+            d.stats = pl->d_stats;
+            d.fld_out = nullptr;
+            d.tl_out = nout > 0 ? d_tl_out[i] : nullptr;
+            d.snap = nout > 0 ? pl->d_out_fld : nullptr;
+            descs[i] = d;
+        }
+        drop_graph(owner);
+        Prepared b;
+        prepare_groups(descs, b);
+        ssp_status st = upload_descs(owner, b.sorted, stream);
+        if (st != SSP_OK) return st;
+        if (owner->use_graph && stream && !has_dense(b)) {
+            // record the launches once (fork/join across the side streams becomes branches
+            // of the graph); the descriptors above stay valid for later replays
+            if (b.groups.size() > 1) HIP_TRY(ensure_side_streams(owner));
+            HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            st = launch_groups(owner, b, owner->d_descs, stream);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(stream, &g);
+            if (st != SSP_OK || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                if (st != SSP_OK) return st;
+                return fail(SSP_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e2));
+            }
+            owner->bgraph = g;
+            HIP_TRY(hipGraphInstantiate(&owner->bgraph_exec, g, nullptr, nullptr, 0));
+            owner->bkey_plans.assign(plans, plans + n);
+            owner->bkey_steps.assign(nsteps, nsteps + n);
+            owner->bkey_tl.assign(n, nullptr);
+            for (int i = 0; i < n; ++i) owner->bkey_tl[i] = d_tl_out ? d_tl_out[i] : nullptr;
+            owner->bkey_stream = stream;
+            HIP_TRY(hipGraphLaunch(owner->bgraph_exec, stream));
+        } else {
+            st = launch_groups(owner, b, owner->d_descs, stream);
+            if (st != SSP_OK) return st;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        plans[i]->async_pending = true;
+        plans[i]->pending_stream = stream;
+    }
+    return SSP_OK;
+}
+
+ssp_status ssp_batch_stats(ssp_plan *const *plans, int n, ssp_stats *stats) {
+    if (!plans || n <= 0) return fail(SSP_E_INVAL, "bad argument");
+    ssp_status worst = SSP_OK;
+    for (int i = 0; i < n; ++i) {
+        ssp_plan *pl = plans[i];
+        if (!pl) return fail(SSP_E_INVAL, "NULL plan");
+        ssp::DevStats st{};
+        HIP_TRY(hipStreamSynchronize(pl->async_pending ? pl->pending_stream : pl->stream));
+        HIP_TRY(hipMemcpy(&st, pl->d_stats, sizeof(st), hipMemcpyDeviceToHost));
+        pl->step_index = st.step_index;
+        pl->async_pending = false;
+        if (stats) std::memcpy(&stats[i], &st, sizeof(ssp_stats));
+        const ssp_status s = static_cast<ssp_status>(st.status);
+        if (s < 0 && (worst >= 0 || s == SSP_E_DIVERGED)) worst = s;
+        else if (s == SSP_W_NOT_CONVERGED && worst == SSP_OK) worst = SSP_W_NOT_CONVERGED;
+    }
+    return worst;
+}
+
 ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int nsteps, void *d_tl,
                             void *d_stats) {
     if (!pl || B <= 0 || !d_psi || !d_step || nsteps < 0) return fail(SSP_E_INVAL, "bad argument");
+    const bool dense = effective_engine(pl) == SSP_ENGINE_DENSE;
     const ssp_plan::GraphKey key{B, nsteps, d_psi, d_step, d_tl, d_stats, pl->stream};
-    if (pl->use_graph && pl->graph_exec && pl->graph_key == key) {
+    if (pl->use_graph && !dense && pl->graph_exec && pl->graph_key == key) {
         HIP_TRY(hipGraphLaunch(pl->graph_exec, pl->stream));
         return SSP_OK;
     }
     if (pl->use_graph && !pl->stream) return fail(SSP_E_INVAL, "graph replay needs a non-null stream");
-    ssp_status st = check_profile_range(pl, 0, 0);
+    ssp_status st = contraction_gate(pl);
     if (st != SSP_OK) return st;
     if (pl->descs_cap < B) {
+        drop_graph(pl);
         dev_free(pl->d_descs);
         pl->descs_cap = 0;
         HIP_TRY(dev_alloc(&pl->d_descs, B));
         pl->descs_cap = B;
     }
     // step counters live on the device and may differ between solves: each solve's output
-    // rows are the output steps after its own counter (computed in the kernels)
+    // rows are the output steps after its own counter (computed in the kernels); a
+    // tabulated profile is checked against them in the kernels (a missing row stops that
+    // solve with SSP_E_INVAL in its statistics)
     if (pl->bwork_cap < B) {
         dev_free(pl->d_bwork);
         pl->bwork_cap = 0;
@@ -957,7 +1401,6 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
         HIP_TRY(dev_alloc(&pl->d_bstats, B));
         pl->bstats_cap = B;
     }
-    std::vector<ssp::SolveDesc> descs(B);
     // rows available per solve: the largest number of output steps in nsteps steps
     const int nout = pl->out_every > 0 ? nsteps / pl->out_every + 1 : 0;
     const size_t snap_elems = d_tl ? static_cast<size_t>(B) * nout * pl->N : 0;
@@ -967,30 +1410,18 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
         HIP_TRY(dev_alloc(&pl->d_snap, snap_elems));
         pl->snap_cap = snap_elems;
     }
-    for (int b = 0; b < B; ++b) {
-        ssp::SolveDesc d = base_desc(pl);
-        d.field = static_cast<float2 *>(d_psi) + static_cast<size_t>(b) * pl->N;
-        ssp::set_work(d, pl->d_bwork + ssp::kWorkPerSolve * static_cast<size_t>(b) * pl->N);
-        d.nout = nout;
-        d.nsteps = nsteps;
-        d.step = static_cast<long long *>(d_step) + b;
-        d.stats = (d_stats ? static_cast<ssp::DevStats *>(d_stats) : pl->d_bstats) + b;
-        d.tl_out = d_tl ? static_cast<float *>(d_tl) + static_cast<size_t>(b) * nout * pl->N : nullptr;
-        d.fld_out = nullptr;
-        if (nout == 0) d.tl_out = nullptr;
-        d.snap = d.tl_out ? pl->d_snap + static_cast<size_t>(b) * nout * pl->N : nullptr;
-        descs[b] = d;
-    }
+    const std::vector<ssp::SolveDesc> descs =
+        device_descs(pl, B, d_psi, d_step, nsteps, nout, d_tl, d_stats, pl->d_bwork, pl->d_bstats, pl->d_snap);
     HIP_TRY(hipMemcpyAsync(pl->d_descs, descs.data(), B * sizeof(ssp::SolveDesc), hipMemcpyHostToDevice,
                            pl->stream));
-    if (pl->use_graph) {
+    const bool outputs = d_tl && nout > 0;
+    if (pl->use_graph && !dense) {
         // record the launches once; the descriptors above stay valid for later replays
         drop_graph(pl);
         HIP_TRY(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = ssp::launch_march(pl->P, effective_variant(pl), pl->tab.direct, pl->d_descs, B, nsteps,
                                          pl->stream);
-        if (e == hipSuccess && d_tl && nout > 0)
-            e = ssp::launch_output(pl->P, pl->tab.direct, pl->d_descs, B, nout, pl->stream);
+        if (e == hipSuccess && outputs) e = ssp::launch_output(pl->P, pl->tab.direct, pl->d_descs, B, nout, pl->stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(pl->stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -1002,12 +1433,15 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
         pl->graph_key = key;
         HIP_TRY(hipGraphLaunch(pl->graph_exec, pl->stream));
     } else {
-        HIP_TRY(ssp::launch_march(pl->P, effective_variant(pl), pl->tab.direct, pl->d_descs, B, nsteps, pl->stream));
-        if (d_tl && nout > 0) HIP_TRY(ssp::launch_output(pl->P, pl->tab.direct, pl->d_descs, B, nout, pl->stream));
+        st = device_launch(pl, descs[0], pl->d_descs, B, nsteps, nout, outputs);
+        if (st != SSP_OK) return st;
     }
-    pl->step_index += nsteps;
     return SSP_OK;
 }
+
+}  // extern "C"
+
+extern "C" {
 
 ssp_status ssp_to_sine(ssp_plan *pl, int B, const void *d_phys, void *d_sine) {
     if (!pl || B <= 0 || !d_phys || !d_sine) return fail(SSP_E_INVAL, "bad argument");
@@ -1044,31 +1478,19 @@ ssp_status ssp_dst_dense_device(ssp_plan *pl, int B, const void *d_in, void *d_o
     if (pl->N > ssp::kMaxDenseNz) return fail(SSP_E_UNIMPL, "Nz above ssp_max_dense_nz()");
     if (pl->bc != ssp::kBcDirichlet) return fail(SSP_E_UNIMPL, "the dense transform is the DST-I (Dirichlet plans)");
     if (B > (1 << 20)) return fail(SSP_E_INVAL, "B too large");
-    if (!pl->d_dense_sh) {
-        std::vector<uint16_t> sh, sl;
-        int kpad = 0;
-        ssp::build_dense_tables(pl->N, kpad, sh, sl);
-        HIP_TRY(dev_alloc(&pl->d_dense_sh, sh.size()));
-        HIP_TRY(dev_alloc(&pl->d_dense_sl, sl.size()));
-        HIP_TRY(hipMemcpy(pl->d_dense_sh, sh.data(), sh.size() * 2, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(pl->d_dense_sl, sl.data(), sl.size() * 2, hipMemcpyHostToDevice));
-        pl->dense_kpad = kpad;
-    }
+    ssp::DenseTables t;
+    ssp_status st = dense_tables(pl->N, t);
+    if (st != SSP_OK) return st;
     if (pl->dense_cols_cap < 2 * B) {
         dev_free(pl->d_dense_xh);
         dev_free(pl->d_dense_xl);
         dev_free(pl->d_dense_expo);
         pl->dense_cols_cap = 0;
-        HIP_TRY(dev_alloc(&pl->d_dense_xh, static_cast<size_t>(2 * B) * pl->dense_kpad));
-        HIP_TRY(dev_alloc(&pl->d_dense_xl, static_cast<size_t>(2 * B) * pl->dense_kpad));
+        HIP_TRY(dev_alloc(&pl->d_dense_xh, static_cast<size_t>(2 * B) * t.kpad));
+        HIP_TRY(dev_alloc(&pl->d_dense_xl, static_cast<size_t>(2 * B) * t.kpad));
         HIP_TRY(dev_alloc(&pl->d_dense_expo, static_cast<size_t>(2 * B)));
         pl->dense_cols_cap = 2 * B;
     }
-    ssp::DenseTables t;
-    t.sh = pl->d_dense_sh;
-    t.sl = pl->d_dense_sl;
-    t.n = pl->N;
-    t.kpad = pl->dense_kpad;
     HIP_TRY(ssp::launch_dense_dst(t, B, static_cast<const float2 *>(d_in), static_cast<float2 *>(d_out),
                                   pl->d_dense_xh, pl->d_dense_xl, pl->d_dense_expo, pl->stream));
     return SSP_OK;

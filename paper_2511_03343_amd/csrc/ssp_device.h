@@ -61,7 +61,16 @@ struct SolveDesc {
     int variant;                // engine layout of the march (host-side grouping only)
     int direct;                 // direct transform kind (0 chirp-z, 1 Fourier, 2 sine; host grouping)
     const float4 *mirror;       // [N] double-float odd-extension image factors (direct sine)
+    // dense engine (Dirichlet plans with N <= kMaxDenseNz), else null:
+    const float4 *tmul;         // [p][N] double-float -b_j/(1 + b_j x_l) in the plain sine basis
+    const float4 *mmod;         // [N] double-float m with (stored representation) = m (.) (sine
+                                //     coefficients), |m| = 1
+    int engine;                 // 0 FFT engine, 1 dense engine (host grouping only)
 };
+
+// Device statuses besides the ssp_status codes they share: a march step whose tabulated
+// profile row is missing stops that solve with kStatusProfileRange (SSP_E_INVAL).
+constexpr int kStatusProfileRange = -1;
 
 // Launch the fused persistent march: one workgroup per descriptor, all with the same FFT
 // length P, each marching its own descriptor's nsteps (nsteps here: the largest, 0 = no

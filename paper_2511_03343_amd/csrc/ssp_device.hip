@@ -31,6 +31,7 @@
 // that no fixed rounding of a table enters every step; residual norms in FP64; carrier
 // phase in FP64.
 #include "ssp_device.h"
+#include "ssp_df.h"
 #include "ssp_tuned.h"
 
 #include <math.h>
@@ -42,34 +43,6 @@ namespace {
 
 constexpr int kOK = 0, kNotConverged = 1, kDiverged = -4;
 
-
-// ----------------------------------------------------------------------------- complex
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
-}
-// x * (w.hi + w.lo) with w = (hi.re, hi.im, lo.re, lo.im): the small products first, so the
-// result carries only the rounding of the arithmetic, not the rounding of the table.
-__device__ __forceinline__ float2 cmul_df(float2 x, float4 w) {
-    float re = fmaf(-x.y, w.w, x.x * w.z);
-    re = fmaf(x.x, w.x, re);
-    re = fmaf(-x.y, w.y, re);
-    float im = fmaf(x.y, w.z, x.x * w.w);
-    im = fmaf(x.x, w.y, im);
-    im = fmaf(x.y, w.x, im);
-    return make_float2(re, im);
-}
-// x * conj(w.hi + w.lo)
-__device__ __forceinline__ float2 cmul_df_conj(float2 x, float4 w) {
-    float re = fmaf(x.y, w.w, x.x * w.z);
-    re = fmaf(x.x, w.x, re);
-    re = fmaf(x.y, w.y, re);
-    float im = fmaf(-x.x, w.w, x.y * w.z);
-    im = fmaf(-x.x, w.y, im);
-    im = fmaf(x.y, w.x, im);
-    return make_float2(re, im);
-}
 
 // ----------------------------------------------------------------------------- memory
 // Global memory is accessed through buffer resources: the base address stays in scalar
@@ -686,14 +659,17 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
         chirp_core<EK, false, true>(x, L, tw, k1, k2);
     } else {
         constexpr int T = Cfg<EK>::T, RT = Cfg<EK>::RT;
+        static_assert(P / T <= 32 && 32 % (P / T) == 0, "twist factor w_{P/T}^i is a radix constant");
         const int N = d.N;
         float2 y[KEEP_GLOBAL ? 1 : RT];
-        // odd-frequency input y = x (.) w_P^n
+        // odd-frequency input y = x (.) w_P^n: for n = t + i T, w_P^n = w_P^t w_{P/T}^i, the
+        // thread's w_P^t from the table (one load) and w_{P/T}^i a double-float radix constant
+        const float4 wt = ld4(d.twist, opaque_tid());
 #pragma unroll
         for (int i = 0; i < RT; ++i) {
             const int pos = opaque_tid() + i * T;
             float2 v = make_float2(0.f, 0.f);
-            if (pos < N) v = cmul_df(x[i], ld4(d.twist, pos));
+            if (pos < N) v = mulw<P / T, false>(cmul_df(x[i], wt), i);
             if constexpr (KEEP_GLOBAL) {
                 if (pos < N) st2(keep, pos, v);
             } else {
@@ -712,7 +688,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T;
-                x[i] = pos < N ? cadd(ld2(keep + N, pos), cmul_df_conj(x[i], ld4(d.twist, pos)))
+                x[i] = pos < N ? cadd(ld2(keep + N, pos), mulw<P / T, true>(cmul_df_conj(x[i], wt), i))
                                : make_float2(0.f, 0.f);
             }
         } else {
@@ -720,7 +696,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T;
-                x[i] = pos < N ? cadd(x[i], cmul_df_conj(y[i], ld4(d.twist, pos))) : make_float2(0.f, 0.f);
+                x[i] = pos < N ? cadd(x[i], mulw<P / T, true>(cmul_df_conj(y[i], wt), i)) : make_float2(0.f, 0.f);
             }
         }
     }
@@ -766,8 +742,6 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *red) {
     }
     __syncthreads();
 }
-
-__device__ __forceinline__ float cnorm2(float2 v) { return fmaf(v.x, v.x, v.y * v.y); }
 
 // exp(i sigma n) for the carrier of step n, in FP64: Cody-Waite reduction by pi/2 (two-part
 // constant) and Taylor series of sin and cos on [-pi/4, pi/4] (truncation < 1e-17).
@@ -894,6 +868,10 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
 
     for (int s = 0; s < nsteps; ++s) {
         const long long nn = n + 1;
+        if (d.prof_mode == PROF_TABLE_STEPS && (nn - d.v_step0 - 1 < 0 || nn - d.v_step0 - 1 >= d.v_rows)) {
+            status = kStatusProfileRange;  // no profile row for this step (uniform)
+            break;
+        }
         if (d.prof_mode != PROF_TABLE_FIXED) load_potential<P, V, kAInRegs, DK>(d, nn, A);
         bool bad = false;
         for (int j = 0; j < p; ++j) {
@@ -1027,7 +1005,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     if (tid == 0) {
         *d.step = n;
         if (status == kOK && notconv > 0) status = kNotConverged;
-        DevStats st;
+        DevStats st;  // (a solve stopped for a missing profile row keeps its steps so far)
         st.steps_done = done;
         st.step_index = n;
         st.neumann_terms = terms;

@@ -384,6 +384,9 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
         return cd(std::cos(ang), std::sin(ang));
     };
     std::vector<cd> dmod(N);
+    const bool dense = bc == kBcDirichlet && N <= kMaxDenseGrid;
+    t.mmod.clear();
+    if (dense) t.mmod.assign(4 * static_cast<size_t>(N), 0.f);
     t.pre.assign(2 * N, 0.f);
     t.post.assign(2 * N, 0.f);
     t.dmod.assign(2 * N, 0.f);
@@ -429,6 +432,13 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
         dmod[m] = (bc == kBcDirichlet && direct == kDirectNone)
                       ? std::conj(chirp(m + 1)) * std::conj(chirp(m + 1)) * I * (0.5 * std::sqrt(2.0 / (N + 1)) / P)
                       : post_f * pre_i;
+        if (dense) {
+            // stored representation = (inverse pre-modulation) (.) coefficients: the
+            // stand-alone forward transform ends with dmod, the plain DST-I with post, and
+            // dmod / post = pre_i for both Dirichlet transform kinds
+            split_df(pre_i.real(), t.mmod[4 * m], t.mmod[4 * m + 2]);
+            split_df(pre_i.imag(), t.mmod[4 * m + 1], t.mmod[4 * m + 3]);
+        }
         put_c(t.pre, m, pre_f);
         put_c(t.post, m, post_i);
         put_c(t.dmod, m, dmod[m]);
@@ -451,6 +461,8 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
     t.bmul.resize(static_cast<size_t>(4) * p * N);
     t.alpha.resize(4 * p);
     t.beta.resize(4 * p);
+    t.tmul.clear();
+    if (dense) t.tmul.resize(static_cast<size_t>(4) * p * N);
     double gain = 0;
     for (int m = 0; m < N; ++m) {
         // eigenvalue of d_z^2 / k0^2 of basis function m: -(l pi/(H k0))^2 with l = m+1
@@ -470,6 +482,11 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
             split_df(sj.imag(), t.s[o + 1], t.s[o + 3]);
             split_df(bj.real(), t.bmul[o], t.bmul[o + 2]);
             split_df(bj.imag(), t.bmul[o + 1], t.bmul[o + 3]);
+            if (dense) {
+                const cd tj = -ps.b[j] * sj;
+                split_df(tj.real(), t.tmul[o], t.tmul[o + 2]);
+                split_df(tj.imag(), t.tmul[o + 1], t.tmul[o + 3]);
+            }
         }
     }
     t.max_gain = gain;
@@ -511,6 +528,101 @@ void build_dense_tables(int n, int &kpad, std::vector<uint16_t> &sh, std::vector
             sh[static_cast<size_t>(k - 1) * kpad + (j - 1)] = hb;
             sl[static_cast<size_t>(k - 1) * kpad + (j - 1)] = lb;
         }
+    }
+}
+
+}  // namespace ssp
+
+// ------------------------------------------------------------------ Neumann contraction
+namespace ssp {
+
+HostDst1::HostDst1(int n) : N(n) {
+    // DST(x)_k = (i/2) sqrt(2/M) conj(c_k) sum_n conj(c_n) x_n (c_{k-n} - c_{k+n}),
+    // c_d = exp(i pi d^2/(2M)), M = N + 1: a Toeplitz minus a Hankel sum over positions
+    // n - 1, both cyclic convolutions of a power-of-two length P >= 2N - 1 (the Hankel one
+    // through the reflected spectrum), as in the device's chirp-z transform
+    const long long M = N + 1;
+    P = 1;
+    while (P < 2 * N - 1) P *= 2;
+    ch.resize(2 * static_cast<size_t>(N) + 1);
+    for (long long d = 0; d <= 2LL * N; ++d) {
+        const long long r = (d * d) % (4 * M);
+        const double ang = kPiD * static_cast<double>(r) / static_cast<double>(2 * M);
+        ch[d] = cd(std::cos(ang), std::sin(ang));
+    }
+    k1.assign(P, 0.0);
+    k2.assign(P, 0.0);
+    for (long long d = 1 - N; d <= N - 1; ++d) k1[((d % P) + P) % P] = ch[d < 0 ? -d : d];
+    for (long long d = 0; d <= 2LL * N - 2; ++d) k2[d % P] = ch[d + 2];
+    host_fft(k1, -1);
+    host_fft(k2, -1);
+}
+
+void HostDst1::apply(std::vector<cd> &x) const {
+    std::vector<cd> y(P, 0.0), z(P);
+    for (int n = 1; n <= N; ++n) y[n - 1] = std::conj(ch[n]) * x[n - 1];
+    host_fft(y, -1);
+    for (int q = 0; q < P; ++q) z[q] = y[q] * k1[q] - y[(P - q) % P] * k2[q];
+    host_fft(z, +1);
+    const cd scale = cd(0, 0.5) * std::sqrt(2.0 / static_cast<double>(N + 1)) / static_cast<double>(P);
+    for (int k = 1; k <= N; ++k) x[k - 1] = scale * std::conj(ch[k]) * z[k - 1];
+}
+
+void neumann_contraction(int nz, double depth, double k0, const PadeSet &ps, int bc, const std::vector<cd> &v,
+                         int rows, int iterations, std::vector<double> &bound, std::vector<double> &estimate) {
+    const int N = nz, p = ps.p;
+    std::vector<double> x(N);
+    for (int m = 0; m < N; ++m) {
+        double l;
+        if (bc == kBcDirichlet) l = m + 1;
+        else if (bc == kBcNeumann) l = m;
+        else l = 2.0 * static_cast<double>(2 * m <= N ? m : m - N);
+        x[m] = -std::pow(l * kPiD / (depth * k0), 2);
+    }
+    double vmax = 0;
+    for (const cd &a : v) vmax = std::max(vmax, std::abs(a));
+    bound.assign(p, 0.0);
+    estimate.assign(p, std::nan(""));
+    for (int j = 0; j < p; ++j) {
+        double g = 0;
+        for (int m = 0; m < N; ++m) g = std::max(g, std::abs(ps.b[j] / (1.0 + ps.b[j] * x[m])));
+        bound[j] = g * vmax;
+    }
+    if (bc != kBcDirichlet || iterations <= 0 || rows <= 0) return;
+    const int half = iterations / 2;
+    const HostDst1 S(N);
+    for (int j = 0; j < p; ++j) {
+        double best = 0;
+        for (int r = 0; r < rows; ++r) {
+            // a fixed pseudo-random start in the sine basis (64-bit LCG)
+            std::vector<cd> u(N);
+            unsigned long long st = 0x9E3779B97F4A7C15ULL + 7919ULL * static_cast<unsigned long long>(j * 131 + r);
+            auto rnd = [&st]() {
+                st = st * 6364136223846793005ULL + 1442695040888963407ULL;
+                return static_cast<double>(st >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+            };
+            for (int m = 0; m < N; ++m) u[m] = cd(rnd(), rnd());
+            double lg = 0, lg_half = 0;
+            for (int it = 1; it <= iterations; ++it) {
+                // u <- b_j D_j S (v (.) S u), then normalised; the log-norms accumulate
+                S.apply(u);
+                for (int m = 0; m < N; ++m) u[m] *= v[static_cast<size_t>(r) * N + m];
+                S.apply(u);
+                double nrm = 0;
+                for (int m = 0; m < N; ++m) {
+                    u[m] *= ps.b[j] / (1.0 + ps.b[j] * x[m]);
+                    nrm += std::norm(u[m]);
+                }
+                nrm = std::sqrt(nrm);
+                if (!(nrm > 0) || !std::isfinite(nrm)) break;
+                for (int m = 0; m < N; ++m) u[m] /= nrm;
+                lg += std::log(nrm);
+                if (it == half) lg_half = lg;
+            }
+            const double rate = std::exp((lg - lg_half) / static_cast<double>(iterations - half));
+            best = std::max(best, rate);
+        }
+        estimate[j] = best;
     }
 }
 

@@ -96,10 +96,37 @@ struct DeviceTables {
     std::vector<float> bmul;          // [p][nz] double-float complex -b_j s_jl * dmod_l (FP64 product)
     std::vector<float> alpha, beta;   // [p] double-float complex combine weights
     double max_gain = 0;              // max_l |e^{i sigma} R(x_l)|
+    // dense engine (Dirichlet grids with nz <= kMaxDenseGrid), else empty:
+    std::vector<float> tmul;          // [p][nz] double-float complex -b_j/(1 + b_j x_l), plain sine basis
+    std::vector<float> mmod;          // [nz] double-float complex m, representation = m (.) coefficients
 };
+
+// Largest grid of the dense engine (its S matrix is kpad^2 fp16 values per part).
+constexpr int kMaxDenseGrid = 2048;
 
 // Build all device tables for a grid (nz, H, k0, boundary condition) and a coefficient set.
 void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, DeviceTables &t);
+
+// Convergence of the Neumann series of every Pade factor (Sec. 3: the series for
+// (1 + b_j X)^{-1} converges when the operator K_j = b_j L_j^{-1} V is a contraction), for the
+// potential rows v [rows][nz] (v + i eta, FP64) of a grid with boundary condition bc:
+//   bound[j]    = max_l |b_j/(1 + b_j x_l)| max |v|, a norm bound of K_j (>= its spectral radius;
+//                 below 1 the series converges geometrically for any input)
+//   estimate[j] = the spectral radius of K_j by power iteration over `iterations` products
+//                 (growth rate over the second half of the iteration, largest over the rows),
+//                 Dirichlet grids only (NaN otherwise or for iterations <= 0); a series whose
+//                 operator has spectral radius >= 1 diverges for generic inputs.
+void neumann_contraction(int nz, double depth, double k0, const PadeSet &ps, int bc, const std::vector<cd> &v,
+                         int rows, int iterations, std::vector<double> &bound, std::vector<double> &estimate);
+
+// Orthonormal DST-I of complex FP64 vectors of length n, in place, through one FFT pair of a
+// power-of-two length >= 2n - 1 (the host transform of the contraction estimate).
+struct HostDst1 {
+    explicit HostDst1(int n);
+    void apply(std::vector<cd> &x) const;
+    int N = 0, P = 0;
+    std::vector<cd> ch, k1, k2;
+};
 
 // Split a double into hi + lo floats (hi = nearest float, lo = nearest float of the rest).
 inline void split_df(double v, float &hi, float &lo) {

@@ -77,6 +77,7 @@ class ServeResult:
     steps_done: int = 0
     neumann_terms: int = 0
     not_converged: int = 0
+    fields: List[np.ndarray] = field(default_factory=list)  # field rows (run(march_fields=True))
     status: int = 0
     admitted: float = math.nan
     finished: float = math.nan
@@ -112,24 +113,18 @@ def plan_device_bytes(nz: int, pade_order: int, out_rows: int) -> int:
     return tables + state + staging
 
 
-# Engine layouts for the serving mix, by FFT length (SSP_OPT_VARIANT).  The library's tuned
-# layouts are chosen on uniform batches of one length, where the two-workgroup layout 2 is
-# fastest at 4096 and 8192; in an over-subscribed mix of lengths the one-workgroup layouts
-# measured faster (the Poisson stream of the serving benchmark: 1.78e8 against 1.61e8 field
-# updates/s, p50 latency 23.4 against 28.8 s).  A plan's layout is fixed when it is created,
-# so a request's result does not depend on what it is batched with.
-SERVING_LAYOUTS = {4096: 0, 8192: 1}
-
-
 class LibBackend:
-    """The HIP library: one plan per admitted request (layouts: FFT length -> engine layout
-    for the plans it creates, the library's tuned layout for other lengths)."""
+    """The HIP library: one plan per admitted request.  Plans take the engine layouts the
+    autotuner measured on a mixed-length batch (SSP_OPT_VARIANT = -2) and the engine chosen
+    for their (Nz, Pade order) class (SSP_OPT_ENGINE = SSP_ENGINE_AUTO); both are fixed per
+    plan, so a request's arithmetic does not depend on what it is batched with."""
 
-    def __init__(self, stream_ptr: Optional[int] = None, layouts: Optional[dict] = None):
+    def __init__(self, stream_ptr: Optional[int] = None, variant: int = -2, engine: Optional[int] = None):
         from . import ssp
         self.ssp = ssp
         self.stream = stream_ptr
-        self.layouts = SERVING_LAYOUTS if layouts is None else layouts
+        self.variant = variant
+        self.engine = ssp.SSP_ENGINE_AUTO if engine is None else engine
 
     def create(self, r: ServeRequest):
         s = self.ssp
@@ -138,9 +133,10 @@ class LibBackend:
             if self.stream is not None:
                 s.ssp_plan_set_stream(pl, self.stream)
             s.ssp_plan_set_option(pl, s.SSP_OPT_OUT_EVERY, r.out_every)
-            fft_len = s.ssp_plan_engine(pl)[2]
-            if fft_len in self.layouts:
-                s.ssp_plan_set_option(pl, s.SSP_OPT_VARIANT, self.layouts[fft_len])
+            s.ssp_plan_set_option(pl, s.SSP_OPT_VARIANT, self.variant)
+            dense_ok = r.nz <= s.ssp_max_dense_nz()
+            s.ssp_plan_set_option(pl, s.SSP_OPT_ENGINE, self.engine if (self.engine != s.SSP_ENGINE_DENSE or dense_ok)
+                                  else s.SSP_ENGINE_FFT)
             if r.c_table is not None:
                 s.ssp_set_profile(pl, 0, -1, r.c_table)
             else:
@@ -157,8 +153,18 @@ class LibBackend:
                                                           want_field=False, want_tl=True)
         return tl, stats
 
+    def march_fields(self, handles: Sequence, nzs: Sequence[int], steps: Sequence[int]):
+        """march() that also returns each plan's field rows (for checks against the oracle)."""
+        st, fl, tl, stats = self.ssp.ssp_march_batch_steps(list(handles), list(nzs), list(steps),
+                                                           want_field=True, want_tl=True)
+        return fl, tl, stats
+
     def destroy(self, handle) -> None:
         self.ssp.ssp_plan_destroy(handle)
+
+    def error_status(self, exc: Exception) -> Optional[int]:
+        """The library status of an exception raised by create(), or None if it is not one."""
+        return getattr(exc, "status", None) if isinstance(exc, self.ssp.SspError) else None
 
     @staticmethod
     def free_bytes() -> int:
@@ -189,18 +195,27 @@ class Server:
         self.peak_bytes = 0
         self.t_create = 0.0   # host time creating plans
         self.t_march = 0.0    # time in the batched march calls
+        self.failed = 0       # requests that ended with an error status
+
+    def tick_steps_cap(self, r: ServeRequest) -> int:
+        """The most range steps one tick gives request r; its output staging is budgeted for
+        that many (see _cost), and run() never gives more."""
+        return min(r.nsteps, self.k * max(1, int(step_cost(16384, 1.0) / step_cost(r.nz, 1.0))) * 4)
 
     def _cost(self, r: ServeRequest) -> int:
-        # output staging for the most steps a tick can give this request
-        k = min(r.nsteps, self.k * max(1, int(step_cost(16384, 1.0) / step_cost(r.nz, 1.0))) * 4)
-        rows = k // max(r.out_every, 1) + 1
+        rows = self.tick_steps_cap(r) // max(r.out_every, 1) + 1
         return plan_device_bytes(r.nz, r.pade_order, rows)
 
-    def run(self, requests: Sequence[ServeRequest], realtime: bool = False) -> Dict[int, ServeResult]:
+    def run(self, requests: Sequence[ServeRequest], realtime: bool = False,
+            march_fields: bool = False) -> Dict[int, ServeResult]:
         """Serve the stream.  realtime: requests become visible at their arrival time on the
-        wall clock (the server idles until then); otherwise idle gaps are skipped, i.e. time
-        advances by the measured duration of each tick and jumps to the next arrival when
-        nothing is active.  Returns the results by request id."""
+        wall clock (the server idles until then); otherwise the server keeps a virtual clock
+        that advances by the measured duration of each tick (admission and march) and jumps
+        to the next arrival when nothing is active, so latencies are those of an arrival
+        process replayed against the device's own pace.  A request whose plan cannot be
+        created (e.g. unstable coefficients) or whose march fails (e.g. a diverged series)
+        ends with that status; the others continue.  march_fields: keep every request's
+        field rows too (ServeResult.fields), for checks.  Returns the results by request id."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         for i, r in enumerate(reqs):
             if r.rid < 0:
@@ -218,68 +233,94 @@ class Server:
         def now() -> float:
             return self.clock() - t_wall0 if realtime else vclock
 
-        while pending or queue or active:
-            t = now()
-            while pending and pending[0].arrival <= t:
-                queue.append(pending.popleft())
-            if not queue and not active:
-                nxt = pending[0].arrival
-                if realtime:
-                    time.sleep(max(0.0, nxt - now()))
-                else:
-                    vclock = nxt
-                continue
-            tick0 = self.clock()
-            # admission in arrival order (no overtaking)
-            tc = self.clock()
-            while queue and len(active) < self.max_active and used + self._cost(queue[0]) <= self.hbm_budget:
-                r = queue.popleft()
-                cost = self._cost(r)
-                h = self.backend.create(r)
-                used += cost
-                active.append({"req": r, "h": h, "left": r.nsteps, "cost": cost, "tps": 40.0})
-                results[r.rid].admitted = t
-            self.t_create += self.clock() - tc
-            self.peak_active = max(self.peak_active, len(active))
-            self.peak_bytes = max(self.peak_bytes, used)
-            if active:
-                costs = [step_cost(a["req"].nz, a["tps"]) for a in active]
-                cmax = max(costs)
-                steps = [max(1, min(a["left"], int(round(self.k * cmax / c)))) for a, c in zip(active, costs)]
-                tm = self.clock()
-                tl, stats = self.backend.march([a["h"] for a in active], [a["req"].nz for a in active], steps)
-                self.t_march += self.clock() - tm
-                self.ticks += 1
-                for a, rows, st, k in zip(active, tl, stats, steps):
-                    res = results[a["req"].rid]
-                    if rows is not None and len(rows):
-                        res.tl.append(np.array(rows, copy=True))
-                    res.steps_done += int(st["steps_done"])
-                    res.neumann_terms += int(st["neumann_terms"])
-                    res.not_converged += int(st["not_converged"])
-                    if st["steps_done"] > 0:
-                        a["tps"] = st["neumann_terms"] / st["steps_done"]
-                    if st["status"] < 0 or (st["status"] > 0 and res.status == 0):
-                        res.status = int(st["status"])
-                    a["left"] = 0 if st["status"] < 0 else a["left"] - k
-            if not realtime:
-                vclock += self.clock() - tick0
-            t_end = now()
-            keep = []
-            for a in active:
-                if a["left"] > 0:
-                    keep.append(a)
+        try:
+            while pending or queue or active:
+                t = now()
+                while pending and pending[0].arrival <= t:
+                    queue.append(pending.popleft())
+                if not queue and not active:
+                    nxt = pending[0].arrival
+                    if realtime:
+                        time.sleep(max(0.0, nxt - now()))
+                    else:
+                        vclock = nxt
                     continue
+                tick0 = self.clock()
+                # admission in arrival order (no overtaking)
+                tc = self.clock()
+                while queue and len(active) < self.max_active and used + self._cost(queue[0]) <= self.hbm_budget:
+                    r = queue.popleft()
+                    cost = self._cost(r)
+                    results[r.rid].admitted = t
+                    try:
+                        h = self.backend.create(r)
+                    except Exception as exc:  # this request fails, the stream goes on
+                        code = self.backend.error_status(exc) if hasattr(self.backend, "error_status") else None
+                        if code is None:
+                            raise
+                        results[r.rid].status = int(code)
+                        results[r.rid].finished = t
+                        self.failed += 1
+                        continue
+                    used += cost
+                    active.append({"req": r, "h": h, "left": r.nsteps, "cost": cost, "tps": 40.0,
+                                   "cap": self.tick_steps_cap(r)})
+                self.t_create += self.clock() - tc
+                self.peak_active = max(self.peak_active, len(active))
+                self.peak_bytes = max(self.peak_bytes, used)
+                if active:
+                    costs = [step_cost(a["req"].nz, a["tps"]) for a in active]
+                    cmax = max(costs)
+                    steps = [max(1, min(a["left"], a["cap"], int(round(self.k * cmax / c))))
+                             for a, c in zip(active, costs)]
+                    tm = self.clock()
+                    handles, nzs = [a["h"] for a in active], [a["req"].nz for a in active]
+                    if march_fields:
+                        fl, tl, stats = self.backend.march_fields(handles, nzs, steps)
+                    else:
+                        fl = [None] * len(active)
+                        tl, stats = self.backend.march(handles, nzs, steps)
+                    self.t_march += self.clock() - tm
+                    self.ticks += 1
+                    for a, rows, frows, st, k in zip(active, tl, fl, stats, steps):
+                        res = results[a["req"].rid]
+                        if rows is not None and len(rows):
+                            res.tl.append(np.array(rows, copy=True))
+                        if frows is not None and len(frows):
+                            res.fields.append(np.array(frows, copy=True))
+                        res.steps_done += int(st["steps_done"])
+                        res.neumann_terms += int(st["neumann_terms"])
+                        res.not_converged += int(st["not_converged"])
+                        if st["steps_done"] > 0:
+                            a["tps"] = st["neumann_terms"] / st["steps_done"]
+                        if st["status"] < 0 or (st["status"] > 0 and res.status == 0):
+                            res.status = int(st["status"])
+                        a["left"] = 0 if st["status"] < 0 else a["left"] - k
+                if not realtime:
+                    vclock += self.clock() - tick0
+                t_end = now()
+                keep = []
+                for a in active:
+                    if a["left"] > 0:
+                        keep.append(a)
+                        continue
+                    self.backend.destroy(a["h"])
+                    used -= a["cost"]
+                    res = results[a["req"].rid]
+                    res.finished = t_end
+                    if res.status >= 0:
+                        res.latency = t_end - a["req"].arrival
+                    else:
+                        self.failed += 1
+                active = keep
+        finally:
+            for a in active:  # an exception left requests on the device: release their plans
                 self.backend.destroy(a["h"])
-                used -= a["cost"]
-                res = results[a["req"].rid]
-                res.finished = t_end
-                res.latency = t_end - a["req"].arrival
-            active = keep
         return results
 
 
 def latency_summary(results: Dict[int, ServeResult]) -> dict:
+    """p50 / p99 / max / mean latency (s) of the requests that completed (status >= 0)."""
     lat = np.array([r.latency for r in results.values() if np.isfinite(r.latency)])
     if lat.size == 0:
         return {"count": 0}

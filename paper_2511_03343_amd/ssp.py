@@ -31,6 +31,16 @@ SSP_OPT_STREAM = 3
 SSP_OPT_ENGINE = 4
 SSP_OPT_GRAPH = 5
 SSP_OPT_VARIANT = 6
+SSP_OPT_PLAIN = 7
+SSP_OPT_FORM = 8
+SSP_OPT_GAIN_LIMIT = 9
+SSP_OPT_CONTRACTION_CHECK = 10
+
+SSP_ENGINE_FFT = 0
+SSP_ENGINE_DENSE = 1
+SSP_ENGINE_AUTO = 2
+SSP_FORM_PRODUCT = 0
+SSP_FORM_SUM = 1
 
 SSP_BC_DIRICHLET = 0
 SSP_BC_NEUMANN = 1
@@ -105,6 +115,9 @@ def lib() -> C.CDLL:
             "ssp_march_batch_steps": (S, [C.POINTER(_VP), C.c_int, C.POINTER(C.c_int), C.POINTER(_DP),
                                           C.POINTER(_FP), C.POINTER(ssp_stats)]),
             "ssp_march_device": (S, [_VP, C.c_int, _VP, _VP, C.c_int, _VP, _VP]),
+            "ssp_march_batch_async": (S, [C.POINTER(_VP), C.c_int, C.POINTER(C.c_int), C.POINTER(_FP)]),
+            "ssp_batch_stats": (S, [C.POINTER(_VP), C.c_int, C.POINTER(ssp_stats)]),
+            "ssp_plan_contraction": (S, [_VP, C.c_int, _DP, _DP]),
             "ssp_to_sine": (S, [_VP, C.c_int, _VP, _VP]),
             "ssp_from_sine": (S, [_VP, C.c_int, _VP, _VP, _VP]),
             "ssp_dst_device": (S, [_VP, C.c_int, _VP, _VP]),
@@ -270,7 +283,18 @@ def ssp_march(plan, nz, psi0, nsteps, want_field=True, want_tl=True):
     return status, fld, tl, st.as_dict()
 
 
+def _check_batch(st, stats):
+    """A batch's returned status: a failure that belongs to individual plans (their own
+    status in the statistics, e.g. one diverged series) is returned with the other plans'
+    results; any other failure raises."""
+    if st < 0 and not any(x.status == st for x in stats):
+        _check(st)
+    return st
+
+
 def ssp_march_batch(plans, nzs, nsteps, want_field=True, want_tl=True):
+    """Returns (status, fields, tls, stats); per-plan failures (status < 0 in that plan's
+    stats) do not raise."""
     n = len(plans)
     arr = (_VP * n)(*plans)
     fl = [np.zeros((ssp_count_outputs(pl, nsteps), nz), dtype=np.complex128) if want_field else None
@@ -280,7 +304,7 @@ def ssp_march_batch(plans, nzs, nsteps, want_field=True, want_tl=True):
     fptr = (_DP * n)(*[None if f is None else _dp(f.view(np.float64)) for f in fl])
     tptr = (_FP * n)(*[None if t is None else _fp(t) for t in tl])
     stats = (ssp_stats * n)()
-    status = _check(lib().ssp_march_batch(arr, n, int(nsteps), fptr, tptr, stats))
+    status = _check_batch(lib().ssp_march_batch(arr, n, int(nsteps), fptr, tptr, stats), stats)
     return status, fl, tl, [s.as_dict() for s in stats]
 
 
@@ -296,8 +320,34 @@ def ssp_march_batch_steps(plans, nzs, nsteps, want_field=True, want_tl=True):
     fptr = (_DP * n)(*[None if f is None else _dp(f.view(np.float64)) for f in fl])
     tptr = (_FP * n)(*[None if t is None else _fp(t) for t in tl])
     stats = (ssp_stats * n)()
-    status = _check(lib().ssp_march_batch_steps(arr, n, ns, fptr, tptr, stats))
+    status = _check_batch(lib().ssp_march_batch_steps(arr, n, ns, fptr, tptr, stats), stats)
     return status, fl, tl, [s.as_dict() for s in stats]
+
+
+def ssp_march_batch_async(plans, nsteps, d_tl=None):
+    """nsteps: sequence of n ints; d_tl: sequence of n device addresses (0/None: no TL rows)
+    or None."""
+    n = len(plans)
+    arr = (_VP * n)(*plans)
+    ns = (C.c_int * n)(*[int(k) for k in nsteps])
+    tptr = None if d_tl is None else (_FP * n)(*[C.cast(C.c_void_p(a), _FP) if a else None for a in d_tl])
+    return _check(lib().ssp_march_batch_async(arr, n, ns, tptr))
+
+
+def ssp_batch_stats(plans):
+    """(worst status, [stats dict per plan]); per-plan failures do not raise."""
+    n = len(plans)
+    arr = (_VP * n)(*plans)
+    stats = (ssp_stats * n)()
+    st = _check_batch(lib().ssp_batch_stats(arr, n, stats), stats)
+    return st, [s.as_dict() for s in stats]
+
+
+def ssp_plan_contraction(plan, p, iterations=40):
+    """(bound [p], estimate [p]) of every Pade factor's Neumann operator."""
+    b, e = np.zeros(p), np.zeros(p)
+    _check(lib().ssp_plan_contraction(plan, int(iterations), _dp(b), _dp(e)))
+    return b, e
 
 
 def ssp_march_device(plan, B, d_psi, d_step, nsteps, d_tl=0, d_stats=0):

@@ -97,7 +97,7 @@ def test_plain_form_equals_fused_bitwise_with_absorber(ssp, gpu):
     for engine in (0, 1):
         pl = make_plan(ssp, s)
         try:
-            ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_ENGINE, engine)
+            ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_PLAIN, engine)
             ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, 0)
             out.append(ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps))
         finally:

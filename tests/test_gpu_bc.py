@@ -179,7 +179,7 @@ def test_plain_form_equals_fused_bitwise(ssp, gpu, bc):
     for engine in (0, 1):
         pl = make_plan(ssp, s)
         try:
-            ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_ENGINE, engine)
+            ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_PLAIN, engine)
             ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, 0)
             out.append(ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps))
         finally:
@@ -310,7 +310,7 @@ def test_periodic_direct_rejects_the_plain_form(ssp, gpu):
     s = with_bc(W.munk_deep(nsteps=2, nz=1024), "periodic")
     pl = make_plan(ssp, s)
     try:
-        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_ENGINE, 1)
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_PLAIN, 1)
         with pytest.raises(ssp.SspError) as e:
             ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
         assert e.value.status == ssp.SSP_E_UNIMPL

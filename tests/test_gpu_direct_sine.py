@@ -113,7 +113,7 @@ def test_plain_form_rejected(ssp, gpu):
     s = W.munk_deep(nsteps=2, nz=1023)
     pl = make_plan(ssp, s)
     try:
-        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_ENGINE, 1)
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_PLAIN, 1)
         with pytest.raises(ssp.SspError) as e:
             ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
         assert e.value.status == ssp.SSP_E_UNIMPL

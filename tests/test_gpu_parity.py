@@ -410,7 +410,7 @@ def test_plain_form_equals_fused_bitwise(ssp, gpu, nz, env):
     for engine in (0, 1):
         pl = make_plan(ssp, s, profile="analytic" if env != "munk" else "table")
         try:
-            ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_ENGINE, engine)
+            ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_PLAIN, engine)
             ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, 0)  # the plain kernels' layout
             out.append(ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps))
         finally:
@@ -450,7 +450,7 @@ def test_layout_option_and_engine_query(ssp, gpu):
             ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, v)
             seen[v] = ssp.ssp_plan_engine(pl)
         assert seen[0][1] == 1024 and seen[1][1] == 512 and seen[2][1] == 256
-        for bad in (3, -2, 0.5):
+        for bad in (3, -3, 0.5):
             with pytest.raises(ssp.SspError) as e:
                 ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, bad)
             assert e.value.status == ssp.SSP_E_INVAL
@@ -473,7 +473,7 @@ def test_plain_form_reports_divergence(ssp, gpu):
     s.neumann_max = 16
     pl = make_plan(ssp, s)
     try:
-        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_ENGINE, 1)
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_PLAIN, 1)
         with pytest.raises(ssp.SspError) as e:
             ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
         assert e.value.status == ssp.SSP_E_DIVERGED
