@@ -10,7 +10,7 @@ constexpr int kTunedVariant[9] = {0, 0, 0, 0, 1, 2, 2, 2, 0};
 constexpr int kTunedDirect[2][9] = {{0, 0, 0, 0, 1, 0, 1, 2, 0}, {0, 0, 0, 0, 1, 2, 2, 2, 0}};
 // kTunedMixed[log2(P) - 7]: chirp-z layouts for batches that mix FFT lengths
 // (SSP_OPT_VARIANT = -2), measured on a mixed-length batch
-constexpr int kTunedMixed[9] = {0, 0, 0, 0, 1, 0, 1, 2, 0};
+constexpr int kTunedMixed[9] = {0, 0, 0, 0, 1, 1, 1, 2, 0};
 // kTunedEngine[Nz class][p class]: 1 = dense engine, 0 = FFT engine, for SSP_ENGINE_AUTO;
 // Nz classes <= 256, <= 512, <= 1024, <= 2048; p classes <= 4, 5-6, 7-8, >= 9
 constexpr int kTunedEngine[4][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};

@@ -631,3 +631,99 @@ def test_eddy_full_size_long_range_vs_stored_oracle(ssp, gpu):
         field = g["field"]
         tl = transmission_loss(g["field"], g["ranges"])
     compare("eddy long range", fld, tl, Ref)
+
+
+@pytest.mark.timeout(900)
+def test_eddy_full_size_full_range_vs_stored_oracle(ssp, gpu):
+    # Munk + eddy over its whole range: Nz = 16384 (split transforms), [8/8], Neumann <= 12,
+    # 10^4 steps (200 km), potential on the device, against the stored FP64 oracle every
+    # 20 km (tests/golden/make_golden.py eddy16384_full)
+    import os
+    from oracle import transmission_loss
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "eddy16384_full_zs1000.npz"))
+    s = W.munk_eddy(nsteps=int(g["nsteps"]))
+    s.out_every = int(g["out_every"])
+    pl = make_plan(ssp, s, profile="analytic")
+    fields, tls, stats_all = [], [], []
+    try:
+        ssp.ssp_set_field(pl, s.starter(), s.nz)
+        chunk = 1000
+        for n0 in range(0, s.nsteps, chunk):
+            st, fld, tl, stats = ssp.ssp_march(pl, s.nz, None, chunk)
+            assert st in (OK, NOT_CONVERGED) and stats["steps_done"] == chunk
+            fields.append(fld)
+            tls.append(tl)
+            stats_all.append(stats)
+            print(f"[eddy full range] step {n0 + chunk}: terms {stats['neumann_terms']}", flush=True)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    fld = np.concatenate(fields)
+    terms = sum(x["neumann_terms"] for x in stats_all)
+    nc = sum(x["not_converged"] for x in stats_all)
+    _report("eddy full range", oracle_status=int(g["status"]), terms=terms,
+            oracle_terms=int(np.sum(g["iterations"])), not_converged=nc,
+            oracle_not_converged=int(g["not_converged"]))
+    ref_field = g["field"].astype(np.complex128)
+
+    class Ref:
+        field = ref_field
+        tl = transmission_loss(ref_field, g["ranges"])
+    err = np.linalg.norm(fld - Ref.field, axis=1) / np.linalg.norm(Ref.field, axis=1)
+    for r, e in zip(g["ranges"], err):
+        print(f"[eddy full range] r = {r / 1000:.0f} km relL2 {e:.3e}", flush=True)
+    compare("eddy full range", fld, np.concatenate(tls), Ref)
+
+
+BROADBAND_GOLDEN = (0, 20, 28, 64, 106, 107, 180, 255)
+
+
+@pytest.mark.timeout(900)
+def test_broadband_full_batch_full_range_vs_stored_oracle(ssp, gpu):
+    # all 256 frequencies of the broadband set in one batch (FFT lengths 8192, 16384 and
+    # 32768, the mixed-batch layouts) over the full 2000 steps (50 km); the sampled
+    # frequencies against the stored FP64 oracle at 25 and 50 km
+    # (tests/golden/make_golden.py broadband): the per-frequency error table
+    import os
+    from oracle import transmission_loss
+    solves = W.broadband()
+    gold = {i: np.load(os.path.join(os.path.dirname(__file__), "golden", f"broadband_f{i:03d}.npz"))
+            for i in BROADBAND_GOLDEN}
+    plans = []
+    try:
+        for i, s in enumerate(solves):
+            s.out_every = 1000
+            pl = make_plan(ssp, s)
+            ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, -2)
+            ssp.ssp_set_field(pl, s.starter(), s.nz)
+            plans.append(pl)
+        rows = {i: [] for i in gold}
+        terms = {i: 0 for i in gold}
+        chunk = 200
+        for n0 in range(0, 2000, chunk):
+            st, fl, tl, stats = ssp.ssp_march_batch(plans, [s.nz for s in solves], chunk)
+            assert st in (OK, NOT_CONVERGED)
+            for i in gold:
+                if fl[i].shape[0]:
+                    rows[i].append(fl[i])
+                terms[i] += stats[i]["neumann_terms"]
+            assert all(x["steps_done"] == chunk for x in stats)
+    finally:
+        for pl in plans:
+            ssp.ssp_plan_destroy(pl)
+    worst = 0.0
+    for i, g in gold.items():
+        s = solves[i]
+        fld = np.concatenate(rows[i])
+        ref = g["field"].astype(np.complex128)
+        assert fld.shape == ref.shape
+        err = np.linalg.norm(fld - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        tl_ref = transmission_loss(ref, g["ranges"])
+        tl_got = transmission_loss(fld, g["ranges"])
+        mask = tl_ref < 120.0
+        dtl = np.abs(tl_got - tl_ref)[mask]
+        print(f"[broadband per frequency] f = {s.freq:7.3f} Hz  Nz = {s.nz:5d}  relL2(25 km) = {err[0]:.2e}  "
+              f"relL2(50 km) = {err[1]:.2e}  max dTL = {dtl.max():.3f} dB  terms {terms[i]} "
+              f"(oracle {int(np.sum(g['iterations']))})", flush=True)
+        worst = max(worst, err.max())
+        assert err.max() <= REL_L2 and dtl.max() <= DTL
+    _report("broadband full range", worst_relL2=f"{worst:.3e}")
