@@ -640,7 +640,10 @@ def test_eddy_full_size_full_range_vs_stored_oracle(ssp, gpu):
     # 20 km (tests/golden/make_golden.py eddy16384_full)
     import os
     from oracle import transmission_loss
-    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "eddy16384_full_zs1000.npz"))
+    path = os.path.join(os.path.dirname(__file__), "golden", "eddy16384_full_zs1000.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle field missing: python tests/golden/make_golden.py eddy16384_full")
+    g = np.load(path)
     s = W.munk_eddy(nsteps=int(g["nsteps"]))
     s.out_every = int(g["out_every"])
     pl = make_plan(ssp, s, profile="analytic")
@@ -686,8 +689,11 @@ def test_broadband_full_batch_full_range_vs_stored_oracle(ssp, gpu):
     import os
     from oracle import transmission_loss
     solves = W.broadband()
-    gold = {i: np.load(os.path.join(os.path.dirname(__file__), "golden", f"broadband_f{i:03d}.npz"))
-            for i in BROADBAND_GOLDEN}
+    paths = {i: os.path.join(os.path.dirname(__file__), "golden", f"broadband_f{i:03d}.npz") for i in BROADBAND_GOLDEN}
+    missing = [i for i, q in paths.items() if not os.path.exists(q)]
+    if missing:
+        pytest.skip(f"stored oracle fields missing: python tests/golden/make_golden.py broadband {missing}")
+    gold = {i: np.load(q) for i, q in paths.items()}
     plans = []
     try:
         for i, s in enumerate(solves):
