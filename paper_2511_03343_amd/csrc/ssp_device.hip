@@ -25,8 +25,12 @@
 // Pade factors are applied in product form u <- g_j u + (1 - g_j) w_j (the same
 // approximant as the paper's sum form; better conditioned in FP32).
 //
-// One workgroup owns one solve for a whole launch: its field, all Pade factors and all
-// Neumann terms of every step stay on chip (registers + LDS).  Precision: complex FP32
+// One workgroup owns one solve for a whole launch: the Neumann series of every Pade factor
+// runs on chip (transforms in registers + LDS); the state between factors stays in
+// registers where the layout has room, else in the solve's work array, and the field is
+// written once per step (the recovery point if the next step diverges).  Tables the
+// kernels read every term (multipliers, potential, chirp spectra) come from L2 where they
+// do not fit the registers.  Precision: complex FP32
 // data; FFT twiddles and the sine-space multipliers are double-float (hi + lo) products so
 // that no fixed rounding of a table enters every step; residual norms in FP64; carrier
 // phase in FP64.
@@ -843,6 +847,13 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     // threads (else in d.wacc)
     constexpr bool kWInRegs = T < 1024 || RT <= 8;
     constexpr int EW = kWInRegs ? RL : 1;
+    // the state between Pade factors stays in registers where the layout has room (one load
+    // and one store of the field per step); otherwise it goes through the solve's work
+    // array (a load and a store per factor).  Room: up to 8 live elements per thread below
+    // 1024 threads, or the 128-thread layout (16 elements; 252 registers, no spills); the
+    // other 16-element layouts would spill
+    constexpr bool kUInRegs = (T < 1024) && (RL <= 8 || T <= 128);
+    constexpr int EU = kUInRegs ? RL : 1;
     // split transforms keep their second input in the solve's scratch (fewer spills)
     constexpr bool kKeepGlobal = true;
     const LdsBufs L = carve_lds<EK>(lds_raw);
@@ -855,7 +866,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     // step (the recovery point if the step diverges) and d.work the state between Pade
     // factors.  Every thread reads and writes only its own positions, so these global
     // accesses need no barriers.
-    float2 w[EW], a[RT], A[EA];
+    float2 w[EW], a[RT], A[EA], u[EU];
     float4 Bm[EB];
     long long n = *d.step;
     // outputs of this launch: steps out_base, out_base + out_every, ... (row = slot)
@@ -873,6 +884,13 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
             break;
         }
         if (d.prof_mode != PROF_TABLE_FIXED) load_potential<P, V, kAInRegs, DK>(d, nn, A);
+        if constexpr (kUInRegs) {
+#pragma unroll
+            for (int i = 0; i < RL; ++i) {
+                const int pos = opaque_tid() + i * T;
+                u[i] = pos < N ? ld2(d.field, pos) : make_float2(0.f, 0.f);
+            }
+        }
         bool bad = false;
         for (int j = 0; j < p; ++j) {
             const float2 *cur = (j == 0) ? d.field : d.work;
@@ -885,7 +903,10 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
             for (int i = 0; i < RL; ++i) {
                 const int pos = opaque_tid() + i * T, m = pos;
                 if (pos < N) {
-                    a[i] = cmul_df(ld2(cur, m), ld4(d.s, j * N + m));
+                    float2 uc;
+                    if constexpr (kUInRegs) uc = u[i];
+                    else uc = ld2(cur, m);
+                    a[i] = cmul_df(uc, ld4(d.s, j * N + m));
                     if constexpr (kBInRegs) Bm[i] = ld4(d.bmul, j * N + m);
                 } else {
                     a[i] = make_float2(0.f, 0.f);
@@ -973,7 +994,8 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                 const int pos = opaque_tid() + i * T, m = pos;
                 if (pos < N) {
                     const float2 ws = kWInRegs ? w[i] : ld2(d.wacc, m);
-                    st2(d.work, m, cadd(cmul_df(ld2(cur, m), al), cmul_df(ws, be)));
+                    if constexpr (kUInRegs) u[i] = cadd(cmul_df(u[i], al), cmul_df(ws, be));
+                    else st2(d.work, m, cadd(cmul_df(ld2(cur, m), al), cmul_df(ws, be)));
                 }
             }
         }
@@ -981,11 +1003,15 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
             status = kDiverged;
             break;
         }
-        // commit the step
+        // commit the step (until here the field held the step-start state: the recovery point)
 #pragma unroll
         for (int i = 0; i < RL; ++i) {
             const int pos = opaque_tid() + i * T, m = pos;
-            if (pos < N) st2(d.field, m, ld2(d.work, m));
+            if constexpr (kUInRegs) {
+                if (pos < N) st2(d.field, m, u[i]);
+            } else {
+                if (pos < N) st2(d.field, m, ld2(d.work, m));
+            }
         }
         n = nn;
         ++done;
@@ -997,7 +1023,11 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
 #pragma unroll
                 for (int i = 0; i < RL; ++i) {
                     const int pos = opaque_tid() + i * T, m = pos;
-                    if (pos < N) st2(d.snap + slot * N, m, ld2(d.field, m));
+                    if constexpr (kUInRegs) {
+                        if (pos < N) st2(d.snap + slot * N, m, u[i]);
+                    } else {
+                        if (pos < N) st2(d.snap + slot * N, m, ld2(d.field, m));
+                    }
                 }
             }
         }
