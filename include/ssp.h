@@ -316,6 +316,23 @@ ssp_status ssp_batch_stats(ssp_plan *const *plans, int n, ssp_stats *stats);
  * statistics.  Dense-engine plans run without graph recording. */
 ssp_status ssp_march_device(ssp_plan *plan, int B, void *d_psi, void *d_step, int nsteps,
                             void *d_tl, void *d_stats);
+/* ssp_march_device for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same arguments,
+ * kernels and results (bitwise), with every scratch array (descriptors, per-solve state
+ * between Pade factors, statistics when d_stats is NULL, output snapshots) carved from one
+ * fixed device array of SSP_NOALLOC_SCRATCH_MIB MiB that the library holds on each device
+ * it runs on until the process ends.  The call allocates nothing, copies nothing from the
+ * host (the descriptors are written by a kernel) and is asynchronous on the plan's stream.
+ * A batch whose scratch exceeds the array (about 5 Nz B complex values plus Nz B
+ * (nsteps/out_every + 1) for TL outputs) is rejected with SSP_E_INVAL; dense-engine plans
+ * with SSP_E_UNIMPL.  Every call on a device shares that device's array, which keeps the
+ * last call's contents: calls that overlap in time on one device (other streams, other
+ * threads) race and must be serialised by the caller.  The statistics kept in the array
+ * when d_stats is NULL are not readable by the caller. */
+#define SSP_NOALLOC_SCRATCH_MIB 64
+ssp_status ssp_march_device_noalloc(ssp_plan *plan, int B, void *d_psi, void *d_step, int nsteps,
+                                    void *d_tl, void *d_stats);
+
 /* physical complex64 [B][Nz] (device) -> sine-basis representation (device), in place ok */
 ssp_status ssp_to_sine(ssp_plan *plan, int B, const void *d_phys, void *d_sine);
 /* sine-basis representation -> physical field with carrier at the given step counters */

@@ -1441,7 +1441,94 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
 
 }  // extern "C"
 
+// ------------------------------------------------------------- no-allocation device march
+// Scratch of ssp_march_device_noalloc: one array per device, held until the process ends.
+// Host code never passes `scratch` itself to a kernel (its host-side name is not a device
+// address); it passes the address hipGetSymbolAddress returns for the current device.
+namespace {
+constexpr size_t kNoAllocScratchBytes = static_cast<size_t>(SSP_NOALLOC_SCRATCH_MIB) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+ssp_status noalloc_scratch(unsigned char **out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static unsigned char *ptr[kMaxDevices] = {};
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SSP_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *addr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)));
+        if (!addr) return fail(SSP_E_DEVICE, "no device address for the scratch array");
+        ptr[dev] = static_cast<unsigned char *>(addr);
+    }
+    *out = ptr[dev];
+    return SSP_OK;
+}
+
+constexpr size_t round256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
+
+// The descriptors of a device batch, written on the device from the plan's template (the
+// same values device_descs builds on the host): no host buffer, no host-to-device copy.
+__global__ void k_fill_descs(ssp::SolveDesc tmpl, int B, float2 *psi, long long *step, float *tl,
+                             ssp::DevStats *stats, float2 *work, float2 *snap, ssp::SolveDesc *out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const size_t N = static_cast<size_t>(tmpl.N), bb = static_cast<size_t>(b);
+    ssp::SolveDesc d = tmpl;
+    d.field = psi + bb * N;
+    d.work = work + ssp::kWorkPerSolve * bb * N;
+    d.pot = d.work + N;
+    d.wacc = d.work + 2 * N;
+    d.xs = d.work + 3 * N;
+    d.step = step + b;
+    d.stats = stats + b;
+    d.fld_out = nullptr;
+    d.tl_out = tl ? tl + bb * tmpl.nout * N : nullptr;
+    d.snap = tl ? snap + bb * tmpl.nout * N : nullptr;
+    out[b] = d;
+}
+}  // namespace
+
 extern "C" {
+
+ssp_status ssp_march_device_noalloc(ssp_plan *pl, int B, void *d_psi, void *d_step, int nsteps, void *d_tl,
+                                    void *d_stats) {
+    if (!pl || B <= 0 || !d_psi || !d_step || nsteps < 0) return fail(SSP_E_INVAL, "bad argument");
+    if (effective_engine(pl) != SSP_ENGINE_FFT)
+        return fail(SSP_E_UNIMPL, "the no-allocation march runs the FFT engine (set SSP_OPT_ENGINE to SSP_ENGINE_FFT)");
+    const int nout = pl->out_every > 0 ? nsteps / pl->out_every + 1 : 0;
+    const bool outputs = d_tl && nout > 0;
+    // scratch layout: descriptors, per-solve work, statistics (when the caller passes none),
+    // output snapshots
+    const size_t desc_bytes = round256(sizeof(ssp::SolveDesc) * static_cast<size_t>(B));
+    const size_t work_bytes = round256(sizeof(float2) * ssp::kWorkPerSolve * static_cast<size_t>(B) * pl->N);
+    const size_t stats_bytes = d_stats ? 0 : round256(sizeof(ssp::DevStats) * static_cast<size_t>(B));
+    const size_t snap_bytes = outputs ? round256(sizeof(float2) * static_cast<size_t>(B) * nout * pl->N) : 0;
+    const size_t need = desc_bytes + work_bytes + stats_bytes + snap_bytes;
+    if (need > kNoAllocScratchBytes)
+        return fail(SSP_E_INVAL, "batch needs more scratch than the fixed " +
+                                     std::to_string(SSP_NOALLOC_SCRATCH_MIB) + " MiB of the no-allocation march");
+    unsigned char *base = nullptr;
+    ssp_status st = noalloc_scratch(&base);
+    if (st != SSP_OK) return st;
+    auto *d_descs = reinterpret_cast<ssp::SolveDesc *>(base);
+    auto *work = reinterpret_cast<float2 *>(base + desc_bytes);
+    auto *stats = reinterpret_cast<ssp::DevStats *>(base + desc_bytes + work_bytes);
+    auto *snap = reinterpret_cast<float2 *>(base + desc_bytes + work_bytes + stats_bytes);
+    ssp::SolveDesc tmpl = base_desc(pl);
+    tmpl.nout = nout;
+    tmpl.nsteps = nsteps;
+    hipLaunchKernelGGL(k_fill_descs, dim3((B + 255) / 256), dim3(256), 0, pl->stream, tmpl, B,
+                       static_cast<float2 *>(d_psi), static_cast<long long *>(d_step),
+                       outputs ? static_cast<float *>(d_tl) : nullptr,
+                       d_stats ? static_cast<ssp::DevStats *>(d_stats) : stats, work, snap, d_descs);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(ssp::launch_march(pl->P, effective_variant(pl), pl->tab.direct, d_descs, B, nsteps, pl->stream));
+    if (outputs) HIP_TRY(ssp::launch_output(pl->P, pl->tab.direct, d_descs, B, nout, pl->stream));
+    return SSP_OK;
+}
 
 ssp_status ssp_to_sine(ssp_plan *pl, int B, const void *d_phys, void *d_sine) {
     if (!pl || B <= 0 || !d_phys || !d_sine) return fail(SSP_E_INVAL, "bad argument");

@@ -115,6 +115,7 @@ def lib() -> C.CDLL:
             "ssp_march_batch_steps": (S, [C.POINTER(_VP), C.c_int, C.POINTER(C.c_int), C.POINTER(_DP),
                                           C.POINTER(_FP), C.POINTER(ssp_stats)]),
             "ssp_march_device": (S, [_VP, C.c_int, _VP, _VP, C.c_int, _VP, _VP]),
+            "ssp_march_device_noalloc": (S, [_VP, C.c_int, _VP, _VP, C.c_int, _VP, _VP]),
             "ssp_march_batch_async": (S, [C.POINTER(_VP), C.c_int, C.POINTER(C.c_int), C.POINTER(_FP)]),
             "ssp_batch_stats": (S, [C.POINTER(_VP), C.c_int, C.POINTER(ssp_stats)]),
             "ssp_plan_contraction": (S, [_VP, C.c_int, _DP, _DP]),
@@ -353,6 +354,11 @@ def ssp_plan_contraction(plan, p, iterations=40):
 def ssp_march_device(plan, B, d_psi, d_step, nsteps, d_tl=0, d_stats=0):
     return _check(lib().ssp_march_device(plan, int(B), d_psi, d_step, int(nsteps), d_tl or None,
                                          d_stats or None))
+
+
+def ssp_march_device_noalloc(plan, B, d_psi, d_step, nsteps, d_tl=0, d_stats=0):
+    return _check(lib().ssp_march_device_noalloc(plan, int(B), d_psi, d_step, int(nsteps), d_tl or None,
+                                                 d_stats or None))
 
 
 def ssp_to_sine(plan, B, d_phys, d_sine):
