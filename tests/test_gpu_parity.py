@@ -345,9 +345,10 @@ def test_batch_equals_alone_bitwise(ssp, gpu):
         assert np.array_equal(a, b)
 
 
-def test_uneven_lengths_one_launch_equal_alone_bitwise(ssp, gpu):
-    # FFT lengths 8192, 16384 and 32768 (broadband frequencies) share one launch; each solve
-    # must give exactly what it gives alone
+def test_uneven_lengths_one_batch_equal_alone_bitwise(ssp, gpu):
+    # FFT lengths 8192, 16384 and 32768 (broadband frequencies) in one batched call (their
+    # launch groups run concurrently; the graph-recorded form of the same batch is checked
+    # in test_gpu_batch.py); each solve must give exactly what it gives alone
     solves = []
     for nz, f in [(3000, 56.25), (6000, 112.5), (12000, 225.0), (16000, 300.0)]:
         s = W.munk_deep(nsteps=6, nz=nz)
