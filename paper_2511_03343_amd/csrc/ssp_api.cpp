@@ -78,7 +78,7 @@ struct ssp_plan {
     float4 *d_mirror = nullptr;         // odd-extension image factors (direct sine transform)
     const float4 *d_twl = nullptr;      // shared last-pass twiddles of 1024-thread engines (not owned)
     uint32_t *d_tw = nullptr;
-    float4 *d_s = nullptr, *d_bmul = nullptr, *d_alpha = nullptr, *d_beta = nullptr;
+    float4 *d_s = nullptr, *d_bmul = nullptr, *d_qmul = nullptr, *d_beta = nullptr;
     float4 *d_twist = nullptr;
     // environment
     int prof_mode = ssp::PROF_TABLE_FIXED, v_rows = 0;
@@ -254,7 +254,7 @@ void free_tables(ssp_plan *pl) {
     dev_free(pl->d_tw);
     dev_free(pl->d_s);
     dev_free(pl->d_bmul);
-    dev_free(pl->d_alpha);
+    dev_free(pl->d_qmul);
     dev_free(pl->d_beta);
     dev_free(pl->d_twist);
     dev_free(pl->d_tmul);
@@ -287,7 +287,7 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     HIP_TRY(dev_alloc(&pl->d_pre, N));
     HIP_TRY(dev_alloc(&pl->d_s, static_cast<size_t>(p) * N));
     HIP_TRY(dev_alloc(&pl->d_bmul, static_cast<size_t>(p) * N));
-    HIP_TRY(dev_alloc(&pl->d_alpha, p));
+    HIP_TRY(dev_alloc(&pl->d_qmul, static_cast<size_t>(p) * N));
     HIP_TRY(dev_alloc(&pl->d_beta, p));
     HIP_TRY(dev_alloc(&pl->d_twist, tab.twist.size() / 4));
     HIP_TRY(dev_alloc(&pl->d_k1i, tab.k1i.size() / 2));
@@ -307,7 +307,7 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     HIP_TRY(upload(pl->d_pre, tab.pre));
     HIP_TRY(upload(pl->d_s, tab.s));
     HIP_TRY(upload(pl->d_bmul, tab.bmul));
-    HIP_TRY(upload(pl->d_alpha, tab.alpha));
+    HIP_TRY(upload(pl->d_qmul, tab.qmul));
     HIP_TRY(upload(pl->d_beta, tab.beta));
     if (!tab.twist.empty()) HIP_TRY(upload(pl->d_twist, tab.twist));
     HIP_TRY(dev_alloc(&pl->d_tmul, tab.tmul.size() / 4));
@@ -339,10 +339,8 @@ int effective_variant(const ssp_plan *pl) {
 
 ssp::SolveDesc base_desc(const ssp_plan *pl) {
     ssp::SolveDesc d{};
-    d.k1 = pl->d_k1;
-    d.k2 = pl->d_k2;
-    d.k1i = pl->d_k1i ? pl->d_k1i : pl->d_k1;
-    d.k2i = pl->d_k2i ? pl->d_k2i : pl->d_k2;
+    d.kf = ssp::KWin{pl->d_k1, pl->d_k2};
+    d.ki = ssp::KWin{pl->d_k1i ? pl->d_k1i : pl->d_k1, pl->d_k2i ? pl->d_k2i : pl->d_k2};
     d.tw = pl->d_tw;
     d.twl = pl->d_twl;
     d.dmod = pl->d_dmod;
@@ -351,7 +349,7 @@ ssp::SolveDesc base_desc(const ssp_plan *pl) {
     d.postf = pl->d_postf ? pl->d_postf : pl->d_post;
     d.s = pl->d_s;
     d.bmul = pl->d_bmul;
-    d.alpha = pl->d_alpha;
+    d.qmul = pl->d_qmul;
     d.beta = pl->d_beta;
     d.twist = pl->d_twist;
     d.N = pl->N;
@@ -1482,6 +1480,7 @@ __global__ void k_fill_descs(ssp::SolveDesc tmpl, int B, float2 *psi, long long 
     d.pot = d.work + N;
     d.wacc = d.work + 2 * N;
     d.xs = d.work + 3 * N;
+    d.a0 = d.work + 5 * N;
     d.step = step + b;
     d.stats = stats + b;
     d.fld_out = nullptr;

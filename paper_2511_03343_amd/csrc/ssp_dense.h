@@ -44,7 +44,9 @@ struct DenseCol {
 
 // Device scratch of a dense-engine launch of B solves of grid size n.
 struct DenseWork {
-    float2 *U, *U0, *W, *G, *V;  // [B][n]: state, step-start state, series sum, product, potential
+    float2 *U, *U0, *W, *G, *V;  // [B][n]: state, step-start state, series sum beyond the first
+                                 // term, product, potential
+    float2 *A0;                  // [B][n]: first series term
     _Float16 *xh, *xl;           // [2B][kpad] operand planes
     int *expo;                   // [2B] operand column exponents
     DenseCol *cols;              // [B]

@@ -193,11 +193,11 @@ __global__ __launch_bounds__(kCT) void k_dm_step_begin(const SolveDesc *__restri
     }
 }
 
-// start of Pade factor j: a_0 = s_j (.) u, w = a_0, its norm; the operand of the first
-// product (zero planes where no series runs)
+// start of Pade factor j: a_0 = s_j (.) u (kept in A0), its norm, the sum of the later terms
+// w' = 0; the operand of the first product (zero planes where no series runs)
 __global__ __launch_bounds__(kCT) void k_dm_factor_begin(const SolveDesc *__restrict__ descs, DenseCol *cols,
-                                                        const float2 *U, float2 *W, _Float16 *xh, _Float16 *xl,
-                                                        int *expo, int kpad, int *active, int j) {
+                                                        const float2 *U, float2 *W, float2 *A0, _Float16 *xh,
+                                                        _Float16 *xl, int *expo, int kpad, int *active, int j) {
     __shared__ double red[2 * (kCT / 64)];
     __shared__ float redf[2 * (kCT / 64)];
     const int b = blockIdx.x;
@@ -210,14 +210,15 @@ __global__ __launch_bounds__(kCT) void k_dm_factor_begin(const SolveDesc *__rest
     for (int i = 0; i < kPer; ++i) a[i] = make_float2(0.f, 0.f);
     if (run) {
         const float2 *u = U + static_cast<size_t>(b) * n;
-        float2 *w = W + static_cast<size_t>(b) * n;
+        float2 *w = W + static_cast<size_t>(b) * n, *a0 = A0 + static_cast<size_t>(b) * n;
         float part = 0.f;
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int k = threadIdx.x + i * kCT;
             if (k < n) {
                 a[i] = cmul_df(u[k], d.s[static_cast<size_t>(j) * n + k]);
-                w[k] = a[i];
+                a0[k] = a[i];
+                w[k] = make_float2(0.f, 0.f);
                 part += cnorm2(a[i]);
             }
         }
@@ -260,8 +261,8 @@ __global__ __launch_bounds__(kCT) void k_dm_grid(const SolveDesc *__restrict__ d
 // after the product back into the sine basis: term m = t_j (.) S y, the series sum, the
 // residual and the stopping rule; the operand of the next term (zero planes once stopped)
 __global__ __launch_bounds__(kCT) void k_dm_sine(const SolveDesc *__restrict__ descs, DenseCol *cols,
-                                                const float2 *G, float2 *W, _Float16 *xh, _Float16 *xl, int *expo,
-                                                int kpad, int *active, int j, int m) {
+                                                const float2 *G, float2 *W, const float2 *A0, _Float16 *xh,
+                                                _Float16 *xl, int *expo, int kpad, int *active, int j, int m) {
     __shared__ double red[2 * (kCT / 64)];
     __shared__ float redf[2 * (kCT / 64)];
     const int b = blockIdx.x;
@@ -271,6 +272,7 @@ __global__ __launch_bounds__(kCT) void k_dm_sine(const SolveDesc *__restrict__ d
     const int n = d.N;
     const float2 *g = G + static_cast<size_t>(b) * n;
     float2 *w = W + static_cast<size_t>(b) * n;
+    const float2 *a0 = A0 + static_cast<size_t>(b) * n;
     float2 a[kPer];
     float tnf = 0.f, wnf = 0.f;
 #pragma unroll
@@ -279,10 +281,10 @@ __global__ __launch_bounds__(kCT) void k_dm_sine(const SolveDesc *__restrict__ d
         a[i] = make_float2(0.f, 0.f);
         if (k < n) {
             a[i] = cmul_df(g[k], d.tmul[static_cast<size_t>(j) * n + k]);
-            const float2 ws = cadd(w[k], a[i]);
+            const float2 ws = cadd(w[k], a[i]);  // w' (the norm is that of w = a0 + w')
             w[k] = ws;
             tnf += cnorm2(a[i]);
-            wnf += cnorm2(ws);
+            wnf += cnorm2(cadd(a0[k], ws));
         }
     }
     double tn = tnf, wn = wnf;
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(kCT) void k_dm_sine(const SolveDesc *__restrict__ d
 }
 
 // end of Pade factor j: divergence (back to the step-start state, the solve stops) or
-// statistics and the product-form update u <- g_j u + (1 - g_j) w
+// statistics and the product-form update as the increment u <- u + (q_j u + beta_j w')
 __global__ __launch_bounds__(kCT) void k_dm_factor_end(const SolveDesc *__restrict__ descs, DenseCol *cols,
                                                       float2 *U, const float2 *U0, const float2 *W, int j) {
     const int b = blockIdx.x;
@@ -334,9 +336,10 @@ __global__ __launch_bounds__(kCT) void k_dm_factor_end(const SolveDesc *__restri
         }
         return;
     }
-    const float4 al = d.alpha[j], be = d.beta[j];
+    const float4 be = d.beta[j];
     const float2 *w = W + static_cast<size_t>(b) * n;
-    for (int k = threadIdx.x; k < n; k += kCT) u[k] = cadd(cmul_df(u[k], al), cmul_df(w[k], be));
+    const float4 *q = d.qmul + static_cast<size_t>(j) * n;
+    for (int k = threadIdx.x; k < n; k += kCT) u[k] = cadd(u[k], cadd(cmul_df(u[k], q[k]), cmul_df(w[k], be)));
     if (threadIdx.x == 0) {
         c.terms += c.used;
         c.max_used = c.used > c.max_used ? c.used : c.max_used;
@@ -405,7 +408,7 @@ constexpr size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(25
 // complex; xh, xl [2B][kpad] fp16; expo [2B]; cols [B]; the active-series counter.
 size_t dense_work_bytes(int B, int n) {
     const size_t kpad = (static_cast<size_t>(n) + 127) / 128 * 128, bb = static_cast<size_t>(B);
-    return 5 * align256(sizeof(float2) * bb * n) + 2 * align256(sizeof(_Float16) * 2 * bb * kpad) +
+    return 6 * align256(sizeof(float2) * bb * n) + 2 * align256(sizeof(_Float16) * 2 * bb * kpad) +
            align256(sizeof(int) * 2 * bb) + align256(sizeof(DenseCol) * bb) + 256;
 }
 
@@ -423,6 +426,7 @@ DenseWork carve_dense_work(void *base, int B, int n) {
     w.W = reinterpret_cast<float2 *>(take(sizeof(float2) * bb * n));
     w.G = reinterpret_cast<float2 *>(take(sizeof(float2) * bb * n));
     w.V = reinterpret_cast<float2 *>(take(sizeof(float2) * bb * n));
+    w.A0 = reinterpret_cast<float2 *>(take(sizeof(float2) * bb * n));
     w.xh = reinterpret_cast<_Float16 *>(take(sizeof(_Float16) * 2 * bb * kpad));
     w.xl = reinterpret_cast<_Float16 *>(take(sizeof(_Float16) * 2 * bb * kpad));
     w.expo = reinterpret_cast<int *>(take(sizeof(int) * 2 * bb));
@@ -448,8 +452,8 @@ hipError_t dense_march(const DenseTables &t, const SolveDesc *d_descs, int B, in
     for (int s = 0; s < nsteps; ++s) {
         DM_LAUNCH(k_dm_step_begin, dim3(B), dim3(kCT), 0, stream, d_descs, w.cols, w.U, w.U0, w.V, s);
         for (int j = 0; j < pmax; ++j) {
-            DM_LAUNCH(k_dm_factor_begin, dim3(B), dim3(kCT), 0, stream, d_descs, w.cols, w.U, w.W, w.xh, w.xl,
-                      w.expo, kpad, w.active, j);
+            DM_LAUNCH(k_dm_factor_begin, dim3(B), dim3(kCT), 0, stream, d_descs, w.cols, w.U, w.W, w.A0, w.xh,
+                      w.xl, w.expo, kpad, w.active, j);
             for (int m = 1; m <= nmax_max; ++m) {
                 e = launch_dense_gemm_only(t, B, w.xh, w.xl, w.expo, w.G, stream);
                 if (e != hipSuccess) return e;
@@ -457,8 +461,8 @@ hipError_t dense_march(const DenseTables &t, const SolveDesc *d_descs, int B, in
                           kpad);
                 e = launch_dense_gemm_only(t, B, w.xh, w.xl, w.expo, w.G, stream);
                 if (e != hipSuccess) return e;
-                DM_LAUNCH(k_dm_sine, dim3(B), dim3(kCT), 0, stream, d_descs, w.cols, w.G, w.W, w.xh, w.xl, w.expo,
-                          kpad, w.active, j, m);
+                DM_LAUNCH(k_dm_sine, dim3(B), dim3(kCT), 0, stream, d_descs, w.cols, w.G, w.W, w.A0, w.xh, w.xl,
+                          w.expo, kpad, w.active, j, m);
                 if (m % kPoll == 0 && m < nmax_max) {
                     e = hipMemcpyAsync(h_active, w.active, sizeof(int), hipMemcpyDeviceToHost, stream);
                     if (e == hipSuccess) e = hipStreamSynchronize(stream);

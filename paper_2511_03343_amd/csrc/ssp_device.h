@@ -22,10 +22,15 @@ enum ProfileMode : int { PROF_TABLE_FIXED = 0, PROF_TABLE_STEPS = 1, PROF_ANALYT
 
 // Everything one workgroup needs to march one solve.  Table pointers are shared by all
 // solves of a plan; state pointers are per solve.
+// The two chirp-window spectra K1, K2 of one transform direction ([P] complex FP32 each).
+struct KWin {
+    const float2 *k1, *k2;
+};
+
 struct SolveDesc {
-    const float2 *k1, *k2;      // [P] chirp-window spectra, forward direction (grid -> basis)
-    const float2 *k1i, *k2i;    // [P] the same for the inverse direction (== k1, k2 for the
-                                //     sine and cosine transforms, their own inverses)
+    KWin kf;                    // [P] chirp-window spectra, forward direction (grid -> basis)
+    KWin ki;                    // [P] the same for the inverse direction (== kf for the sine
+                                //     and cosine transforms, their own inverses)
     const uint32_t *tw;         // first-octant twiddle table (see DeviceTables::twiddle)
     const float4 *twl;          // last-pass twiddles of the split-transform engine,
                                 //     [RT-1][1024] (see last_twiddles), else null
@@ -33,7 +38,8 @@ struct SolveDesc {
     const float2 *pre;          // [N] forward pre-modulation (grid values -> chirp-z input)
     const float2 *postf;        // [N] forward post-modulation (stand-alone transform)
     const float4 *s, *bmul;     // [p][N] double-float
-    const float4 *alpha, *beta; // [p] double-float
+    const float4 *qmul;         // [p][N] double-float q_j = C_j r_j - 1 (see DeviceTables::qmul)
+    const float4 *beta;         // [p] double-float C_j (1 - g_j)
     const float4 *twist;        // [P/2] double-float w_P^n (split transforms, P > 16384), else null
     int N, P, p, nmax;
     double tol2;                // tol^2 (squared-norm test)
@@ -48,8 +54,10 @@ struct SolveDesc {
     float2 *field;              // [N] sine-basis state (modulated representation)
     float2 *work;               // [N] scratch state between Pade factors
     float2 *pot;                // [N] scratch potential A = v (.) dmod of the current step
-    float2 *wacc;               // [N] scratch Neumann partial sum (kernels that do not hold it in registers)
+    float2 *wacc;               // [N] scratch Neumann sum beyond the first term (kernels that do
+                                //     not hold it in registers)
     float2 *xs;                 // [2N] scratch of split transforms
+    float2 *a0;                 // [N] scratch first series term (kernels that do not hold it in registers)
     long long *step;            // global step counter
     DevStats *stats;
     float2 *snap;               // [nout][N] sine-basis snapshots at output steps, or null
@@ -77,13 +85,14 @@ constexpr int kStatusProfileRange = -1;
 // launch).  direct: the plans' direct transform kind (0: chirp-z cores; 1: periodic grid of
 // length P, FFTs; 2: Dirichlet grid of length P/2 - 1, the FFT of the odd extension;
 // P <= 16384 for both).  Returns hipSuccess or the launch error.
-// Scratch elements (complex) per solve behind SolveDesc::work: work, pot, wacc, xs.
-constexpr int kWorkPerSolve = 5;
+// Scratch elements (complex) per solve behind SolveDesc::work: work, pot, wacc, xs (2N), a0.
+constexpr int kWorkPerSolve = 6;
 inline void set_work(SolveDesc &d, float2 *base) {
     d.work = base;
     d.pot = base + d.N;
     d.wacc = base + 2 * static_cast<size_t>(d.N);
     d.xs = base + 3 * static_cast<size_t>(d.N);
+    d.a0 = base + 5 * static_cast<size_t>(d.N);
 }
 
 hipError_t launch_march(int P, int variant, int direct, const SolveDesc *d_descs, int nsolves, int nsteps,

@@ -23,7 +23,13 @@
 //   Neumann term m:   a_m = B_j (.) IFFT(comb(FFT( A (.) IFFT(comb(FFT(a_{m-1}))) )))
 // with A = v (.) conj(c)^2 (i/2) sqrt(2/M)/P and B_j = -b_j/(1 + b_j x) (.) the same factor.
 // Pade factors are applied in product form u <- g_j u + (1 - g_j) w_j (the same
-// approximant as the paper's sum form; better conditioned in FP32).
+// approximant as the paper's sum form; better conditioned in FP32), written as the
+// increment u <- u + (q_j u + beta_j w'_j) with q_j = r_j - 1 (r_j = g_j + (1 - g_j) s_j the
+// factor's isovelocity multiplier) and w'_j the Neumann terms beyond the first.  The state
+// then takes one rounding per factor: for the propagating modes r_j is within ~1e-6 of 1,
+// the state changes by a few units in the last place per step, and the roundings of the
+// large products g_j u and (1 - g_j) w_j would repeat from step to step and grow linearly
+// with range.
 //
 // One workgroup owns one solve for a whole launch: the Neumann series of every Pade factor
 // runs on chip (transforms in registers + LDS); the state between factors stays in
@@ -32,8 +38,8 @@
 // kernels read every term (multipliers, potential, chirp spectra) come from L2 where they
 // do not fit the registers.  Precision: complex FP32
 // data; FFT twiddles and the sine-space multipliers are double-float (hi + lo) products so
-// that no fixed rounding of a table enters every step; residual norms in FP64; carrier
-// phase in FP64.
+// that no fixed rounding of a table enters every step on the isovelocity path; residual
+// norms in FP64; carrier phase in FP64.
 #include "ssp_device.h"
 #include "ssp_df.h"
 #include "ssp_tuned.h"
@@ -539,9 +545,7 @@ __device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, c
 // Z_q = Y_q K1_q - Y_{-q} K2_q for the distributed spectrum (one LDS exchange, phase PH).
 // ODD: the odd-frequency half of a split transform, whose reflection is q -> P-1-q.
 template <int P, int PH, bool ODD>
-__device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const LdsBufs &L,
-                                              const float2 *__restrict__ k1,
-                                              const float2 *__restrict__ k2) {
+__device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, KWin k) {
     constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
     const int tid = opaque_tid();
     before_write<P>();
@@ -565,7 +569,7 @@ __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const Lds
         float2 yr;
         if (!ODD && i == 0) yr = c ? buf[0] : rb[(RT - 1) * T];
         else yr = rb[(RT - 1 - i) * T];
-        x[i] = csub(cmul(x[i], ld2s(k1, t2, i * T)), cmul(yr, ld2s(k2, t2, i * T)));
+        x[i] = csub(cmul(x[i], ld2s(k.k1, t2, i * T)), cmul(yr, ld2s(k.k2, t2, i * T)));
     }
 }
 
@@ -576,11 +580,11 @@ __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const Lds
 // half is zero and the output's upper half is not needed; it is returned zero.
 template <int P, bool ODD, bool HALF = false>
 __device__ __forceinline__ void chirp_core(float2 (&x)[Cfg<P>::RT], const LdsBufs &L,
-                                           const Twiddles<P> &tw, const float2 *k1, const float2 *k2) {
+                                           const Twiddles<P> &tw, KWin k) {
     constexpr int F = fft_phases<P>();
     __syncthreads();
     fft<P, false, 0, HALF, false>(x, L, tw);
-    chirp_combine<P, F, ODD>(x, L, k1, k2);
+    chirp_combine<P, F, ODD>(x, L, k);
     fft<P, true, F + 1, false, HALF>(x, L, tw);
 }
 
@@ -648,7 +652,7 @@ __device__ __forceinline__ void sine_core(float2 (&x)[Cfg<EK>::RT], const LdsBuf
 }
 
 // One transform core for convolution length P (positions 0 .. eng_len-1 distributed as in
-// the engine), with the chirp-window spectra k1, k2 of the direction it runs in.  For P above kMaxEngine the odd-frequency half needs the input again after the
+// the engine), with the chirp-window spectra k of the direction it runs in.  For P above kMaxEngine the odd-frequency half needs the input again after the
 // even half has overwritten x: KEEP_GLOBAL keeps it (and the even result) in the solve's
 // scratch keep[0 .. 2N), else in registers.  Both give identical results.  Positions >= N
 // of the input must be zero.  Output: split lengths return zero at positions >= N; unsplit
@@ -656,11 +660,11 @@ __device__ __forceinline__ void sine_core(float2 (&x)[Cfg<EK>::RT], const LdsBuf
 template <int P, int V, bool KEEP_GLOBAL, int EKEY = eng_key<P, V>()>
 __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBufs &L,
                                          const Twiddles<EKEY> &tw, const SolveDesc &d, float2 *keep,
-                                         const float2 *k1, const float2 *k2) {
+                                         KWin k) {
     constexpr int H = eng_len<P>();
     constexpr int EK = eng_key<P, V>();
     if constexpr (H == P) {
-        chirp_core<EK, false, true>(x, L, tw, k1, k2);
+        chirp_core<EK, false, true>(x, L, tw, k);
     } else {
         constexpr int T = Cfg<EK>::T, RT = Cfg<EK>::RT;
         static_assert(P / T <= 32 && 32 % (P / T) == 0, "twist factor w_{P/T}^i is a radix constant");
@@ -680,7 +684,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
                 y[i] = v;
             }
         }
-        chirp_core<EK, false>(x, L, tw, k1, k2);
+        chirp_core<EK, false>(x, L, tw, k);
         if constexpr (KEEP_GLOBAL) {
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
@@ -688,7 +692,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
                 if (pos < N) st2(keep + N, pos, x[i]);
                 x[i] = pos < N ? ld2(keep, pos) : make_float2(0.f, 0.f);
             }
-            chirp_core<EK, true>(x, L, tw, k1 + H, k2 + H);
+            chirp_core<EK, true>(x, L, tw, KWin{k.k1 + H, k.k2 + H});
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T;
@@ -696,7 +700,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
                                : make_float2(0.f, 0.f);
             }
         } else {
-            chirp_core<EK, true>(y, L, tw, k1 + H, k2 + H);
+            chirp_core<EK, true>(y, L, tw, KWin{k.k1 + H, k.k2 + H});
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T;
@@ -843,15 +847,20 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     // table); otherwise it comes from L2
     constexpr bool kAInRegs = kBInRegs || (ECfg<P, V>::SINGLE && RL <= 16);
     constexpr int EA = kAInRegs ? RL : 1;
-    // the series sum w_j stays in registers up to 8 elements per thread or below 1024
-    // threads (else in d.wacc)
+    // the series sum beyond the first term (w') stays in registers up to 8 elements per
+    // thread or below 1024 threads (else in d.wacc); the first term a0 (for the norm of
+    // w = a0 + w') only in the small layouts (4 live elements, or 8 up to 128 threads):
+    // elsewhere the registers would spill, and it comes from d.a0
     constexpr bool kWInRegs = T < 1024 || RT <= 8;
     constexpr int EW = kWInRegs ? RL : 1;
+    constexpr bool kA0InRegs = kWInRegs && T < 1024 && (RL <= 4 || (RL <= 8 && T <= 128));
+    constexpr int E0 = kA0InRegs ? RL : 1;
     // the state between Pade factors stays in registers where the layout has room (one load
     // and one store of the field per step); otherwise it goes through the solve's work
     // array (a load and a store per factor).  Room: up to 8 live elements per thread below
-    // 1024 threads, or the 128-thread layout (16 elements; 252 registers, no spills); the
-    // other 16-element layouts would spill
+    // 1024 threads, and the 16-element layouts of up to 256 threads (at 8192 the 256-thread
+    // layout then spills 3 registers, measured as fast as without); the 512-thread one of
+    // 16384 would spill 18
     constexpr bool kUInRegs = (T < 1024) && (RL <= 8 || T <= 128);
     constexpr int EU = kUInRegs ? RL : 1;
     // split transforms keep their second input in the solve's scratch (fewer spills)
@@ -866,7 +875,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     // step (the recovery point if the step diverges) and d.work the state between Pade
     // factors.  Every thread reads and writes only its own positions, so these global
     // accesses need no barriers.
-    float2 w[EW], a[RT], A[EA], u[EU];
+    float2 w[EW], a[RT], A[EA], u[EU], a0r[E0];
     float4 Bm[EB];
     long long n = *d.step;
     // outputs of this launch: steps out_base, out_base + out_every, ... (row = slot)
@@ -908,12 +917,13 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                     else uc = ld2(cur, m);
                     a[i] = cmul_df(uc, ld4(d.s, j * N + m));
                     if constexpr (kBInRegs) Bm[i] = ld4(d.bmul, j * N + m);
+                    if constexpr (!kA0InRegs) st2(d.a0, m, a[i]);
                 } else {
                     a[i] = make_float2(0.f, 0.f);
                     if constexpr (kBInRegs) Bm[i] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                if constexpr (kWInRegs) w[i] = a[i];
-                else if (pos < N) st2(d.wacc, m, a[i]);
+                if constexpr (kA0InRegs) a0r[i] = a[i];
+                if constexpr (kWInRegs) w[i] = make_float2(0.f, 0.f);
                 t0f += cnorm2(a[i]);
             }
             double t0 = t0f, dummy = 0.0;
@@ -928,7 +938,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                 const bool fwd = (h & 1) != 0;
                 if constexpr (DK == kDkFourier) direct_core<EK>(a, L, tw, fwd);
                 else if constexpr (DK == kDkSine) sine_core<EK>(a, L, tw, d.mirror, d.N);
-                else dst_core<P, V, kKeepGlobal>(a, L, tw, d, d.xs, fwd ? d.k1 : d.k1i, fwd ? d.k2 : d.k2i);
+                else dst_core<P, V, kKeepGlobal>(a, L, tw, d, d.xs, fwd ? d.kf : d.ki);
                 if ((h & 1) == 0) {
 #pragma unroll
                     for (int i = 0; i < RL; ++i) {
@@ -951,13 +961,14 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                                                      : make_float4(0.f, 0.f, 0.f, 0.f);
                     a[i] = cmul_df(a[i], bm);
                     tnf += cnorm2(a[i]);
+                    // w' += a_m (the first term m = 1 starts it); the norm is that of w = a0 + w'
                     if constexpr (kWInRegs) {
-                        w[i] = cadd(w[i], a[i]);
-                        wnf += cnorm2(w[i]);
+                        w[i] = h == 1 ? a[i] : cadd(w[i], a[i]);
+                        wnf += cnorm2(cadd(kA0InRegs ? a0r[i] : (pos < N ? ld2(d.a0, pos) : a[i]), w[i]));
                     } else if (pos < N) {
-                        const float2 ws = cadd(ld2(d.wacc, pos), a[i]);
+                        const float2 ws = h == 1 ? a[i] : cadd(ld2(d.wacc, pos), a[i]);
                         st2(d.wacc, pos, ws);
-                        wnf += cnorm2(ws);
+                        wnf += cnorm2(cadd(ld2(d.a0, pos), ws));
                     }
                 }
                 tn = tnf;
@@ -987,15 +998,18 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
             }
             terms += used;
             max_used = used > max_used ? used : max_used;
-            // product-form factor: u <- g_j u + (1 - g_j) w_j  (alpha, beta double-float)
-            const float4 al = ld4(d.alpha, j), be = ld4(d.beta, j);
+            // product-form factor as an increment: u <- u + (q_j u + beta_j w')  (q_j, beta_j
+            // double-float; w' = 0 without Neumann terms)
+            const float4 be = ld4(d.beta, j);
 #pragma unroll
             for (int i = 0; i < RL; ++i) {
                 const int pos = opaque_tid() + i * T, m = pos;
                 if (pos < N) {
-                    const float2 ws = kWInRegs ? w[i] : ld2(d.wacc, m);
-                    if constexpr (kUInRegs) u[i] = cadd(cmul_df(u[i], al), cmul_df(ws, be));
-                    else st2(d.work, m, cadd(cmul_df(ld2(cur, m), al), cmul_df(ws, be)));
+                    const float2 ws = kWInRegs ? w[i] : (used > 0 ? ld2(d.wacc, m) : make_float2(0.f, 0.f));
+                    const float2 uc = kUInRegs ? u[i] : ld2(cur, m);
+                    const float2 un = cadd(uc, cadd(cmul_df(uc, ld4(d.qmul, j * N + m)), cmul_df(ws, be)));
+                    if constexpr (kUInRegs) u[i] = un;
+                    else st2(d.work, m, un);
                 }
             }
         }
@@ -1126,7 +1140,7 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_transform(const SolveDesc *
         __syncthreads();  // the previous vector's last LDS reads are done
         if constexpr (DK == kDkFourier) direct_core<eng_key<P, 0>()>(x, L, tw, mode != 2);
         else if constexpr (DK == kDkSine) sine_core<eng_key<P, 0>()>(x, L, tw, d.mirror, N);
-        else dst_core<P, 0, false>(x, L, tw, d, nullptr, mode == 2 ? d.k1i : d.k1, mode == 2 ? d.k2i : d.k2);
+        else dst_core<P, 0, false>(x, L, tw, d, nullptr, mode == 2 ? d.ki : d.kf);
         float2 car = make_float2(1.f, 0.f);
         if (mode == 2) car = carrier(d.sigma, step[v]);
         float2 *vout = out + static_cast<size_t>(v) * N;
@@ -1168,7 +1182,7 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_output(const SolveDesc *__r
     }
     if constexpr (DK == kDkFourier) direct_core<eng_key<P, 0>()>(x, L, tw, false);
     else if constexpr (DK == kDkSine) sine_core<eng_key<P, 0>()>(x, L, tw, d.mirror, N);
-    else dst_core<P, 0, false>(x, L, tw, d, nullptr, d.k1i, d.k2i);
+    else dst_core<P, 0, false>(x, L, tw, d, nullptr, d.ki);
     const float2 car = carrier(d.sigma, n);
     const float lr = log10f(static_cast<float>(static_cast<double>(n) * d.dr));
 #pragma unroll
@@ -1209,7 +1223,7 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_plain_start(const SolveDesc
         if (pos < N) {
             const float2 v = cmul_df(ld2(cur, m), ld4(d.s, j * N + m));
             st2(a, m, v);
-            st2(w, m, v);
+            st2(d.a0, m, v);
             part += cnorm2(v);
         }
     }
@@ -1242,7 +1256,7 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_plain_half(const SolveDesc 
         const int pos = opaque_tid() + i * T;
         x[i] = (pos < N) ? ld2(a, pos) : make_float2(0.f, 0.f);
     }
-    dst_core<P, 0, false>(x, L, tw, d, nullptr, (h & 1) ? d.k1 : d.k1i, (h & 1) ? d.k2 : d.k2i);
+    dst_core<P, 0, false>(x, L, tw, d, nullptr, (h & 1) ? d.kf : d.ki);
     if ((h & 1) == 0) {
         float2 A[RT];
         load_potential<P, 0, true>(d, n, A);
@@ -1259,11 +1273,11 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_plain_half(const SolveDesc 
         const int pos = opaque_tid() + i * T, m = pos;
         if (pos < N) {
             const float2 v = cmul_df(x[i], ld4(d.bmul, j * N + m));
-            const float2 ww = cadd(ld2(w, m), v);
+            const float2 ww = h == 1 ? v : cadd(ld2(w, m), v);
             st2(a, m, v);
             st2(w, m, ww);
             tnf += cnorm2(v);
-            wnf += cnorm2(ww);
+            wnf += cnorm2(cadd(ld2(d.a0, m), ww));
         }
     }
     double tn = tnf, wn = wnf;
@@ -1290,6 +1304,7 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_plain_finish(const SolveDes
     if (ps->halt) return;
     const bool conv = ps->done && !ps->bad;
     const bool diverged = ps->bad || (!conv && ps->tn >= ps->t0);
+    const bool any = ps->used > 0;  // Neumann terms were added (w holds their sum)
     __syncthreads();  // every thread has read ps before thread 0 updates it
     if (diverged) {
         if (threadIdx.x == 0) {
@@ -1310,11 +1325,14 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_plain_finish(const SolveDes
     }
     const int N = d.N;
     const float2 *cur = (j == 0) ? d.field : d.work;
-    const float4 al = ld4(d.alpha, j), be = ld4(d.beta, j);
+    const float4 be = ld4(d.beta, j);
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
         const int pos = opaque_tid() + i * T, m = pos;
-        if (pos < N) st2(d.work, m, cadd(cmul_df(ld2(cur, m), al), cmul_df(ld2(w, m), be)));
+        if (pos < N) {
+            const float2 uc = ld2(cur, m), ws = any ? ld2(w, m) : make_float2(0.f, 0.f);
+            st2(d.work, m, cadd(uc, cadd(cmul_df(uc, ld4(d.qmul, j * N + m)), cmul_df(ws, be))));
+        }
     }
 }
 

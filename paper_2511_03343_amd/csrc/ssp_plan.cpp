@@ -281,15 +281,22 @@ void put_c(std::vector<float> &v, size_t i, cd z) {
     v[2 * i + 1] = static_cast<float>(z.imag());
 }
 
-// FFT of a window given on positions 0..P-1, stored in the engine's slot order.
-std::vector<float> window_spectrum(std::vector<cd> w, int P, bool split) {
+// FFT of a window given on positions 0..P-1, in the engine's slot order (FP64).
+std::vector<cd> window_spectrum(std::vector<cd> w, int P, bool split) {
     host_fft(w, -1);
     const int PE = split ? P / 2 : P;
-    std::vector<float> out(2 * static_cast<size_t>(P));
+    std::vector<cd> out(P);
     for (int q = 0; q < P; ++q) {
         const int slot = split ? ((q & 1) ? PE + q / 2 : q / 2) : q;
-        put_c(out, slot, w[q]);
+        out[slot] = w[q];
     }
+    return out;
+}
+
+// A spectrum as interleaved complex FP32.
+std::vector<float> to_f32(const std::vector<cd> &k) {
+    std::vector<float> out(2 * k.size());
+    for (size_t q = 0; q < k.size(); ++q) put_c(out, static_cast<int>(q), k[q]);
     return out;
 }
 
@@ -341,11 +348,11 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
             // the sum conv + corr as conv - (-corr)
             for (long long d = 0; d <= 2LL * N - 2; ++d) K2[d % P] = -chirp(d);
         }
-        t.k1 = window_spectrum(K1, P, split);
-        t.k2 = window_spectrum(K2, P, split);
+        t.k1 = to_f32(window_spectrum(K1, P, split));
+        t.k2 = to_f32(window_spectrum(K2, P, split));
         if (bc == kBcPeriodic) {
             for (long long d = 1 - N; d <= N - 1; ++d) K1[((d % P) + P) % P] = std::conj(chirp(d));
-            t.k1i = window_spectrum(K1, P, split);
+            t.k1i = to_f32(window_spectrum(K1, P, split));
             t.k2i = t.k2;  // zero
         }
     }
@@ -459,7 +466,7 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
     const int p = ps.p;
     t.s.resize(static_cast<size_t>(4) * p * N);
     t.bmul.resize(static_cast<size_t>(4) * p * N);
-    t.alpha.resize(4 * p);
+    t.qmul.resize(static_cast<size_t>(4) * p * N);
     t.beta.resize(4 * p);
     t.tmul.clear();
     if (dense) t.tmul.resize(static_cast<size_t>(4) * p * N);
@@ -477,9 +484,15 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
         for (int j = 0; j < p; ++j) {
             cd sj = 1.0 / (1.0 + ps.b[j] * x);
             cd bj = -ps.b[j] * sj * dmod[m];
+            // C_j r_j - 1 = C_j (1 - g_j)(s_j - 1) + (C_j - 1), with s_j - 1 = -b_j x s_j
+            // (no cancellation for x near 0)
+            const cd g = ps.a[j] / ps.b[j], Cj = j == p - 1 ? ps.C : cd(1.0, 0.0);
+            const cd qj = Cj * (1.0 - g) * (-ps.b[j] * x * sj) + (Cj - 1.0);
             size_t o = (static_cast<size_t>(j) * N + m) * 4;
             split_df(sj.real(), t.s[o], t.s[o + 2]);
             split_df(sj.imag(), t.s[o + 1], t.s[o + 3]);
+            split_df(qj.real(), t.qmul[o], t.qmul[o + 2]);
+            split_df(qj.imag(), t.qmul[o + 1], t.qmul[o + 3]);
             split_df(bj.real(), t.bmul[o], t.bmul[o + 2]);
             split_df(bj.imag(), t.bmul[o + 1], t.bmul[o + 3]);
             if (dense) {
@@ -492,13 +505,8 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
     t.max_gain = gain;
     for (int j = 0; j < p; ++j) {
         cd g = ps.a[j] / ps.b[j];
-        cd al = g, be = 1.0 - g;
-        if (j == p - 1) {
-            al *= ps.C;
-            be *= ps.C;
-        }
-        split_df(al.real(), t.alpha[4 * j], t.alpha[4 * j + 2]);
-        split_df(al.imag(), t.alpha[4 * j + 1], t.alpha[4 * j + 3]);
+        cd be = 1.0 - g;
+        if (j == p - 1) be *= ps.C;
         split_df(be.real(), t.beta[4 * j], t.beta[4 * j + 2]);
         split_df(be.imag(), t.beta[4 * j + 1], t.beta[4 * j + 3]);
     }

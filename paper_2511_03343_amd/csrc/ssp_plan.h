@@ -74,7 +74,9 @@ struct DeviceTables {
     // k1i/k2i, when not empty, the inverse direction (the Fourier transform only; the sine
     // and cosine transforms are their own inverses).  For P > kMaxEngineFFT they are stored
     // as the even frequencies followed by the odd ones (the two halves of a split
-    // transform).
+    // transform).  Their FP32 rounding is a fixed perturbation of every transform, but the
+    // transforms only carry the Neumann terms (the isovelocity part of each factor is a
+    // double-float product in the sine basis), where it stays below the other roundings.
     std::vector<float> k1, k2, k1i, k2i;
     std::vector<float> pre;           // [nz] complex FP32 forward pre-modulation
     std::vector<float> post;          // [nz] complex FP32 inverse post-modulation (incl. 1/P)
@@ -94,7 +96,14 @@ struct DeviceTables {
     // Pade factors in the chirp-modulated sine basis:
     std::vector<float> s;             // [p][nz] double-float complex 1/(1 + b_j x_l)
     std::vector<float> bmul;          // [p][nz] double-float complex -b_j s_jl * dmod_l (FP64 product)
-    std::vector<float> alpha, beta;   // [p] double-float complex combine weights
+    // The product-form factor u <- C_j (g_j u + (1 - g_j) w_j), w_j = s_j u + w'_j (w'_j the
+    // Neumann terms beyond the first; C_j = C for the last factor, else 1) applied as the
+    // increment u <- u + (q_j u + beta_j w'_j): for the propagating modes r_j = g_j + (1 -
+    // g_j) s_j is within ~1e-6 of 1, and the increment keeps the FP32 roundings of the
+    // large intermediate products g_j u and (1 - g_j) w_j, which repeat from step to step
+    // while the mode barely changes, out of the state.
+    std::vector<float> qmul;          // [p][nz] double-float complex C_j r_j - 1
+    std::vector<float> beta;          // [p] double-float complex C_j (1 - g_j)
     double max_gain = 0;              // max_l |e^{i sigma} R(x_l)|
     // dense engine (Dirichlet grids with nz <= kMaxDenseGrid), else empty:
     std::vector<float> tmul;          // [p][nz] double-float complex -b_j/(1 + b_j x_l), plain sine basis
