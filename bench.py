@@ -354,6 +354,12 @@ def run_broadband(args, ssp, torch, stream, dev):
     for pl in plans:
         ssp.ssp_plan_set_stream(pl, stream.cuda_stream)
         ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, -2)   # layouts tuned on a mixed batch
+    if args.layouts:
+        chosen = {int(k): int(v) for k, v in (kv.split("=") for kv in args.layouts.split(","))}
+        for pl in plans:
+            P = ssp.ssp_plan_engine(pl)[2]
+            if P in chosen:
+                ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, chosen[P])
     ssp.ssp_plan_set_option(plans[0], ssp.SSP_OPT_GRAPH, 1 if args.graph else 0)
     for pl, s in zip(plans, solves):
         ssp.ssp_set_field(pl, s.starter(), s.nz)
@@ -557,6 +563,8 @@ def main():
                     help="broadband: skip the deep Munk line and the serving stream")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB of a plain device copy run first (counter calibration)")
+    ap.add_argument("--layouts", default=None, metavar="P=V[,P=V]",
+                    help="broadband: engine layout per FFT length instead of the tuned one")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-transforms", action="store_true",
                     help="skip the stand-alone transform measurements")

@@ -77,6 +77,7 @@ struct ssp_plan {
     float2 *d_k1i = nullptr, *d_k2i = nullptr, *d_postf = nullptr;  // only where they differ
     float4 *d_mirror = nullptr;         // odd-extension image factors (direct sine transform)
     const float4 *d_twl = nullptr;      // shared last-pass twiddles of 1024-thread engines (not owned)
+    const float4 *d_twl2 = nullptr;     // ... of the layout-2 split engine (split plans; not owned)
     uint32_t *d_tw = nullptr;
     float4 *d_s = nullptr, *d_bmul = nullptr, *d_qmul = nullptr, *d_beta = nullptr;
     float4 *d_twist = nullptr;
@@ -302,6 +303,9 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     if (!tab.k2.empty()) HIP_TRY(upload(pl->d_k2, tab.k2));
     HIP_TRY(upload(pl->d_tw, tab.twiddle));
     HIP_TRY(ssp::last_twiddles(P, pl->d_tw, &pl->d_twl));
+    // split plans: their octant table is that of the 16384-point engine, whose layout-2 table
+    // serves the layout-2 split engine
+    if (P > 16384) HIP_TRY(ssp::last_twiddles(P / 2, pl->d_tw, &pl->d_twl2));
     HIP_TRY(upload(pl->d_dmod, tab.dmod));
     HIP_TRY(upload(pl->d_post, tab.post));
     HIP_TRY(upload(pl->d_pre, tab.pre));
@@ -343,6 +347,7 @@ ssp::SolveDesc base_desc(const ssp_plan *pl) {
     d.ki = ssp::KWin{pl->d_k1i ? pl->d_k1i : pl->d_k1, pl->d_k2i ? pl->d_k2i : pl->d_k2};
     d.tw = pl->d_tw;
     d.twl = pl->d_twl;
+    d.twl2 = pl->d_twl2;
     d.dmod = pl->d_dmod;
     d.post = pl->d_post;
     d.pre = pl->d_pre;

@@ -34,6 +34,8 @@ struct SolveDesc {
     const uint32_t *tw;         // first-octant twiddle table (see DeviceTables::twiddle)
     const float4 *twl;          // last-pass twiddles of the split-transform engine,
                                 //     [RT-1][1024] (see last_twiddles), else null
+    const float4 *twl2;         // the same for the layout-2 split engine ([31][512]: the
+                                //     table of the layout-2 16384-point engine), else null
     const float2 *dmod, *post;  // [N] folded modulation; inverse post-modulation
     const float2 *pre;          // [N] forward pre-modulation (grid values -> chirp-z input)
     const float2 *postf;        // [N] forward post-modulation (stand-alone transform)

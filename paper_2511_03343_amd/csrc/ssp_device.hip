@@ -315,13 +315,13 @@ constexpr int mid_tab_offset() { return mid_tab_len<P>() - mid_tab_from<P, Ns>()
 // per lane, which the second half's state leaves short) and the layout-2 engines (31
 // twiddles per thread, 93 registers) read them from a device table ([r-1][t], coalesced,
 // shared by every workgroup, so it stays in L2).  The split engine loads them before the
-// barrier that precedes their use; layout 2 at their use (the other workgroup on the compute
-// unit covers the latency).  (The unsplit 1024-thread engines measured faster with register
-// twiddles and a few spills.)
+// barrier that precedes their use in layout 0; layout 2 (also of split transforms) at their
+// use (the other workgroup on the compute unit covers the latency).  (The unsplit
+// 1024-thread engines measured faster with register twiddles and a few spills.)
 template <int P>
 struct Twiddles {
     static constexpr bool kRegs = !key_split(P) && key_var(P) != 2;
-    static constexpr bool kPrefetch = key_split(P);  // table twiddles loaded ahead of the barrier
+    static constexpr bool kPrefetch = key_split(P) && key_var(P) != 2;  // table twiddles loaded ahead of the barrier
     static constexpr int NTW = kRegs ? Cfg<P>::RT - 1 : 1;
     float2 h[NTW];   // FP32 nearest value
     uint32_t l[NTW]; // remainder as two bf16 (re high, im low)
@@ -667,17 +667,21 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
         chirp_core<EK, false, true>(x, L, tw, k);
     } else {
         constexpr int T = Cfg<EK>::T, RT = Cfg<EK>::RT;
-        static_assert(P / T <= 32 && 32 % (P / T) == 0, "twist factor w_{P/T}^i is a radix constant");
+        // odd-frequency input y = x (.) w_P^n: for n = t + i T, w_P^n = w_P^{t + (i mod NW) T}
+        // w_Q^{i / NW} with Q = P/(NW T) <= 32: NW table values per thread (the table holds
+        // w_P^n for n < P/2) and a double-float radix-Q constant
+        constexpr int NW = (P / T) > 32 ? (P / T) / 32 : 1, Q = P / (NW * T);
+        static_assert(Q <= 32 && 32 % Q == 0 && NW * T <= P / 2, "twist factor w_Q^i is a radix constant");
         const int N = d.N;
         float2 y[KEEP_GLOBAL ? 1 : RT];
-        // odd-frequency input y = x (.) w_P^n: for n = t + i T, w_P^n = w_P^t w_{P/T}^i, the
-        // thread's w_P^t from the table (one load) and w_{P/T}^i a double-float radix constant
-        const float4 wt = ld4(d.twist, opaque_tid());
+        float4 wt[NW];
+#pragma unroll
+        for (int k2 = 0; k2 < NW; ++k2) wt[k2] = ld4(d.twist, opaque_tid() + k2 * T);
 #pragma unroll
         for (int i = 0; i < RT; ++i) {
             const int pos = opaque_tid() + i * T;
             float2 v = make_float2(0.f, 0.f);
-            if (pos < N) v = mulw<P / T, false>(cmul_df(x[i], wt), i);
+            if (pos < N) v = mulw<Q, false>(cmul_df(x[i], wt[i % NW]), i / NW);
             if constexpr (KEEP_GLOBAL) {
                 if (pos < N) st2(keep, pos, v);
             } else {
@@ -696,7 +700,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T;
-                x[i] = pos < N ? cadd(ld2(keep + N, pos), mulw<P / T, true>(cmul_df_conj(x[i], wt), i))
+                x[i] = pos < N ? cadd(ld2(keep + N, pos), mulw<Q, true>(cmul_df_conj(x[i], wt[i % NW]), i / NW))
                                : make_float2(0.f, 0.f);
             }
         } else {
@@ -704,7 +708,8 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T;
-                x[i] = pos < N ? cadd(x[i], mulw<P / T, true>(cmul_df_conj(y[i], wt), i)) : make_float2(0.f, 0.f);
+                x[i] = pos < N ? cadd(x[i], mulw<Q, true>(cmul_df_conj(y[i], wt[i % NW]), i / NW))
+                               : make_float2(0.f, 0.f);
             }
         }
     }
@@ -848,28 +853,32 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     constexpr bool kAInRegs = kBInRegs || (ECfg<P, V>::SINGLE && RL <= 16);
     constexpr int EA = kAInRegs ? RL : 1;
     // the series sum beyond the first term (w') stays in registers up to 8 elements per
-    // thread or below 1024 threads (else in d.wacc); the first term a0 (for the norm of
-    // w = a0 + w') only in the small layouts (4 live elements, or 8 up to 128 threads):
-    // elsewhere the registers would spill, and it comes from d.a0
-    constexpr bool kWInRegs = T < 1024 || RT <= 8;
+    // thread, or 16 below 1024 threads (else in d.wacc)
+    constexpr bool kWInRegs = RT <= 8 || (T < 1024 && RL <= 16);
     constexpr int EW = kWInRegs ? RL : 1;
-    constexpr bool kA0InRegs = kWInRegs && T < 1024 && (RL <= 4 || (RL <= 8 && T <= 128));
-    constexpr int E0 = kA0InRegs ? RL : 1;
     // the state between Pade factors stays in registers where the layout has room (one load
     // and one store of the field per step); otherwise it goes through the solve's work
     // array (a load and a store per factor).  Room: up to 8 live elements per thread below
-    // 1024 threads, and the 16-element layouts of up to 256 threads (at 8192 the 256-thread
-    // layout then spills 3 registers, measured as fast as without); the 512-thread one of
-    // 16384 would spill 18
-    constexpr bool kUInRegs = (T < 1024) && (RL <= 8 || T <= 128);
+    // 1024 threads, and the 16-element layouts of up to 256 threads (a few spills outside
+    // the term loop); the 512-thread one of 16384 would spill in it
+    constexpr bool kUInRegs = (T < 1024) && (RL <= 8 || (RL <= 16 && T <= 256));
     constexpr int EU = kUInRegs ? RL : 1;
+    // the first term a0 (for the norm of w = a0 + w' in every term): in registers in the
+    // small layouts (4 live elements, or 8 up to 128 threads); recomputed as s_j (.) u from
+    // the state in registers and the multiplier table (L2) where the state is there; else
+    // stored once per factor in the solve's d.a0 and read back
+    constexpr int kA0Regs = 0, kA0FromU = 1, kA0Global = 2;
+    constexpr int kA0 = (kWInRegs && T < 1024 && (RL <= 4 || (RL <= 8 && T <= 128))) ? kA0Regs
+                        : (kUInRegs && kWInRegs)                                     ? kA0FromU
+                                                                                     : kA0Global;
+    constexpr int E0 = kA0 == kA0Regs ? RL : 1;
     // split transforms keep their second input in the solve's scratch (fewer spills)
     constexpr bool kKeepGlobal = true;
     const LdsBufs L = carve_lds<EK>(lds_raw);
     const int tid = threadIdx.x;
     const int N = d.N, p = d.p, nmax = d.nmax;
     Twiddles<EK> tw;
-    init_twiddles<EK>(tw, L.tw4, d.tw, d.twl);
+    init_twiddles<EK>(tw, L.tw4, d.tw, (key_split(EK) && key_var(EK) == 2) ? d.twl2 : d.twl);
 
     // The state u is not held in registers: d.field holds the state at the start of the
     // step (the recovery point if the step diverges) and d.work the state between Pade
@@ -917,12 +926,12 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                     else uc = ld2(cur, m);
                     a[i] = cmul_df(uc, ld4(d.s, j * N + m));
                     if constexpr (kBInRegs) Bm[i] = ld4(d.bmul, j * N + m);
-                    if constexpr (!kA0InRegs) st2(d.a0, m, a[i]);
+                    if constexpr (kA0 == kA0Global) st2(d.a0, m, a[i]);
                 } else {
                     a[i] = make_float2(0.f, 0.f);
                     if constexpr (kBInRegs) Bm[i] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                if constexpr (kA0InRegs) a0r[i] = a[i];
+                if constexpr (kA0 == kA0Regs) a0r[i] = a[i];
                 if constexpr (kWInRegs) w[i] = make_float2(0.f, 0.f);
                 t0f += cnorm2(a[i]);
             }
@@ -951,7 +960,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                     }
                     continue;
                 }
-                float tnf = 0.f, wnf = 0.f;
+                float tnf = 0.f, wpf = 0.f;
 #pragma unroll
                 for (int i = 0; i < RL; ++i) {
                     const int pos = opaque_tid() + i * T;
@@ -961,21 +970,48 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                                                      : make_float4(0.f, 0.f, 0.f, 0.f);
                     a[i] = cmul_df(a[i], bm);
                     tnf += cnorm2(a[i]);
-                    // w' += a_m (the first term m = 1 starts it); the norm is that of w = a0 + w'
+                    // w' += a_m (the first term m = 1 starts it)
                     if constexpr (kWInRegs) {
                         w[i] = h == 1 ? a[i] : cadd(w[i], a[i]);
-                        wnf += cnorm2(cadd(kA0InRegs ? a0r[i] : (pos < N ? ld2(d.a0, pos) : a[i]), w[i]));
+                        wpf += cnorm2(w[i]);
                     } else if (pos < N) {
                         const float2 ws = h == 1 ? a[i] : cadd(ld2(d.wacc, pos), a[i]);
                         st2(d.wacc, pos, ws);
-                        wnf += cnorm2(cadd(ld2(d.a0, pos), ws));
+                        wpf += cnorm2(ws);
                     }
                 }
                 tn = tnf;
-                wn = wnf;
-                block_sum2<T>(tn, wn, red);
+                double wp = wpf;
+                block_sum2<T>(tn, wp, red);
                 used = (h >> 1) + 1;
-                if (!(isfinite(tn) && isfinite(wn))) {
+                if (!(isfinite(tn) && isfinite(wp))) {
+                    bad = true;
+                    break;
+                }
+                // The stopping rule compares |a_m|^2 with tol^2 |w|^2, w = a0 + w'.  By the
+                // triangle inequality |w| <= |a0| + |w'|: while |a_m|^2 exceeds tol^2 times that
+                // bound (with a margin well above the rounding of the sums) the exact test
+                // cannot pass, and the exact norm (which needs a0) is formed only when it can,
+                // and at the last term (whose norm the residual statistic reports).  Decisions
+                // and reported norms are those of evaluating it every term.
+                const double ub = sqrt(t0) + sqrt(wp);
+                if (h + 1 < 2 * nmax && tn > d.tol2 * ub * ub * (1.0 + 1e-4)) continue;
+                float wnf = 0.f;
+#pragma unroll
+                for (int i = 0; i < RL; ++i) {
+                    const int pos = opaque_tid() + i * T;
+                    if (pos < N) {
+                        float2 a0v;
+                        if constexpr (kA0 == kA0Regs) a0v = a0r[i];
+                        else if constexpr (kA0 == kA0FromU) a0v = cmul_df(u[i], ld4(d.s, j * N + pos));
+                        else a0v = ld2(d.a0, pos);
+                        wnf += cnorm2(cadd(a0v, kWInRegs ? w[i] : ld2(d.wacc, pos)));
+                    }
+                }
+                wn = wnf;
+                double dummy = 0.0;
+                block_sum2<T>(wn, dummy, red);
+                if (!isfinite(wn)) {
                     bad = true;
                     break;
                 }
@@ -1422,7 +1458,7 @@ hipError_t launch_march_PV(int v, const SolveDesc *d_descs, int nsolves, int nst
     if constexpr (variant_exists(eng_len<P>(), 1)) {
         if (v == 1) return launch_march_P<P, 1>(d_descs, nsolves, nsteps, stream);
     }
-    if constexpr (P <= kMaxEngine && variant_exists(eng_len<P>(), 2)) {  // split lengths: layout 0 only
+    if constexpr (variant_exists(eng_len<P>(), 2)) {
         if (v == 2) return launch_march_P<P, 2>(d_descs, nsolves, nsteps, stream);
     }
     return launch_march_P<P, 0>(d_descs, nsolves, nsteps, stream);
@@ -1524,7 +1560,7 @@ hipError_t launch_march_direct_P(int kind, int v, const SolveDesc *d_descs, int 
 bool march_family_member(int P) { return P == 8192 || P == 16384 || P == 32768; }
 
 bool engine_variant_exists(int P, int variant) {
-    if (P > kMaxEngine) return variant == 0;  // the split engine has one layout
+    if (P > kMaxEngine) return variant == 0 || variant == 2;  // the split engine: layouts 0 and 2
     return variant >= 0 && variant <= 2 && variant_exists(P, variant);
 }
 

@@ -250,23 +250,25 @@ def test_eddy_in_two_workgroup_layouts(ssp, gpu, nz, nsteps, profile):
     compare(f"eddy layout 2 {profile} nz={nz}", fld, tl, ref)
 
 
-@pytest.mark.parametrize("profile", ["table", "analytic"])
-def test_eddy_full_size_start(ssp, gpu, profile):
+@pytest.mark.parametrize("profile,variant", [("table", 0), ("analytic", 0), ("analytic", 2)])
+def test_eddy_full_size_start(ssp, gpu, profile, variant):
     # Munk + eddy at its full size (200 Hz, Nz = 16384, [8/8], Neumann <= 12, dr = 20 m):
-    # the first 10 steps, split transforms throughout
+    # the first 10 steps, split transforms throughout, in both layouts of the split engine
     s = W.munk_eddy(nsteps=10)
     pl = make_plan(ssp, s, profile=profile)
     try:
+        ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, variant)
+        assert ssp.ssp_plan_engine(pl)[0] == variant
         st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
     finally:
         ssp.ssp_plan_destroy(pl)
     ref = oracle_march(s)
-    _report(f"eddy full start {profile}", status=st, oracle_status=ref.status,
+    _report(f"eddy full start {profile} layout {variant}", status=st, oracle_status=ref.status,
             terms=stats["neumann_terms"], oracle_terms=int(ref.iterations.sum()),
             not_converged=stats["not_converged"])
     assert st in (OK, NOT_CONVERGED) and ref.status in (OK, NOT_CONVERGED)
     assert stats["steps_done"] == ref.steps_done == s.nsteps
-    compare(f"eddy full start {profile}", fld, tl, ref)
+    compare(f"eddy full start {profile} layout {variant}", fld, tl, ref)
 
 
 # ------------------------------------------------------------------------------- statuses
@@ -421,9 +423,10 @@ def test_plain_form_equals_fused_bitwise(ssp, gpu, nz, env):
     assert np.array_equal(f0, f1) and np.array_equal(t0, t1)
 
 
-# every engine layout of the lengths that have several (FFT lengths 1024 ... 8192; a layout
-# a length does not have falls back to layout 0)
-@pytest.mark.parametrize("nz", [510, 1000, 2046, 4096, 6000])
+# every engine layout of the lengths that have several (FFT lengths 1024 ... 32768; a layout
+# a length does not have falls back to layout 0; Nz = 12000 runs the split transform, whose
+# layout 2 is the 512-thread engine of the 16384-point halves)
+@pytest.mark.parametrize("nz", [510, 1000, 2046, 4096, 6000, 12000])
 @pytest.mark.parametrize("variant", [0, 1, 2])
 def test_engine_layouts_vs_oracle(ssp, gpu, nz, variant):
     s = W.munk_deep(nsteps=16, nz=nz)
@@ -458,6 +461,15 @@ def test_layout_option_and_engine_query(ssp, gpu):
         assert ssp.ssp_plan_engine(pl) == seen[2]
         ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, -1)
         assert ssp.ssp_plan_engine(pl) == (v0, t0, p0)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    pl = ssp.ssp_plan_create(12000, 5000.0, 225.0, 1500.0, 25.0, 6, 48, 1e-10)  # split: 0 and 2
+    try:
+        got = {}
+        for v in (0, 1, 2):
+            ssp.ssp_plan_set_option(pl, ssp.SSP_OPT_VARIANT, v)
+            got[v] = ssp.ssp_plan_engine(pl)
+        assert got[0] == (0, 1024, 32768) and got[1] == got[0] and got[2] == (2, 512, 32768)
     finally:
         ssp.ssp_plan_destroy(pl)
     pl = ssp.ssp_plan_create(300, 1000.0, 50.0, 1500.0, 10.0, 2, 0, 1e-10)  # FFT length 1024
