@@ -42,14 +42,18 @@ PEAK_FP32 = 157.3e12   # MI355X published FP32 vector peak (FLOP/s)
 PEAK_HBM = 8.0e12      # MI355X HBM3E (B/s)
 
 # HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc passes (FETCH_SIZE,
-# WRITE_SIZE) of `bench.py --steps 100 --warmup 10 --roof-launches 2 --copy-calibration 1024`,
-# each scaled by the counter's reading for a plain 1 GiB device copy in the same run
+# WRITE_SIZE) of `bench.py [--workload munk4096 --steps 100 | --steps 40] --warmup 40|10
+# --roof-launches 2 --copy-calibration 1024 --no-extras`, averaged over the two roofline
+# launches, each counter scaled by its reading for a plain 1 GiB device copy in the same run
 # (FETCH_SIZE reads 0.5x the bytes moved, WRITE_SIZE 1.0x).  Keyed by the workload's launch
-# shape and a fingerprint of the kernel sources and layout table: any change to their code
-# (comments aside) makes the figure stale, and it is then reported as null.
+# shape (workload, Nz or FFT length of the dominant group, solves, steps per launch) and a
+# fingerprint of the kernel sources and layout table: any change to their code (comments
+# aside) makes the figure stale, and it is then reported as null.
 TRAFFIC = {
-    ("munk4096", 4096, 512, 100): {"fingerprint": "631755b3858450d3", "fetch": 2584023488.0,
-                                   "write": 9400292640.0},
+    ("broadband", 32768, 150, 40): {"fingerprint": "9d775d3d184a4164", "fetch": 6.7195e11,
+                                    "write": 1.7966e11},
+    ("munk4096", 4096, 512, 100): {"fingerprint": "9d775d3d184a4164", "fetch": 1.4651e8,
+                                   "write": 1.7577e9},
 }
 
 
