@@ -1485,7 +1485,6 @@ __global__ void k_fill_descs(ssp::SolveDesc tmpl, int B, float2 *psi, long long 
     d.pot = d.work + N;
     d.wacc = d.work + 2 * N;
     d.xs = d.work + 3 * N;
-    d.a0 = d.work + 5 * N;
     d.step = step + b;
     d.stats = stats + b;
     d.fld_out = nullptr;

@@ -59,7 +59,6 @@ struct SolveDesc {
     float2 *wacc;               // [N] scratch Neumann sum beyond the first term (kernels that do
                                 //     not hold it in registers)
     float2 *xs;                 // [2N] scratch of split transforms
-    float2 *a0;                 // [N] scratch first series term (kernels that do not hold it in registers)
     long long *step;            // global step counter
     DevStats *stats;
     float2 *snap;               // [nout][N] sine-basis snapshots at output steps, or null
@@ -87,14 +86,13 @@ constexpr int kStatusProfileRange = -1;
 // launch).  direct: the plans' direct transform kind (0: chirp-z cores; 1: periodic grid of
 // length P, FFTs; 2: Dirichlet grid of length P/2 - 1, the FFT of the odd extension;
 // P <= 16384 for both).  Returns hipSuccess or the launch error.
-// Scratch elements (complex) per solve behind SolveDesc::work: work, pot, wacc, xs (2N), a0.
-constexpr int kWorkPerSolve = 6;
+// Scratch elements (complex) per solve behind SolveDesc::work: work, pot, wacc, xs (2N).
+constexpr int kWorkPerSolve = 5;
 inline void set_work(SolveDesc &d, float2 *base) {
     d.work = base;
     d.pot = base + d.N;
     d.wacc = base + 2 * static_cast<size_t>(d.N);
     d.xs = base + 3 * static_cast<size_t>(d.N);
-    d.a0 = base + 5 * static_cast<size_t>(d.N);
 }
 
 hipError_t launch_march(int P, int variant, int direct, const SolveDesc *d_descs, int nsolves, int nsteps,

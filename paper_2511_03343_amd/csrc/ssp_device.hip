@@ -859,19 +859,11 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     // the state between Pade factors stays in registers where the layout has room (one load
     // and one store of the field per step); otherwise it goes through the solve's work
     // array (a load and a store per factor).  Room: up to 8 live elements per thread below
-    // 1024 threads, and the 16-element layouts of up to 256 threads (a few spills outside
-    // the term loop); the 512-thread one of 16384 would spill in it
-    constexpr bool kUInRegs = (T < 1024) && (RL <= 8 || (RL <= 16 && T <= 256));
+    // 1024 threads, and 16 in the single-buffer layouts of up to 256 threads (their register
+    // cap keeps two waves per SIMD; a few spills outside the term loop); elsewhere 16 more
+    // would push the kernel past 256 registers and halve its occupancy
+    constexpr bool kUInRegs = (T < 1024) && (RL <= 8 || (RL <= 16 && T <= 256 && ECfg<P, V>::SINGLE));
     constexpr int EU = kUInRegs ? RL : 1;
-    // the first term a0 (for the norm of w = a0 + w' in every term): in registers in the
-    // small layouts (4 live elements, or 8 up to 128 threads); recomputed as s_j (.) u from
-    // the state in registers and the multiplier table (L2) where the state is there; else
-    // stored once per factor in the solve's d.a0 and read back
-    constexpr int kA0Regs = 0, kA0FromU = 1, kA0Global = 2;
-    constexpr int kA0 = (kWInRegs && T < 1024 && (RL <= 4 || (RL <= 8 && T <= 128))) ? kA0Regs
-                        : (kUInRegs && kWInRegs)                                     ? kA0FromU
-                                                                                     : kA0Global;
-    constexpr int E0 = kA0 == kA0Regs ? RL : 1;
     // split transforms keep their second input in the solve's scratch (fewer spills)
     constexpr bool kKeepGlobal = true;
     const LdsBufs L = carve_lds<EK>(lds_raw);
@@ -884,7 +876,7 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     // step (the recovery point if the step diverges) and d.work the state between Pade
     // factors.  Every thread reads and writes only its own positions, so these global
     // accesses need no barriers.
-    float2 w[EW], a[RT], A[EA], u[EU], a0r[E0];
+    float2 w[EW], a[RT], A[EA], u[EU];
     float4 Bm[EB];
     long long n = *d.step;
     // outputs of this launch: steps out_base, out_base + out_every, ... (row = slot)
@@ -926,12 +918,10 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                     else uc = ld2(cur, m);
                     a[i] = cmul_df(uc, ld4(d.s, j * N + m));
                     if constexpr (kBInRegs) Bm[i] = ld4(d.bmul, j * N + m);
-                    if constexpr (kA0 == kA0Global) st2(d.a0, m, a[i]);
                 } else {
                     a[i] = make_float2(0.f, 0.f);
                     if constexpr (kBInRegs) Bm[i] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                if constexpr (kA0 == kA0Regs) a0r[i] = a[i];
                 if constexpr (kWInRegs) w[i] = make_float2(0.f, 0.f);
                 t0f += cnorm2(a[i]);
             }
@@ -1001,10 +991,8 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                 for (int i = 0; i < RL; ++i) {
                     const int pos = opaque_tid() + i * T;
                     if (pos < N) {
-                        float2 a0v;
-                        if constexpr (kA0 == kA0Regs) a0v = a0r[i];
-                        else if constexpr (kA0 == kA0FromU) a0v = cmul_df(u[i], ld4(d.s, j * N + pos));
-                        else a0v = ld2(d.a0, pos);
+                        // a0 = s_j (.) u again, from the factor's input state
+                        const float2 a0v = cmul_df(kUInRegs ? u[i] : ld2(cur, pos), ld4(d.s, j * N + pos));
                         wnf += cnorm2(cadd(a0v, kWInRegs ? w[i] : ld2(d.wacc, pos)));
                     }
                 }
@@ -1259,7 +1247,6 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_plain_start(const SolveDesc
         if (pos < N) {
             const float2 v = cmul_df(ld2(cur, m), ld4(d.s, j * N + m));
             st2(a, m, v);
-            st2(d.a0, m, v);
             part += cnorm2(v);
         }
     }
@@ -1303,6 +1290,7 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_plain_half(const SolveDesc 
         }
         return;
     }
+    const float2 *cur = (j == 0) ? d.field : d.work;  // the factor's input state
     float tnf = 0.f, wnf = 0.f;
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
@@ -1313,7 +1301,7 @@ __global__ __launch_bounds__((ECfg<P, 0>::T)) void k_plain_half(const SolveDesc 
             st2(a, m, v);
             st2(w, m, ww);
             tnf += cnorm2(v);
-            wnf += cnorm2(cadd(ld2(d.a0, m), ww));
+            wnf += cnorm2(cadd(cmul_df(ld2(cur, m), ld4(d.s, j * N + m)), ww));
         }
     }
     double tn = tnf, wn = wnf;

@@ -63,7 +63,7 @@ def test_noalloc_rejects_a_batch_above_the_scratch(ssp, gpu):
     stream = torch.cuda.Stream()
     pl = _plan(ssp, s, stream)
     try:
-        B = 1024  # 6 x 4096 x 1024 complex values of state alone: 192 MiB
+        B = 1024  # 5 x 4096 x 1024 complex values of state alone: 160 MiB
         d_psi = torch.zeros((B, s.nz), dtype=torch.complex64, device="cuda")
         d_step = torch.zeros(B, dtype=torch.int64, device="cuda")
         with pytest.raises(ssp.SspError) as e:
