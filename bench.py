@@ -50,10 +50,10 @@ PEAK_HBM = 8.0e12      # MI355X HBM3E (B/s)
 # fingerprint of the kernel sources and layout table: any change to their code (comments
 # aside) makes the figure stale, and it is then reported as null.
 TRAFFIC = {
-    ("broadband", 32768, 150, 40): {"fingerprint": "9d775d3d184a4164", "fetch": 6.7195e11,
-                                    "write": 1.7966e11},
-    ("munk4096", 4096, 512, 100): {"fingerprint": "9d775d3d184a4164", "fetch": 1.4651e8,
-                                   "write": 1.7577e9},
+    ("broadband", 32768, 150, 40): {"fingerprint": "6d008ec4a2951556", "fetch": 6.8086e11,
+                                    "write": 1.7644e11},
+    ("munk4096", 4096, 512, 100): {"fingerprint": "6d008ec4a2951556", "fetch": 3.109e7,
+                                   "write": 1.7587e9},
 }
 
 

@@ -7,7 +7,7 @@ namespace ssp {
 constexpr int kTunedVariant[9] = {0, 0, 0, 0, 1, 2, 2, 2, 0};
 // kTunedDirect[kind - 1][log2(P) - 7]: direct Fourier (periodic Nz = P), direct sine
 // (Dirichlet Nz = P/2 - 1)
-constexpr int kTunedDirect[2][9] = {{0, 0, 0, 0, 1, 0, 1, 2, 0}, {0, 0, 0, 0, 1, 2, 2, 2, 0}};
+constexpr int kTunedDirect[2][9] = {{0, 0, 0, 0, 1, 0, 0, 0, 0}, {0, 0, 0, 0, 1, 2, 2, 2, 0}};
 // kTunedMixed[log2(P) - 7]: chirp-z layouts for batches that mix FFT lengths
 // (SSP_OPT_VARIANT = -2), measured on a mixed-length batch
 constexpr int kTunedMixed[9] = {0, 0, 0, 0, 1, 1, 1, 2, 0};
