@@ -50,10 +50,10 @@ PEAK_HBM = 8.0e12      # MI355X HBM3E (B/s)
 # fingerprint of the kernel sources and layout table: any change to their code (comments
 # aside) makes the figure stale, and it is then reported as null.
 TRAFFIC = {
-    ("broadband", 32768, 150, 40): {"fingerprint": "6d008ec4a2951556", "fetch": 6.8086e11,
-                                    "write": 1.7644e11},
-    ("munk4096", 4096, 512, 100): {"fingerprint": "6d008ec4a2951556", "fetch": 3.109e7,
-                                   "write": 1.7587e9},
+    ("broadband", 32768, 150, 40): {"fingerprint": "1f92bc374889f51c", "fetch": 6.8110e11,
+                                    "write": 1.7639e11},
+    ("munk4096", 4096, 512, 100): {"fingerprint": "1f92bc374889f51c", "fetch": 3.1071e7,
+                                   "write": 1.7790e9},
 }
 
 
