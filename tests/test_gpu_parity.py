@@ -289,6 +289,40 @@ def test_divergence_reported_and_field_kept(ssp, gpu):
     assert np.linalg.norm(back - s.starter()) / np.linalg.norm(s.starter()) < 2e-6
 
 
+@pytest.mark.parametrize("nz", [500, 4096])
+def test_divergence_after_unwritten_steps(ssp, gpu, nz):
+    # layouts that keep the state in registers write it back every 64 steps and at the end
+    # of a launch: a step that diverges after unwritten steps (here step 5, where a slow
+    # layer enters the tabulated profile) reloads the written state and marches those steps
+    # again, so the field is the state after the last good step, bitwise equal to a march
+    # that stops there, and the oracle stops at the same step
+    s = W.munk_deep(nsteps=8, nz=nz)
+    z = (np.arange(nz) + 1) * s.depth / (nz + 1)
+    c = np.repeat(s.profile()[0][None, :], 8, axis=0)
+    c[4:, (z > 1000.0) & (z < 1500.0)] = 1000.0
+
+    def run(nsteps):
+        pl = ssp.ssp_plan_create(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol)
+        try:
+            ssp.ssp_set_profile(pl, 0, 8, c)
+            ssp.ssp_set_field(pl, s.starter(), s.nz)
+            st, _, _, stats = ssp.ssp_march_batch([pl], [s.nz], nsteps, want_field=False, want_tl=False)
+            return st, stats[0], ssp.ssp_get_field(pl, s.nz)
+        finally:
+            ssp.ssp_plan_destroy(pl)
+
+    st, stats, back = run(8)
+    st4, stats4, good = run(4)
+    _report(f"diverged after unwritten steps nz={nz}", status=st, steps=stats["steps_done"])
+    assert st == ssp.SSP_E_DIVERGED and stats["status"] == ssp.SSP_E_DIVERGED and stats["steps_done"] == 4
+    assert st4 == OK and stats4["steps_done"] == 4
+    assert np.array_equal(back, good)
+    o = OraclePlan(s.nz, s.depth, s.freq, s.c0, s.dr, s.pade_order, s.neumann_max, s.tol)
+    ref = o.march(s.starter(), 8, c, out_every=0)
+    assert ref.status == DIVERGED and ref.steps_done == 4
+    assert np.linalg.norm(back - ref.final) / np.linalg.norm(ref.final) <= 1e-4
+
+
 def test_not_converged_reported(ssp, gpu):
     s = W.munk_deep(nsteps=3, nz=511, neumann_max=3)
     s.out_every = 1
