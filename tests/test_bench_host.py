@@ -41,6 +41,16 @@ def test_measured_traffic_is_keyed_by_grid_and_boundary():
     assert bench.measured_traffic(workload, nz, batch, chunk, "periodic") is None
 
 
+def test_measured_traffic_belongs_to_the_current_sources():
+    # the counter figures in bench.py were taken on the kernels of this tree: the dominant
+    # kernels of the default line (the broadband split group) and of its munk4096 key
+    assert set(bench.TRAFFIC) >= {("broadband", 32768, 150, 40), ("munk4096", 4096, 512, 100)}
+    fp = bench.source_fingerprint()
+    for key, t in bench.TRAFFIC.items():
+        assert t["fingerprint"] == fp, key
+        assert bench.measured_traffic(*key) == t["fetch"] + t["write"] > 0
+
+
 def test_workload_description_names_the_grid():
     assert "Nz=4095" in bench._describe("munk4096", 4095)
     assert "Nz=4096" in bench._describe("munk4096", None)
