@@ -872,10 +872,10 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
     Twiddles<EK> tw;
     init_twiddles<EK>(tw, L.tw4, d.tw, (key_split(EK) && key_var(EK) == 2) ? d.twl2 : d.twl);
 
-    // The state u is not held in registers: d.field holds the state at the start of the
-    // step (the recovery point if the step diverges) and d.work the state between Pade
-    // factors.  Every thread reads and writes only its own positions, so these global
-    // accesses need no barriers.
+    // d.field holds the state at the start of the step (the recovery point if the step
+    // diverges); the state between Pade factors is in registers (kUInRegs) or in d.work.
+    // Every thread reads and writes only its own positions, so these global accesses need
+    // no barriers.
     float2 w[EW], a[RT], A[EA], u[EU];
     float4 Bm[EB];
     long long n = *d.step;
