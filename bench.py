@@ -625,8 +625,9 @@ def main():
 
     extras = {}
     if args.workload == "broadband" and not args.no_extras:
-        # the deep Munk waveguide (Nz = 4096, 512 solves) as a device batch, and the
-        # continuous-batching server on the Poisson stream
+        # the deep Munk waveguide (Nz = 4096, 512 solves) and the Munk + eddy waveguide
+        # (Nz = 16384, 256 solves) as device batches, and the continuous-batching server on
+        # the Poisson stream
         ea = argparse.Namespace(**vars(args))
         ea.workload, ea.nz, ea.bc, ea.absorber = "munk4096", None, "dirichlet", None
         ea.batch, ea.steps, ea.warmup, ea.chunk, ea.plain_steps = 512, 100, 20, 100, 0
@@ -636,6 +637,16 @@ def main():
                               "unit": "field updates/s", "ms_per_step": 1e3 * w2 / c2["range_steps_timed"],
                               "status": s2, "roofline": r2, **c2}
         log(f"munk4096: {u2 / w2:.4g} field updates/s")
+        # the range-dependent Munk + eddy waveguide at Nz = 16384 (potential on the device)
+        eb = argparse.Namespace(**vars(args))
+        eb.workload, eb.nz, eb.bc, eb.absorber = "eddy16384", None, "dirichlet", None
+        eb.batch, eb.steps, eb.warmup, eb.chunk, eb.plain_steps = 256, 50, 10, 50, 0
+        eb.roof_launches = 1
+        u4, w4, r4, c4, s4, _, _ = run_device_batch(eb, ssp, torch, stream, dev)
+        extras["eddy16384"] = {"workload": _describe("eddy16384", None), "value": u4 / w4,
+                               "unit": "field updates/s", "ms_per_step": 1e3 * w4 / c4["range_steps_timed"],
+                               "status": s4, "roofline": r4, **c4}
+        log(f"eddy16384: {u4 / w4:.4g} field updates/s")
         sa = argparse.Namespace(**vars(args))
         sa.workload, sa.batch, sa.chunk = "serving", 1024, 50
         u3, w3, r3, c3, s3, _, _ = run_serving(sa, ssp, torch, stream, dev)
