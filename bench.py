@@ -42,18 +42,21 @@ PEAK_FP32 = 157.3e12   # MI355X published FP32 vector peak (FLOP/s)
 PEAK_HBM = 8.0e12      # MI355X HBM3E (B/s)
 
 # HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc passes (FETCH_SIZE,
-# WRITE_SIZE) of `bench.py [--workload munk4096 --steps 100 | --steps 40] --warmup 40|10
-# --roof-launches 2 --copy-calibration 1024 --no-extras`, averaged over the two roofline
-# launches, each counter scaled by its reading for a plain 1 GiB device copy in the same run
-# (FETCH_SIZE reads 0.5x the bytes moved, WRITE_SIZE 1.0x).  Keyed by the workload's launch
+# WRITE_SIZE) of `bench.py [--steps 40 --warmup 40 | --workload munk4096 --steps 100 --warmup
+# 10 | --workload eddy16384 --steps 50 --warmup 10] --roof-launches 2 --copy-calibration 1024
+# --no-extras`, averaged over the two roofline launches, each counter scaled by its reading
+# for a plain 1 GiB device copy in the same run (FETCH_SIZE reads 0.5x the bytes moved,
+# WRITE_SIZE 1.0x).  Keyed by the workload's launch
 # shape (workload, Nz or FFT length of the dominant group, solves, steps per launch) and a
 # fingerprint of the kernel sources and layout table: any change to their code (comments
 # aside) makes the figure stale, and it is then reported as null.
 TRAFFIC = {
-    ("broadband", 32768, 150, 40): {"fingerprint": "1f92bc374889f51c", "fetch": 6.8110e11,
-                                    "write": 1.7639e11},
-    ("munk4096", 4096, 512, 100): {"fingerprint": "1f92bc374889f51c", "fetch": 3.1071e7,
-                                   "write": 1.7790e9},
+    ("broadband", 32768, 150, 40): {"fingerprint": "469b736312ef0998", "fetch": 4.9360e11,
+                                    "write": 1.7603e11},
+    ("munk4096", 4096, 512, 100): {"fingerprint": "469b736312ef0998", "fetch": 3.1129e7,
+                                   "write": 1.7564e9},
+    ("eddy16384", 16384, 256, 50): {"fingerprint": "469b736312ef0998", "fetch": 8.6209e11,
+                                    "write": 5.8740e11},
 }
 
 

@@ -73,8 +73,8 @@ struct ssp_plan {
     ssp::PadeSet ps;
     ssp::DeviceTables tab;
     // device tables
-    float2 *d_k1 = nullptr, *d_k2 = nullptr, *d_dmod = nullptr, *d_post = nullptr, *d_pre = nullptr;
-    float2 *d_k1i = nullptr, *d_k2i = nullptr, *d_postf = nullptr;  // only where they differ
+    float2 *d_k1 = nullptr, *d_k2 = nullptr, *d_kph = nullptr, *d_dmod = nullptr, *d_post = nullptr, *d_pre = nullptr;
+    float2 *d_k1i = nullptr, *d_postf = nullptr;  // only where they differ
     float4 *d_mirror = nullptr;         // odd-extension image factors (direct sine transform)
     const float4 *d_twl = nullptr;      // shared last-pass twiddles of 1024-thread engines (not owned)
     const float4 *d_twl2 = nullptr;     // ... of the layout-2 split engine (split plans; not owned)
@@ -245,8 +245,8 @@ void free_side_streams(ssp_plan *pl) {
 void free_tables(ssp_plan *pl) {
     dev_free(pl->d_k1);
     dev_free(pl->d_k2);
+    dev_free(pl->d_kph);
     dev_free(pl->d_k1i);
-    dev_free(pl->d_k2i);
     dev_free(pl->d_postf);
     dev_free(pl->d_mirror);
     dev_free(pl->d_dmod);
@@ -281,7 +281,8 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     free_tables(pl);
     const int N = pl->N, P = tab.P, p = ps.p;
     HIP_TRY(dev_alloc(&pl->d_k1, tab.k1.size() / 2));   // [P], none for direct transforms
-    HIP_TRY(dev_alloc(&pl->d_k2, tab.k2.size() / 2));
+    HIP_TRY(dev_alloc(&pl->d_k2, tab.k2.size() / 2));    // unsplit lengths
+    HIP_TRY(dev_alloc(&pl->d_kph, tab.kph.size() / 2));  // split lengths
     HIP_TRY(dev_alloc(&pl->d_tw, tab.twiddle.size()));
     HIP_TRY(dev_alloc(&pl->d_dmod, N));
     HIP_TRY(dev_alloc(&pl->d_post, N));
@@ -292,15 +293,14 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     HIP_TRY(dev_alloc(&pl->d_beta, p));
     HIP_TRY(dev_alloc(&pl->d_twist, tab.twist.size() / 4));
     HIP_TRY(dev_alloc(&pl->d_k1i, tab.k1i.size() / 2));
-    HIP_TRY(dev_alloc(&pl->d_k2i, tab.k2i.size() / 2));
     HIP_TRY(dev_alloc(&pl->d_postf, tab.postf.size() / 2));
     if (!tab.k1i.empty()) HIP_TRY(upload(pl->d_k1i, tab.k1i));
-    if (!tab.k2i.empty()) HIP_TRY(upload(pl->d_k2i, tab.k2i));
     if (!tab.postf.empty()) HIP_TRY(upload(pl->d_postf, tab.postf));
     HIP_TRY(dev_alloc(&pl->d_mirror, tab.mirror.size() / 4));
     if (!tab.mirror.empty()) HIP_TRY(upload(pl->d_mirror, tab.mirror));
     if (!tab.k1.empty()) HIP_TRY(upload(pl->d_k1, tab.k1));
     if (!tab.k2.empty()) HIP_TRY(upload(pl->d_k2, tab.k2));
+    if (!tab.kph.empty()) HIP_TRY(upload(pl->d_kph, tab.kph));
     HIP_TRY(upload(pl->d_tw, tab.twiddle));
     HIP_TRY(ssp::last_twiddles(P, pl->d_tw, &pl->d_twl));
     // split plans: their octant table is that of the 16384-point engine, whose layout-2 table
@@ -343,8 +343,9 @@ int effective_variant(const ssp_plan *pl) {
 
 ssp::SolveDesc base_desc(const ssp_plan *pl) {
     ssp::SolveDesc d{};
-    d.kf = ssp::KWin{pl->d_k1, pl->d_k2};
-    d.ki = ssp::KWin{pl->d_k1i ? pl->d_k1i : pl->d_k1, pl->d_k2i ? pl->d_k2i : pl->d_k2};
+    const float sg = static_cast<float>(pl->tab.ksign);
+    d.kf = ssp::KWin{pl->d_k1, pl->d_k2, pl->d_kph, sg, nullptr};
+    d.ki = ssp::KWin{pl->d_k1i ? pl->d_k1i : pl->d_k1, pl->d_k2, pl->d_kph, sg, nullptr};
     d.tw = pl->d_tw;
     d.twl = pl->d_twl;
     d.twl2 = pl->d_twl2;
@@ -381,6 +382,20 @@ ssp::SolveDesc base_desc(const ssp_plan *pl) {
     d.tmul = pl->d_tmul;
     d.mmod = pl->d_mmod;
     d.engine = effective_engine(pl);
+    // split lengths: Hankel phase steps w^{s D i} of the march's layout and of layout 0
+    // (D = twice the layout's thread count; see SolveDesc)
+    auto phase_steps = [&](float2 *h, int variant) {
+        const long long P = pl->P, s = pl->N - 1, D = 2LL * ssp::engine_threads(pl->P, variant);
+        for (int i = 0; i < 16; ++i) {
+            const long long r = (((s % P) + P) % P) * ((D * i) % P) % P;
+            const double ang = -2.0 * M_PI * static_cast<double>(r) / static_cast<double>(P);
+            h[i] = make_float2(static_cast<float>(std::cos(ang)), static_cast<float>(std::sin(ang)));
+        }
+    };
+    if (pl->P > ssp::kMaxEngineFFT && !pl->tab.direct) {
+        phase_steps(d.hstep, d.variant);
+        phase_steps(d.hstep0, 0);
+    }
     return d;
 }
 

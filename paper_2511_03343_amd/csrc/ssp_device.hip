@@ -544,10 +544,25 @@ __device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, c
 
 // Z_q = Y_q K1_q - Y_{-q} K2_q for the distributed spectrum (one LDS exchange, phase PH).
 // ODD: the odd-frequency half of a split transform, whose reflection is q -> P-1-q.
+// Unsplit lengths read both spectra.  A split half derives K2 from K1 (the Hankel spectra of
+// the many plans of a batch do not stay in the L2, and every spectrum value read there costs
+// fabric traffic): K2_q = phi w^{s q} K1_{q + L/2} (L the convolution length, w = exp(-2 pi
+// i/L); see KWin), and spectrum position q + L/2 (same parity as q) is the thread's own
+// element i + RT/2, so each K1 value read serves two elements.  The phase of element i is the
+// thread's base phase (two entries of the phase table) times the step w^{s 2T i} from the
+// descriptor; element i + RT/2 takes sign (-1)^s times that phase.
 template <int P, int PH, bool ODD>
 __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, KWin k) {
-    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT;
+    constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT, H2 = RT / 2;
+    constexpr bool SPLIT = key_split(P);
+    static_assert(!SPLIT || (RT % 2 == 0 && H2 <= 16 && (2 * T) % 64 == 0), "element pairs, phase steps");
     const int tid = opaque_tid();
+    float2 base = make_float2(0.f, 0.f);
+    if constexpr (SPLIT) {
+        // phase of element 0 (frequency 2 tid + ODD), read before the exchange
+        const int q0 = 2 * tid + (ODD ? 1 : 0);
+        base = cmul(ld2(k.kph, q0 & 63), ld2(k.kph, 64 + (q0 >> 6)));
+    }
     before_write<P>();
     float2 *buf = phase_buf<P, PH>(L);
     // unit-stride exchange: no padding
@@ -564,12 +579,24 @@ __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const Lds
     const int u = ODD ? (T - 1 - t2) : ((T - t2) & (T - 1));
     const int c = ODD ? 0 : (t2 == 0 ? 1 : 0);
     const float2 *rb = buf + u + c * T;
+    auto refl = [&](int i) -> float2 {
+        if (!ODD && i == 0) return c ? buf[0] : rb[(RT - 1) * T];
+        return rb[(RT - 1 - i) * T];
+    };
+    if constexpr (SPLIT) {
 #pragma unroll
-    for (int i = 0; i < RT; ++i) {
-        float2 yr;
-        if (!ODD && i == 0) yr = c ? buf[0] : rb[(RT - 1) * T];
-        else yr = rb[(RT - 1 - i) * T];
-        x[i] = csub(cmul(x[i], ld2s(k.k1, t2, i * T)), cmul(yr, ld2s(k.k2, t2, i * T)));
+        for (int i = 0; i < H2; ++i) {
+            const float2 ph = i == 0 ? base : cmul(base, k.hs[i]);
+            const float2 phb = make_float2(k.sg * ph.x, k.sg * ph.y);
+            const float2 ka = ld2s(k.k1, t2, i * T), kb = ld2s(k.k1, t2, (i + H2) * T);
+            const float2 ya = refl(i), yb = refl(i + H2);
+            x[i] = csub(cmul(x[i], ka), cmul(ya, cmul(ph, kb)));
+            x[i + H2] = csub(cmul(x[i + H2], kb), cmul(yb, cmul(phb, ka)));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+            x[i] = csub(cmul(x[i], ld2s(k.k1, t2, i * T)), cmul(refl(i), ld2s(k.k2, t2, i * T)));
     }
 }
 
@@ -663,6 +690,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
                                          KWin k) {
     constexpr int H = eng_len<P>();
     constexpr int EK = eng_key<P, V>();
+    k.hs = V == 0 ? d.hstep0 : d.hstep;  // (split lengths)
     if constexpr (H == P) {
         chirp_core<EK, false, true>(x, L, tw, k);
     } else {
@@ -696,7 +724,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
                 if (pos < N) st2(keep + N, pos, x[i]);
                 x[i] = pos < N ? ld2(keep, pos) : make_float2(0.f, 0.f);
             }
-            chirp_core<EK, true>(x, L, tw, KWin{k.k1 + H, k.k2 + H});
+            chirp_core<EK, true>(x, L, tw, KWin{k.k1 + H, nullptr, k.kph, k.sg, k.hs});
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T;
@@ -704,7 +732,7 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
                                : make_float2(0.f, 0.f);
             }
         } else {
-            chirp_core<EK, true>(y, L, tw, KWin{k.k1 + H, k.k2 + H});
+            chirp_core<EK, true>(y, L, tw, KWin{k.k1 + H, nullptr, k.kph, k.sg, k.hs});
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T;

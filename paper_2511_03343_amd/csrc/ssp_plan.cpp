@@ -337,7 +337,8 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
     t.k1.clear();
     t.k2.clear();
     t.k1i.clear();
-    t.k2i.clear();
+    t.kph.clear();
+    t.ksign = 1;
     if (direct == kDirectNone) {
         std::vector<cd> K1(P, 0.0), K2(P, 0.0);
         for (long long d = 1 - N; d <= N - 1; ++d) K1[((d % P) + P) % P] = chirp(d);
@@ -349,11 +350,28 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
             for (long long d = 0; d <= 2LL * N - 2; ++d) K2[d % P] = -chirp(d);
         }
         t.k1 = to_f32(window_spectrum(K1, P, split));
-        t.k2 = to_f32(window_spectrum(K2, P, split));
+        if (!split) {
+            t.k2 = to_f32(window_spectrum(K2, P, false));
+        } else {
+            // split lengths: the phase that derives K2 from K1 (zero: no Hankel window)
+            t.kph.assign(2 * (64 + static_cast<size_t>(P) / 64), 0.f);
+            if (bc != kBcPeriodic) {
+                const long long M = D / 2, s = N - 1;
+                static const cd quarter[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
+                const cd phi = (bc == kBcNeumann ? -1.0 : 1.0) * quarter[M % 4];  // e^{i pi M/2}
+                auto wp = [&](long long j) {  // exp(-2 pi i j / P), j reduced exactly
+                    const long long r = ((j % P) + P) % P;
+                    const double ang = -2.0 * kPiD * static_cast<double>(r) / P;
+                    return cd(std::cos(ang), std::sin(ang));
+                };
+                for (int k = 0; k < 64; ++k) put_c(t.kph, k, phi * wp(s * k));
+                for (int m = 0; m < P / 64; ++m) put_c(t.kph, 64 + m, wp(64 * s * m));
+                t.ksign = (s % 2 == 0) ? 1 : -1;
+            }
+        }
         if (bc == kBcPeriodic) {
             for (long long d = 1 - N; d <= N - 1; ++d) K1[((d % P) + P) % P] = std::conj(chirp(d));
             t.k1i = to_f32(window_spectrum(K1, P, split));
-            t.k2i = t.k2;  // zero
         }
     }
     t.twist.clear();

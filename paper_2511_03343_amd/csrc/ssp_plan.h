@@ -68,16 +68,23 @@ struct DeviceTables {
     // chirp-z transform of length nz through a cyclic convolution of length P, with the
     // chirp c_d = exp(i pi d^2 / D) (D = 2(nz+1) sine, 2(nz-1) cosine, nz Fourier):
     // [P] complex FP32 spectra of the two chirp windows, Toeplitz c_d (d in [1-nz, nz-1])
-    // and Hankel (d in [0, 2nz-2]: c_{d+2} for the sine transform, whose element n sits
-    // at position n-1, and -c_d for the cosine transform; zero for the Fourier
-    // transform).  k1/k2 serve the forward direction (grid values -> coefficients);
-    // k1i/k2i, when not empty, the inverse direction (the Fourier transform only; the sine
-    // and cosine transforms are their own inverses).  For P > kMaxEngineFFT they are stored
-    // as the even frequencies followed by the odd ones (the two halves of a split
-    // transform).  Their FP32 rounding is a fixed perturbation of every transform, but the
-    // transforms only carry the Neumann terms (the isovelocity part of each factor is a
-    // double-float product in the sine basis), where it stays below the other roundings.
-    std::vector<float> k1, k2, k1i, k2i;
+    // and Hankel (d in [0, 2nz-2]: c_{d+2} for the sine transform, whose element n sits at
+    // position n-1, and -c_d for the cosine transform; zero for the Fourier transform).
+    // k1/k2 serve the forward direction (grid values -> coefficients); k1i, when not empty,
+    // the inverse direction (the Fourier transform only, whose Hankel window is zero both
+    // ways; the sine and cosine transforms are their own inverses).  For P > kMaxEngineFFT
+    // k1 is stored as the even frequencies followed by the odd ones (the two halves of a split
+    // transform), and k2 is not stored: the chirp is even about M = D/2 up to a sign pattern,
+    // c_{M+e} = e^{i pi M/2} (-1)^e c_e, so the Hankel window is the Toeplitz window moved by
+    // s = nz - 1 positions and modulated by (-1)^e, and K2_q = phi w^{s q} K1_{q + P/2} with
+    // w = exp(-2 pi i/P) and phi = e^{i pi M/2} (sine) or -e^{i pi M/2} (cosine).  kph holds
+    // that phase as [64 + P/64] complex FP32: phi w^{s k} for k < 64, then w^{64 s m} for
+    // m < P/64 (the device multiplies one of each; all zero for the Fourier transform);
+    // ksign = (-1)^s.  The FP32 roundings are a fixed perturbation of every transform, but
+    // the transforms only carry the Neumann terms (the isovelocity part of each factor is a
+    // double-float product in the sine basis), where they stay below the other roundings.
+    std::vector<float> k1, k2, k1i, kph;
+    int ksign = 1;
     std::vector<float> pre;           // [nz] complex FP32 forward pre-modulation
     std::vector<float> post;          // [nz] complex FP32 inverse post-modulation (incl. 1/P)
     std::vector<float> postf;         // [nz] forward post-modulation, when it differs from post

@@ -43,8 +43,10 @@ def test_measured_traffic_is_keyed_by_grid_and_boundary():
 
 def test_measured_traffic_belongs_to_the_current_sources():
     # the counter figures in bench.py were taken on the kernels of this tree: the dominant
-    # kernels of the default line (the broadband split group) and of its munk4096 key
-    assert set(bench.TRAFFIC) >= {("broadband", 32768, 150, 40), ("munk4096", 4096, 512, 100)}
+    # kernels of the default line (the broadband split group) and of its munk4096 and
+    # eddy16384 keys
+    assert set(bench.TRAFFIC) >= {("broadband", 32768, 150, 40), ("munk4096", 4096, 512, 100),
+                                  ("eddy16384", 16384, 256, 50)}
     fp = bench.source_fingerprint()
     for key, t in bench.TRAFFIC.items():
         assert t["fingerprint"] == fp, key
