@@ -73,7 +73,8 @@ struct ssp_plan {
     ssp::PadeSet ps;
     ssp::DeviceTables tab;
     // device tables
-    float2 *d_k1 = nullptr, *d_k2 = nullptr, *d_kph = nullptr, *d_dmod = nullptr, *d_post = nullptr, *d_pre = nullptr;
+    float4 *d_kph = nullptr;  // split lengths: the phase table of the derived Hankel spectrum
+    float2 *d_k1 = nullptr, *d_k2 = nullptr, *d_dmod = nullptr, *d_post = nullptr, *d_pre = nullptr;
     float2 *d_k1i = nullptr, *d_postf = nullptr;  // only where they differ
     float4 *d_mirror = nullptr;         // odd-extension image factors (direct sine transform)
     const float4 *d_twl = nullptr;      // shared last-pass twiddles of 1024-thread engines (not owned)
@@ -282,7 +283,7 @@ ssp_status build_plan_tables(ssp_plan *pl) {
     const int N = pl->N, P = tab.P, p = ps.p;
     HIP_TRY(dev_alloc(&pl->d_k1, tab.k1.size() / 2));   // [P], none for direct transforms
     HIP_TRY(dev_alloc(&pl->d_k2, tab.k2.size() / 2));    // unsplit lengths
-    HIP_TRY(dev_alloc(&pl->d_kph, tab.kph.size() / 2));  // split lengths
+    HIP_TRY(dev_alloc(&pl->d_kph, tab.kph.size() / 4));  // split lengths
     HIP_TRY(dev_alloc(&pl->d_tw, tab.twiddle.size()));
     HIP_TRY(dev_alloc(&pl->d_dmod, N));
     HIP_TRY(dev_alloc(&pl->d_post, N));
@@ -384,12 +385,15 @@ ssp::SolveDesc base_desc(const ssp_plan *pl) {
     d.engine = effective_engine(pl);
     // split lengths: Hankel phase steps w^{s D i} of the march's layout and of layout 0
     // (D = twice the layout's thread count; see SolveDesc)
-    auto phase_steps = [&](float2 *h, int variant) {
+    auto phase_steps = [&](float4 *h, int variant) {
         const long long P = pl->P, s = pl->N - 1, D = 2LL * ssp::engine_threads(pl->P, variant);
         for (int i = 0; i < 16; ++i) {
             const long long r = (((s % P) + P) % P) * ((D * i) % P) % P;
             const double ang = -2.0 * M_PI * static_cast<double>(r) / static_cast<double>(P);
-            h[i] = make_float2(static_cast<float>(std::cos(ang)), static_cast<float>(std::sin(ang)));
+            float f[4];
+            ssp::split_df(std::cos(ang), f[0], f[2]);
+            ssp::split_df(std::sin(ang), f[1], f[3]);
+            h[i] = make_float4(f[0], f[1], f[2], f[3]);
         }
     };
     if (pl->P > ssp::kMaxEngineFFT && !pl->tab.direct) {

@@ -25,13 +25,15 @@ enum ProfileMode : int { PROF_TABLE_FIXED = 0, PROF_TABLE_STEPS = 1, PROF_ANALYT
 // The chirp-window spectra of one transform direction: K1, the Toeplitz spectrum ([P] complex
 // FP32), and for unsplit lengths K2, the Hankel spectrum ([P]).  Split lengths derive K2 from
 // K1 (see DeviceTables::kph): K2_q = phi w^{s q} K1_{q + P/2} (w = exp(-2 pi i/P), s = Nz - 1),
-// with kph[k] = phi w^{s k} for k < 64, then kph[64 + m] = w^{64 s m} for m < P/64 (zero for
-// the Fourier transform: no Hankel window), sg = (-1)^s and hs the phase steps of the engine
-// layout that runs the transform (SolveDesc::hstep, set on the device).
+// with kph[k] = phi w^{s k} for k < 64, then kph[64 + m] = w^{64 s m} for m < P/64 (double-
+// float; zero for the Fourier transform: no Hankel window), sg = (-1)^s and hs the
+// double-float phase steps of the engine layout that runs the transform (SolveDesc::hstep,
+// set on the device).
 struct KWin {
-    const float2 *k1, *k2, *kph;
+    const float2 *k1, *k2;
+    const float4 *kph;
     float sg;
-    const float2 *hs;
+    const float4 *hs;
 };
 
 struct SolveDesc {
@@ -83,10 +85,11 @@ struct SolveDesc {
                                 //     coefficients), |m| = 1
     int engine;                 // 0 FFT engine, 1 dense engine (host grouping only)
     // split lengths: Hankel phase steps w^{s D i} (i < 16, w = exp(-2 pi i/P), s = N - 1; see
-    // KWin) between the elements of one thread of a split half, D = twice the thread count
-    // of an engine layout: hstep for the march's layout, hstep0 for layout 0 (the transform,
-    // output and plain-form kernels).  Read through the descriptor, they are scalar loads.
-    float2 hstep[16], hstep0[16];
+    // KWin; double-float) between the elements of one thread of a split half, D = twice the
+    // thread count of an engine layout: hstep for the march's layout, hstep0 for layout 0
+    // (the transform, output and plain-form kernels).  Read through the descriptor, they are
+    // scalar loads.
+    float4 hstep[16], hstep0[16];
 };
 
 // Device statuses besides the ssp_status codes they share: a march step whose tabulated

@@ -549,8 +549,9 @@ __device__ __forceinline__ void fft(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, c
 // fabric traffic): K2_q = phi w^{s q} K1_{q + L/2} (L the convolution length, w = exp(-2 pi
 // i/L); see KWin), and spectrum position q + L/2 (same parity as q) is the thread's own
 // element i + RT/2, so each K1 value read serves two elements.  The phase of element i is the
-// thread's base phase (two entries of the phase table) times the step w^{s 2T i} from the
-// descriptor; element i + RT/2 takes sign (-1)^s times that phase.
+// thread's base phase (the product of two double-float entries of the phase table, rounded
+// once) times the double-float step w^{s 2T i} from the descriptor; element i + RT/2 takes
+// sign (-1)^s times that phase.  No FP32 rounding is shared by many spectrum positions.
 template <int P, int PH, bool ODD>
 __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const LdsBufs &L, KWin k) {
     constexpr int T = Cfg<P>::T, RT = Cfg<P>::RT, H2 = RT / 2;
@@ -561,7 +562,9 @@ __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const Lds
     if constexpr (SPLIT) {
         // phase of element 0 (frequency 2 tid + ODD), read before the exchange
         const int q0 = 2 * tid + (ODD ? 1 : 0);
-        base = cmul(ld2(k.kph, q0 & 63), ld2(k.kph, 64 + (q0 >> 6)));
+        const float4 a = ld4(k.kph, q0 & 63), b = ld4(k.kph, 64 + (q0 >> 6));
+        // (a.hi + a.lo)(b.hi + b.lo) without the lo * lo term
+        base = cadd(cmul_df(make_float2(a.x, a.y), b), cmul(make_float2(a.z, a.w), make_float2(b.x, b.y)));
     }
     before_write<P>();
     float2 *buf = phase_buf<P, PH>(L);
@@ -586,7 +589,7 @@ __device__ __forceinline__ void chirp_combine(float2 (&x)[Cfg<P>::RT], const Lds
     if constexpr (SPLIT) {
 #pragma unroll
         for (int i = 0; i < H2; ++i) {
-            const float2 ph = i == 0 ? base : cmul(base, k.hs[i]);
+            const float2 ph = i == 0 ? base : cmul_df(base, k.hs[i]);
             const float2 phb = make_float2(k.sg * ph.x, k.sg * ph.y);
             const float2 ka = ld2s(k.k1, t2, i * T), kb = ld2s(k.k1, t2, (i + H2) * T);
             const float2 ya = refl(i), yb = refl(i + H2);

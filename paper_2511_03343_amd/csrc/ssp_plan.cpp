@@ -354,7 +354,7 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
             t.k2 = to_f32(window_spectrum(K2, P, false));
         } else {
             // split lengths: the phase that derives K2 from K1 (zero: no Hankel window)
-            t.kph.assign(2 * (64 + static_cast<size_t>(P) / 64), 0.f);
+            t.kph.assign(4 * (64 + static_cast<size_t>(P) / 64), 0.f);
             if (bc != kBcPeriodic) {
                 const long long M = D / 2, s = N - 1;
                 static const cd quarter[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
@@ -364,8 +364,12 @@ void build_tables(int nz, double depth, double k0, const PadeSet &ps, int bc, De
                     const double ang = -2.0 * kPiD * static_cast<double>(r) / P;
                     return cd(std::cos(ang), std::sin(ang));
                 };
-                for (int k = 0; k < 64; ++k) put_c(t.kph, k, phi * wp(s * k));
-                for (int m = 0; m < P / 64; ++m) put_c(t.kph, 64 + m, wp(64 * s * m));
+                auto put = [&](int e, cd z) {  // double-float complex entry e
+                    split_df(z.real(), t.kph[4 * e], t.kph[4 * e + 2]);
+                    split_df(z.imag(), t.kph[4 * e + 1], t.kph[4 * e + 3]);
+                };
+                for (int k = 0; k < 64; ++k) put(k, phi * wp(s * k));
+                for (int m = 0; m < P / 64; ++m) put(64 + m, wp(64 * s * m));
                 t.ksign = (s % 2 == 0) ? 1 : -1;
             }
         }

@@ -78,11 +78,15 @@ struct DeviceTables {
     // c_{M+e} = e^{i pi M/2} (-1)^e c_e, so the Hankel window is the Toeplitz window moved by
     // s = nz - 1 positions and modulated by (-1)^e, and K2_q = phi w^{s q} K1_{q + P/2} with
     // w = exp(-2 pi i/P) and phi = e^{i pi M/2} (sine) or -e^{i pi M/2} (cosine).  kph holds
-    // that phase as [64 + P/64] complex FP32: phi w^{s k} for k < 64, then w^{64 s m} for
-    // m < P/64 (the device multiplies one of each; all zero for the Fourier transform);
-    // ksign = (-1)^s.  The FP32 roundings are a fixed perturbation of every transform, but
-    // the transforms only carry the Neumann terms (the isovelocity part of each factor is a
-    // double-float product in the sine basis), where they stay below the other roundings.
+    // that phase as [64 + P/64] double-float complex: phi w^{s k} for k < 64, then w^{64 s m}
+    // for m < P/64 (the device multiplies one of each; all zero for the Fourier transform);
+    // ksign = (-1)^s.  Double-float, because every entry is shared by many spectrum
+    // positions: an FP32 rounding there is a common relative error of a structured set of
+    // K2 values, and the march accumulates it coherently (in FP32 the broadband 300 Hz
+    // field drifted 3x faster).  The FP32 roundings of K1, K2 themselves are independent per
+    // position, a fixed perturbation of every transform that stays below the other
+    // roundings (the transforms only carry the Neumann terms; the isovelocity part of each
+    // factor is a double-float product in the sine basis).
     std::vector<float> k1, k2, k1i, kph;
     int ksign = 1;
     std::vector<float> pre;           // [nz] complex FP32 forward pre-modulation

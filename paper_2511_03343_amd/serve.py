@@ -105,7 +105,7 @@ def plan_device_bytes(nz: int, pade_order: int, out_rows: int) -> int:
     potential, field and per-solve scratch, and output staging for out_rows rows."""
     P = fft_length(nz)
     PE = P // 2 if P > 16384 else P
-    tables = (8 * P + 8 * (64 + P // 64) if P > 16384 else 2 * 8 * P) + 12 * (PE // 8 + 1) + 3 * 8 * nz + 3 * 16 * pade_order * nz + 16 * pade_order
+    tables = (8 * P + 16 * (64 + P // 64) if P > 16384 else 2 * 8 * P) + 12 * (PE // 8 + 1) + 3 * 8 * nz + 3 * 16 * pade_order * nz + 16 * pade_order
     if P > 16384:
         tables += 16 * (P // 2)
     state = 4 * nz + 8 * nz + 5 * 8 * nz + 8 + 48 + 512
