@@ -51,12 +51,12 @@ PEAK_HBM = 8.0e12      # MI355X HBM3E (B/s)
 # fingerprint of the kernel sources and layout table: any change to their code (comments
 # aside) makes the figure stale, and it is then reported as null.
 TRAFFIC = {
-    ("broadband", 32768, 150, 40): {"fingerprint": "06034a89e4a640e6", "fetch": 4.9430e11,
-                                    "write": 1.7599e11},
-    ("munk4096", 4096, 512, 100): {"fingerprint": "06034a89e4a640e6", "fetch": 5.0009e7,
-                                   "write": 1.7776e9},
-    ("eddy16384", 16384, 256, 50): {"fingerprint": "06034a89e4a640e6", "fetch": 8.6426e11,
-                                    "write": 5.8735e11},
+    ("broadband", 32768, 150, 40): {"fingerprint": "0172813ed0d85ea7", "fetch": 4.9476e11,
+                                    "write": 1.7600e11},
+    ("munk4096", 4096, 512, 100): {"fingerprint": "0172813ed0d85ea7", "fetch": 3.1469e7,
+                                   "write": 1.7557e9},
+    ("eddy16384", 16384, 256, 50): {"fingerprint": "0172813ed0d85ea7", "fetch": 8.6699e11,
+                                    "write": 5.8738e11},
 }
 
 
