@@ -51,12 +51,12 @@ PEAK_HBM = 8.0e12      # MI355X HBM3E (B/s)
 # fingerprint of the kernel sources and layout table: any change to their code (comments
 # aside) makes the figure stale, and it is then reported as null.
 TRAFFIC = {
-    ("broadband", 32768, 150, 40): {"fingerprint": "0172813ed0d85ea7", "fetch": 4.9476e11,
-                                    "write": 1.7600e11},
-    ("munk4096", 4096, 512, 100): {"fingerprint": "0172813ed0d85ea7", "fetch": 3.1469e7,
-                                   "write": 1.7557e9},
-    ("eddy16384", 16384, 256, 50): {"fingerprint": "0172813ed0d85ea7", "fetch": 8.6699e11,
-                                    "write": 5.8738e11},
+    ("broadband", 32768, 150, 40): {"fingerprint": "33ac4eeccc09bd85", "fetch": 5.5951e11,
+                                    "write": 2.3548e11},
+    ("munk4096", 4096, 512, 100): {"fingerprint": "33ac4eeccc09bd85", "fetch": 3.0071e7,
+                                   "write": 1.6500e9},
+    ("eddy16384", 16384, 256, 50): {"fingerprint": "33ac4eeccc09bd85", "fetch": 8.6894e11,
+                                    "write": 5.8745e11},
 }
 
 

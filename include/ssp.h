@@ -323,7 +323,8 @@ ssp_status ssp_march_device(ssp_plan *plan, int B, void *d_psi, void *d_step, in
  * fixed device array of SSP_NOALLOC_SCRATCH_MIB MiB that the library holds on each device
  * it runs on until the process ends.  The call allocates nothing, copies nothing from the
  * host (the descriptors are written by a kernel) and is asynchronous on the plan's stream.
- * A batch whose scratch exceeds the array (about 5 Nz B complex values plus Nz B
+ * A batch whose scratch exceeds the array (5 S B complex values, S = P/2 >= Nz for the
+ * plan's FFT length P, or S = Nz for a periodic grid whose length is an FFT length, plus Nz B
  * (nsteps/out_every + 1) for TL outputs) is rejected with SSP_E_INVAL; dense-engine plans
  * with SSP_E_UNIMPL.  Every call on a device shares that device's array, which keeps the
  * last call's contents: calls that overlap in time on one device (other streams, other

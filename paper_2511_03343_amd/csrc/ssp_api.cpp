@@ -99,7 +99,7 @@ struct ssp_plan {
     // batched descriptors (device-resident march)
     ssp::SolveDesc *d_descs = nullptr;
     int descs_cap = 0;
-    float2 *d_bwork = nullptr;          // scratch of a device batch [cap][kWorkPerSolve N]
+    float2 *d_bwork = nullptr;          // scratch of a device batch [cap][solve_work_elems]
     int bwork_cap = 0;
     float2 *d_snap = nullptr;           // output snapshots of a device batch
     size_t snap_cap = 0;
@@ -342,6 +342,11 @@ int effective_variant(const ssp_plan *pl) {
     return ssp::engine_variant_exists(pl->P, v) ? v : 0;
 }
 
+// Complex scratch elements of one solve's march (see ssp::set_work).
+size_t solve_work_elems(const ssp_plan *pl) {
+    return ssp::kWorkPerSolve * ssp::work_stride(pl->P, pl->tab.direct);
+}
+
 ssp::SolveDesc base_desc(const ssp_plan *pl) {
     ssp::SolveDesc d{};
     const float sg = static_cast<float>(pl->tab.ksign);
@@ -554,7 +559,7 @@ ssp_status ssp_plan_create_bc(int Nz, double H, double f, double c0, double dr, 
     if (st == SSP_OK) {
         hipError_t e = hipSuccess;
         if (e == hipSuccess) e = dev_alloc(&pl->d_field, Nz);
-        if (e == hipSuccess) e = dev_alloc(&pl->d_work, ssp::kWorkPerSolve * static_cast<size_t>(Nz));
+        if (e == hipSuccess) e = dev_alloc(&pl->d_work, solve_work_elems(pl));
         if (e == hipSuccess) e = dev_alloc(&pl->d_step, 1);
         if (e == hipSuccess) e = dev_alloc(&pl->d_stats, 1);
         if (e == hipSuccess) e = dev_alloc(&pl->d_desc, 1);
@@ -1227,7 +1232,7 @@ ssp_status march_batch_impl(ssp_plan *const *plans, int n, const int *steps, dou
 }
 
 // Descriptors of a device-resident batch of B solves of one plan (ssp_march_device and its
-// no-allocation variant): scratch base (kWorkPerSolve N per solve), stats (d_stats or
+// no-allocation variant): scratch base (solve_work_elems per solve), stats (d_stats or
 // stats_base), snapshots (snap_base, nout rows per solve) and TL rows (d_tl).
 std::vector<ssp::SolveDesc> device_descs(const ssp_plan *pl, int B, void *d_psi, void *d_step, int nsteps, int nout,
                                          void *d_tl, void *d_stats, float2 *work_base, ssp::DevStats *stats_base,
@@ -1236,7 +1241,7 @@ std::vector<ssp::SolveDesc> device_descs(const ssp_plan *pl, int B, void *d_psi,
     for (int b = 0; b < B; ++b) {
         ssp::SolveDesc d = base_desc(pl);
         d.field = static_cast<float2 *>(d_psi) + static_cast<size_t>(b) * pl->N;
-        ssp::set_work(d, work_base + ssp::kWorkPerSolve * static_cast<size_t>(b) * pl->N);
+        ssp::set_work(d, work_base + solve_work_elems(pl) * static_cast<size_t>(b));
         d.nout = nout;
         d.nsteps = nsteps;
         d.step = static_cast<long long *>(d_step) + b;
@@ -1414,7 +1419,7 @@ ssp_status ssp_march_device(ssp_plan *pl, int B, void *d_psi, void *d_step, int 
     if (pl->bwork_cap < B) {
         dev_free(pl->d_bwork);
         pl->bwork_cap = 0;
-        HIP_TRY(dev_alloc(&pl->d_bwork, ssp::kWorkPerSolve * static_cast<size_t>(B) * pl->N));
+        HIP_TRY(dev_alloc(&pl->d_bwork, solve_work_elems(pl) * static_cast<size_t>(B)));
         pl->bwork_cap = B;
     }
     if (!d_stats && pl->bstats_cap < B) {
@@ -1500,10 +1505,11 @@ __global__ void k_fill_descs(ssp::SolveDesc tmpl, int B, float2 *psi, long long 
     const size_t N = static_cast<size_t>(tmpl.N), bb = static_cast<size_t>(b);
     ssp::SolveDesc d = tmpl;
     d.field = psi + bb * N;
-    d.work = work + ssp::kWorkPerSolve * bb * N;
-    d.pot = d.work + N;
-    d.wacc = d.work + 2 * N;
-    d.xs = d.work + 3 * N;
+    const size_t S = ssp::work_stride(tmpl.P, tmpl.direct);
+    d.work = work + ssp::kWorkPerSolve * bb * S;
+    d.pot = d.work + S;
+    d.wacc = d.work + 2 * S;
+    d.xs = d.work + 3 * S;
     d.step = step + b;
     d.stats = stats + b;
     d.fld_out = nullptr;
@@ -1525,7 +1531,7 @@ ssp_status ssp_march_device_noalloc(ssp_plan *pl, int B, void *d_psi, void *d_st
     // scratch layout: descriptors, per-solve work, statistics (when the caller passes none),
     // output snapshots
     const size_t desc_bytes = round256(sizeof(ssp::SolveDesc) * static_cast<size_t>(B));
-    const size_t work_bytes = round256(sizeof(float2) * ssp::kWorkPerSolve * static_cast<size_t>(B) * pl->N);
+    const size_t work_bytes = round256(sizeof(float2) * solve_work_elems(pl) * static_cast<size_t>(B));
     const size_t stats_bytes = d_stats ? 0 : round256(sizeof(ssp::DevStats) * static_cast<size_t>(B));
     const size_t snap_bytes = outputs ? round256(sizeof(float2) * static_cast<size_t>(B) * nout * pl->N) : 0;
     const size_t need = desc_bytes + work_bytes + stats_bytes + snap_bytes;

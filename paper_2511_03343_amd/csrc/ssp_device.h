@@ -67,7 +67,7 @@ struct SolveDesc {
     float2 *pot;                // [N] scratch potential A = v (.) dmod of the current step
     float2 *wacc;               // [N] scratch Neumann sum beyond the first term (kernels that do
                                 //     not hold it in registers)
-    float2 *xs;                 // [2N] scratch of split transforms
+    float2 *xs;                 // [2][work_stride] scratch of split transforms
     long long *step;            // global step counter
     DevStats *stats;
     float2 *snap;               // [nout][N] sine-basis snapshots at output steps, or null
@@ -101,13 +101,22 @@ constexpr int kStatusProfileRange = -1;
 // launch).  direct: the plans' direct transform kind (0: chirp-z cores; 1: periodic grid of
 // length P, FFTs; 2: Dirichlet grid of length P/2 - 1, the FFT of the odd extension;
 // P <= 16384 for both).  Returns hipSuccess or the launch error.
-// Scratch elements (complex) per solve behind SolveDesc::work: work, pot, wacc, xs (2N).
+// Scratch per solve behind SolveDesc::work: work, pot, wacc and the two halves of xs, each
+// work_stride elements (complex) long: the positions t + iT (i < live elements) that the
+// threads of every layout touch, P/2 for chirp-z and direct sine plans, P (= Nz) for direct
+// periodic ones; at least Nz.  The per-position loops of the Neumann terms then access this
+// scratch without a bounds test (positions >= Nz hold values that are never used), which
+// keeps them free of branches, so that their memory accesses overlap.
 constexpr int kWorkPerSolve = 5;
+__host__ __device__ inline size_t work_stride(int P, int direct) {
+    return direct == 1 ? static_cast<size_t>(P) : static_cast<size_t>(P) / 2;
+}
 inline void set_work(SolveDesc &d, float2 *base) {
+    const size_t S = work_stride(d.P, d.direct);
     d.work = base;
-    d.pot = base + d.N;
-    d.wacc = base + 2 * static_cast<size_t>(d.N);
-    d.xs = base + 3 * static_cast<size_t>(d.N);
+    d.pot = base + S;
+    d.wacc = base + 2 * S;
+    d.xs = base + 3 * S;
 }
 
 hipError_t launch_march(int P, int variant, int direct, const SolveDesc *d_descs, int nsolves, int nsteps,

@@ -719,13 +719,15 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
         float4 wt[NW];
 #pragma unroll
         for (int k2 = 0; k2 < NW; ++k2) wt[k2] = ld4(d.twist, opaque_tid() + k2 * T);
+        // (the keep scratch is two halves of H positions, one per thread position t + i T:
+        // its accesses need no bounds test, and positions >= N carry zeros or unused values)
 #pragma unroll
         for (int i = 0; i < RT; ++i) {
             const int pos = opaque_tid() + i * T;
-            float2 v = make_float2(0.f, 0.f);
-            if (pos < N) v = mulw<Q, false>(cmul_df(x[i], wt[i % NW]), i / NW);
+            const float2 tv = mulw<Q, false>(cmul_df(x[i], wt[i % NW]), i / NW);
+            const float2 v = pos < N ? tv : make_float2(0.f, 0.f);
             if constexpr (KEEP_GLOBAL) {
-                if (pos < N) st2(keep, pos, v);
+                st2(keep, pos, v);
             } else {
                 y[i] = v;
             }
@@ -735,15 +737,16 @@ __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBu
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T;
-                if (pos < N) st2(keep + N, pos, x[i]);
-                x[i] = pos < N ? ld2(keep, pos) : make_float2(0.f, 0.f);
+                st2(keep + H, pos, x[i]);
+                x[i] = ld2(keep, pos);  // zero at positions >= N
             }
             chirp_core<EK, true>(x, L, tw, KWin{k.k1 + H, nullptr, k.kph, k.sg, k.hs});
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int pos = opaque_tid() + i * T;
-                x[i] = pos < N ? cadd(ld2(keep + N, pos), mulw<Q, true>(cmul_df_conj(x[i], wt[i % NW]), i / NW))
-                               : make_float2(0.f, 0.f);
+                const float2 e = ld2(keep + H, pos);
+                const float2 z = cadd(e, mulw<Q, true>(cmul_df_conj(x[i], wt[i % NW]), i / NW));
+                x[i] = pos < N ? z : make_float2(0.f, 0.f);
             }
         } else {
             chirp_core<EK, true>(y, L, tw, KWin{k.k1 + H, nullptr, k.kph, k.sg, k.hs});
@@ -986,30 +989,50 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                         if constexpr (kAInRegs) {
                             a[i] = cmul(A[i], a[i]);
                         } else {
+                            // pot spans the work stride: no bounds test on the load
                             const int pos = opaque_tid() + i * T;
-                            a[i] = (pos < N) ? cmul(ld2(d.pot, pos), a[i]) : make_float2(0.f, 0.f);
+                            const float2 pv = ld2(d.pot, pos);
+                            a[i] = (pos < N) ? cmul(pv, a[i]) : make_float2(0.f, 0.f);
                         }
                     }
                     continue;
                 }
                 float tnf = 0.f, wpf = 0.f;
+                // groups of G positions: the group's loads are issued before its stores, so
+                // that they overlap (a load cannot move above a store to a buffer that the
+                // compiler cannot tell apart from the one it reads)
+                constexpr int G = RL < 4 ? RL : 4;
 #pragma unroll
-                for (int i = 0; i < RL; ++i) {
-                    const int pos = opaque_tid() + i * T;
-                    float4 bm;
-                    if constexpr (kBInRegs) bm = Bm[i];
-                    else bm = (pos < N) ? ld4(d.bmul, j * N + pos)
-                                                     : make_float4(0.f, 0.f, 0.f, 0.f);
-                    a[i] = cmul_df(a[i], bm);
-                    tnf += cnorm2(a[i]);
-                    // w' += a_m (the first term m = 1 starts it)
-                    if constexpr (kWInRegs) {
-                        w[i] = h == 1 ? a[i] : cadd(w[i], a[i]);
-                        wpf += cnorm2(w[i]);
-                    } else if (pos < N) {
-                        const float2 ws = h == 1 ? a[i] : cadd(ld2(d.wacc, pos), a[i]);
-                        st2(d.wacc, pos, ws);
-                        wpf += cnorm2(ws);
+                for (int g = 0; g < RL; g += G) {
+                    float4 bm[G];
+                    float2 wo[G];
+#pragma unroll
+                    for (int k2 = 0; k2 < G; ++k2) {
+                        const int pos = opaque_tid() + (g + k2) * T;
+                        // the table row has N entries: a clamped position, the product selected
+                        if constexpr (!kBInRegs) bm[k2] = ld4(d.bmul, j * N + (pos < N ? pos : N - 1));
+                        // wacc spans the work stride; beyond N it accumulates zeros
+                        if constexpr (!kWInRegs) wo[k2] = h == 1 ? make_float2(0.f, 0.f) : ld2(d.wacc, pos);
+                    }
+#pragma unroll
+                    for (int k2 = 0; k2 < G; ++k2) {
+                        const int i = g + k2, pos = opaque_tid() + i * T;
+                        if constexpr (kBInRegs) {
+                            a[i] = cmul_df(a[i], Bm[i]);  // zero beyond N
+                        } else {
+                            const float2 ab = cmul_df(a[i], bm[k2]);
+                            a[i] = pos < N ? ab : make_float2(0.f, 0.f);
+                        }
+                        tnf += cnorm2(a[i]);
+                        // w' += a_m (the first term m = 1 starts it)
+                        if constexpr (kWInRegs) {
+                            w[i] = h == 1 ? a[i] : cadd(w[i], a[i]);
+                            wpf += cnorm2(w[i]);
+                        } else {
+                            const float2 ws = cadd(wo[k2], a[i]);
+                            st2(d.wacc, pos, ws);
+                            wpf += cnorm2(ws);
+                        }
                     }
                 }
                 tn = tnf;
@@ -1029,13 +1052,27 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                 const double ub = sqrt(t0) + sqrt(wp);
                 if (h + 1 < 2 * nmax && tn > d.tol2 * ub * ub * (1.0 + 1e-4)) continue;
                 float wnf = 0.f;
+                // a0 = s_j (.) u again, from the factor's input state; loads at clamped
+                // positions (the state and the table have N entries) in pairs, terms selected
+                constexpr int G2 = RL < 2 ? RL : 2;
 #pragma unroll
-                for (int i = 0; i < RL; ++i) {
-                    const int pos = opaque_tid() + i * T;
-                    if (pos < N) {
-                        // a0 = s_j (.) u again, from the factor's input state
-                        const float2 a0v = cmul_df(kUInRegs ? u[i] : ld2(cur, pos), ld4(d.s, j * N + pos));
-                        wnf += cnorm2(cadd(a0v, kWInRegs ? w[i] : ld2(d.wacc, pos)));
+                for (int g = 0; g < RL; g += G2) {
+                    float2 uc[G2], wv[G2];
+                    float4 sv[G2];
+#pragma unroll
+                    for (int k2 = 0; k2 < G2; ++k2) {
+                        const int i = g + k2, pos = opaque_tid() + i * T, pc = pos < N ? pos : N - 1;
+                        if constexpr (kUInRegs) uc[k2] = u[i];
+                        else uc[k2] = ld2(cur, pc);
+                        sv[k2] = ld4(d.s, j * N + pc);
+                        if constexpr (kWInRegs) wv[k2] = w[i];
+                        else wv[k2] = ld2(d.wacc, pos);
+                    }
+#pragma unroll
+                    for (int k2 = 0; k2 < G2; ++k2) {
+                        const int pos = opaque_tid() + (g + k2) * T;
+                        const float e = cnorm2(cadd(cmul_df(uc[k2], sv[k2]), wv[k2]));
+                        wnf += pos < N ? e : 0.f;
                     }
                 }
                 wn = wnf;

@@ -108,7 +108,7 @@ def plan_device_bytes(nz: int, pade_order: int, out_rows: int) -> int:
     tables = (8 * P + 16 * (64 + P // 64) if P > 16384 else 2 * 8 * P) + 12 * (PE // 8 + 1) + 3 * 8 * nz + 3 * 16 * pade_order * nz + 16 * pade_order
     if P > 16384:
         tables += 16 * (P // 2)
-    state = 4 * nz + 8 * nz + 5 * 8 * nz + 8 + 48 + 512
+    state = 4 * nz + 8 * nz + 5 * 8 * (P // 2) + 8 + 48 + 512   # work stride P/2 (>= nz)
     staging = 12 * nz * max(out_rows, 1)
     return tables + state + staging
 
