@@ -51,12 +51,12 @@ PEAK_HBM = 8.0e12      # MI355X HBM3E (B/s)
 # fingerprint of the kernel sources and layout table: any change to their code (comments
 # aside) makes the figure stale, and it is then reported as null.
 TRAFFIC = {
-    ("broadband", 32768, 150, 40): {"fingerprint": "33ac4eeccc09bd85", "fetch": 5.5951e11,
-                                    "write": 2.3548e11},
-    ("munk4096", 4096, 512, 100): {"fingerprint": "33ac4eeccc09bd85", "fetch": 3.0071e7,
-                                   "write": 1.6500e9},
-    ("eddy16384", 16384, 256, 50): {"fingerprint": "33ac4eeccc09bd85", "fetch": 8.6894e11,
-                                    "write": 5.8745e11},
+    ("broadband", 32768, 150, 40): {"fingerprint": "d1c4eee860e3566b", "fetch": 5.5730e+11,
+                                    "write": 2.3520e+11},
+    ("munk4096", 4096, 512, 100): {"fingerprint": "d1c4eee860e3566b", "fetch": 3.1452e+07,
+                                   "write": 1.7597e+09},
+    ("eddy16384", 16384, 256, 50): {"fingerprint": "d1c4eee860e3566b", "fetch": 8.7109e+11,
+                                    "write": 5.8745e+11},
 }
 
 

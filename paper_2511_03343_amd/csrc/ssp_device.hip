@@ -998,37 +998,47 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                     continue;
                 }
                 float tnf = 0.f, wpf = 0.f;
-                // groups of G positions: the group's loads are issued before its stores, so
-                // that they overlap (a load cannot move above a store to a buffer that the
-                // compiler cannot tell apart from the one it reads)
-                constexpr int G = RL < 4 ? RL : 4;
+                if constexpr (kWInRegs) {
 #pragma unroll
-                for (int g = 0; g < RL; g += G) {
-                    float4 bm[G];
-                    float2 wo[G];
-#pragma unroll
-                    for (int k2 = 0; k2 < G; ++k2) {
-                        const int pos = opaque_tid() + (g + k2) * T;
-                        // the table row has N entries: a clamped position, the product selected
-                        if constexpr (!kBInRegs) bm[k2] = ld4(d.bmul, j * N + (pos < N ? pos : N - 1));
-                        // wacc spans the work stride; beyond N it accumulates zeros
-                        if constexpr (!kWInRegs) wo[k2] = h == 1 ? make_float2(0.f, 0.f) : ld2(d.wacc, pos);
-                    }
-#pragma unroll
-                    for (int k2 = 0; k2 < G; ++k2) {
-                        const int i = g + k2, pos = opaque_tid() + i * T;
-                        if constexpr (kBInRegs) {
-                            a[i] = cmul_df(a[i], Bm[i]);  // zero beyond N
-                        } else {
-                            const float2 ab = cmul_df(a[i], bm[k2]);
-                            a[i] = pos < N ? ab : make_float2(0.f, 0.f);
-                        }
+                    for (int i = 0; i < RL; ++i) {
+                        const int pos = opaque_tid() + i * T;
+                        float4 bm;
+                        if constexpr (kBInRegs) bm = Bm[i];
+                        else bm = (pos < N) ? ld4(d.bmul, j * N + pos) : make_float4(0.f, 0.f, 0.f, 0.f);
+                        a[i] = cmul_df(a[i], bm);
                         tnf += cnorm2(a[i]);
                         // w' += a_m (the first term m = 1 starts it)
-                        if constexpr (kWInRegs) {
-                            w[i] = h == 1 ? a[i] : cadd(w[i], a[i]);
-                            wpf += cnorm2(w[i]);
-                        } else {
+                        w[i] = h == 1 ? a[i] : cadd(w[i], a[i]);
+                        wpf += cnorm2(w[i]);
+                    }
+                } else {
+                    // the series sum goes through wacc, which spans the work stride: groups of
+                    // G positions without a bounds test on wacc, whose loads are issued before
+                    // the group's stores so that they overlap (a load cannot move above a store
+                    // to a buffer that the compiler cannot tell apart from the one it reads);
+                    // the multiplier row has N entries: a clamped position, the product selected
+                    constexpr int G = RL < 4 ? RL : 4;
+#pragma unroll
+                    for (int g = 0; g < RL; g += G) {
+                        float4 bm[G];
+                        float2 wo[G];
+#pragma unroll
+                        for (int k2 = 0; k2 < G; ++k2) {
+                            const int pos = opaque_tid() + (g + k2) * T;
+                            if constexpr (!kBInRegs) bm[k2] = ld4(d.bmul, j * N + (pos < N ? pos : N - 1));
+                            wo[k2] = h == 1 ? make_float2(0.f, 0.f) : ld2(d.wacc, pos);
+                        }
+#pragma unroll
+                        for (int k2 = 0; k2 < G; ++k2) {
+                            const int i = g + k2, pos = opaque_tid() + i * T;
+                            if constexpr (kBInRegs) {
+                                a[i] = cmul_df(a[i], Bm[i]);  // zero beyond N
+                            } else {
+                                const float2 ab = cmul_df(a[i], bm[k2]);
+                                a[i] = pos < N ? ab : make_float2(0.f, 0.f);
+                            }
+                            tnf += cnorm2(a[i]);
+                            // w' += a_m (the first term m = 1 starts it; beyond N it sums zeros)
                             const float2 ws = cadd(wo[k2], a[i]);
                             st2(d.wacc, pos, ws);
                             wpf += cnorm2(ws);
@@ -1052,27 +1062,39 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
                 const double ub = sqrt(t0) + sqrt(wp);
                 if (h + 1 < 2 * nmax && tn > d.tol2 * ub * ub * (1.0 + 1e-4)) continue;
                 float wnf = 0.f;
-                // a0 = s_j (.) u again, from the factor's input state; loads at clamped
-                // positions (the state and the table have N entries) in pairs, terms selected
-                constexpr int G2 = RL < 2 ? RL : 2;
+                if constexpr (kWInRegs) {
 #pragma unroll
-                for (int g = 0; g < RL; g += G2) {
-                    float2 uc[G2], wv[G2];
-                    float4 sv[G2];
-#pragma unroll
-                    for (int k2 = 0; k2 < G2; ++k2) {
-                        const int i = g + k2, pos = opaque_tid() + i * T, pc = pos < N ? pos : N - 1;
-                        if constexpr (kUInRegs) uc[k2] = u[i];
-                        else uc[k2] = ld2(cur, pc);
-                        sv[k2] = ld4(d.s, j * N + pc);
-                        if constexpr (kWInRegs) wv[k2] = w[i];
-                        else wv[k2] = ld2(d.wacc, pos);
+                    for (int i = 0; i < RL; ++i) {
+                        const int pos = opaque_tid() + i * T;
+                        if (pos < N) {
+                            // a0 = s_j (.) u again, from the factor's input state
+                            const float2 a0v = cmul_df(kUInRegs ? u[i] : ld2(cur, pos), ld4(d.s, j * N + pos));
+                            wnf += cnorm2(cadd(a0v, w[i]));
+                        }
                     }
+                } else {
+                    // a0 = s_j (.) u again, from the factor's input state; loads at clamped
+                    // positions (the state and the table have N entries) in pairs, terms
+                    // selected
+                    constexpr int G2 = RL < 2 ? RL : 2;
 #pragma unroll
-                    for (int k2 = 0; k2 < G2; ++k2) {
-                        const int pos = opaque_tid() + (g + k2) * T;
-                        const float e = cnorm2(cadd(cmul_df(uc[k2], sv[k2]), wv[k2]));
-                        wnf += pos < N ? e : 0.f;
+                    for (int g = 0; g < RL; g += G2) {
+                        float2 uc[G2], wv[G2];
+                        float4 sv[G2];
+#pragma unroll
+                        for (int k2 = 0; k2 < G2; ++k2) {
+                            const int i = g + k2, pos = opaque_tid() + i * T, pc = pos < N ? pos : N - 1;
+                            if constexpr (kUInRegs) uc[k2] = u[i];
+                            else uc[k2] = ld2(cur, pc);
+                            sv[k2] = ld4(d.s, j * N + pc);
+                            wv[k2] = ld2(d.wacc, pos);
+                        }
+#pragma unroll
+                        for (int k2 = 0; k2 < G2; ++k2) {
+                            const int pos = opaque_tid() + (g + k2) * T;
+                            const float e = cnorm2(cadd(cmul_df(uc[k2], sv[k2]), wv[k2]));
+                            wnf += pos < N ? e : 0.f;
+                        }
                     }
                 }
                 wn = wnf;
