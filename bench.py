@@ -51,11 +51,11 @@ PEAK_HBM = 8.0e12      # MI355X HBM3E (B/s)
 # fingerprint of the kernel sources and layout table: any change to their code (comments
 # aside) makes the figure stale, and it is then reported as null.
 TRAFFIC = {
-    ("broadband", 32768, 150, 40): {"fingerprint": "d1c4eee860e3566b", "fetch": 5.5730e+11,
-                                    "write": 2.3520e+11},
-    ("munk4096", 4096, 512, 100): {"fingerprint": "d1c4eee860e3566b", "fetch": 3.1452e+07,
-                                   "write": 1.7597e+09},
-    ("eddy16384", 16384, 256, 50): {"fingerprint": "d1c4eee860e3566b", "fetch": 8.7109e+11,
+    ("broadband", 32768, 150, 40): {"fingerprint": "c910d553603787a2", "fetch": 5.5848e+11,
+                                    "write": 2.3530e+11},
+    ("munk4096", 4096, 512, 100): {"fingerprint": "c910d553603787a2", "fetch": 3.0074e+07,
+                                   "write": 1.6567e+09},
+    ("eddy16384", 16384, 256, 50): {"fingerprint": "c910d553603787a2", "fetch": 8.7358e+11,
                                     "write": 5.8745e+11},
 }
 

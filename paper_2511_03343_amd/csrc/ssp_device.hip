@@ -957,11 +957,18 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
 #pragma unroll
             for (int i = 0; i < RL; ++i) {
                 const int pos = opaque_tid() + i * T, m = pos;
-                if (pos < N) {
-                    float2 uc;
-                    if constexpr (kUInRegs) uc = u[i];
-                    else uc = ld2(cur, m);
-                    a[i] = cmul_df(uc, ld4(d.s, j * N + m));
+                if constexpr (kUInRegs) {
+                    // no stores in this loop: tables at a clamped position, values selected,
+                    // so that the loads overlap
+                    const int pc = pos < N ? pos : N - 1;
+                    const float2 av = cmul_df(u[i], ld4(d.s, j * N + pc));
+                    a[i] = pos < N ? av : make_float2(0.f, 0.f);
+                    if constexpr (kBInRegs) {
+                        const float4 bv = ld4(d.bmul, j * N + pc);
+                        Bm[i] = pos < N ? bv : make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+                } else if (pos < N) {
+                    a[i] = cmul_df(ld2(cur, m), ld4(d.s, j * N + m));
                     if constexpr (kBInRegs) Bm[i] = ld4(d.bmul, j * N + m);
                 } else {
                     a[i] = make_float2(0.f, 0.f);
@@ -1002,10 +1009,14 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
 #pragma unroll
                     for (int i = 0; i < RL; ++i) {
                         const int pos = opaque_tid() + i * T;
-                        float4 bm;
-                        if constexpr (kBInRegs) bm = Bm[i];
-                        else bm = (pos < N) ? ld4(d.bmul, j * N + pos) : make_float4(0.f, 0.f, 0.f, 0.f);
-                        a[i] = cmul_df(a[i], bm);
+                        if constexpr (kBInRegs) {
+                            a[i] = cmul_df(a[i], Bm[i]);  // zero beyond N
+                        } else {
+                            // clamped position, product selected: no branch around the load
+                            const float4 bm = ld4(d.bmul, j * N + (pos < N ? pos : N - 1));
+                            const float2 ab = cmul_df(a[i], bm);
+                            a[i] = pos < N ? ab : make_float2(0.f, 0.f);
+                        }
                         tnf += cnorm2(a[i]);
                         // w' += a_m (the first term m = 1 starts it)
                         w[i] = h == 1 ? a[i] : cadd(w[i], a[i]);
@@ -1129,7 +1140,13 @@ __device__ __forceinline__ void march_body(const SolveDesc &d, int nsteps, float
 #pragma unroll
             for (int i = 0; i < RL; ++i) {
                 const int pos = opaque_tid() + i * T, m = pos;
-                if (pos < N) {
+                if constexpr (kUInRegs && kWInRegs) {
+                    // registers only besides the table: clamped position, value selected
+                    const float2 uc = u[i];
+                    const float4 q = ld4(d.qmul, j * N + (pos < N ? pos : N - 1));
+                    const float2 un = cadd(uc, cadd(cmul_df(uc, q), cmul_df(w[i], be)));
+                    u[i] = pos < N ? un : uc;
+                } else if (pos < N) {
                     const float2 ws = kWInRegs ? w[i] : (used > 0 ? ld2(d.wacc, m) : make_float2(0.f, 0.f));
                     const float2 uc = kUInRegs ? u[i] : ld2(cur, m);
                     const float2 un = cadd(uc, cadd(cmul_df(uc, ld4(d.qmul, j * N + m)), cmul_df(ws, be)));
