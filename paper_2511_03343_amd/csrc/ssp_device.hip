@@ -693,11 +693,13 @@ __device__ __forceinline__ void sine_core(float2 (&x)[Cfg<EK>::RT], const LdsBuf
 }
 
 // One transform core for convolution length P (positions 0 .. eng_len-1 distributed as in
-// the engine), with the chirp-window spectra k of the direction it runs in.  For P above kMaxEngine the odd-frequency half needs the input again after the
-// even half has overwritten x: KEEP_GLOBAL keeps it (and the even result) in the solve's
-// scratch keep[0 .. 2N), else in registers.  Both give identical results.  Positions >= N
-// of the input must be zero.  Output: split lengths return zero at positions >= N; unsplit
-// lengths return zero at positions >= P/2 and values without meaning in [N, P/2).
+// the engine), with the chirp-window spectra k of the direction it runs in.  For P above
+// kMaxEngine the odd-frequency half needs the input again after the even half has
+// overwritten x: KEEP_GLOBAL keeps it (and the even result) in the solve's scratch
+// keep[0 .. 2H) (H = P/2 positions per half), else in registers.  Both give identical
+// results.  Positions >= N of the input must be zero.  Output: split lengths return zero at
+// positions >= N; unsplit lengths return zero at positions >= P/2 and values without meaning
+// in [N, P/2).
 template <int P, int V, bool KEEP_GLOBAL, int EKEY = eng_key<P, V>()>
 __device__ __forceinline__ void dst_core(float2 (&x)[Cfg<EKEY>::RT], const LdsBufs &L,
                                          const Twiddles<EKEY> &tw, const SolveDesc &d, float2 *keep,
