@@ -66,3 +66,14 @@ def test_algorithmic_flops_count():
     tr = 5 * nz * math.log2(nz)
     want = terms * 2 * (tr + 8 * nz) + steps * p * 16 * nz + outputs * tr
     assert bench.algorithmic_flops(nz, p, terms, steps, outputs) == want
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    # every solve is independent; the benchmark measures one GPU and says so for N > 1
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(bench.ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout.strip() == ""
