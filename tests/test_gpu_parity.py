@@ -164,7 +164,9 @@ def test_homogeneous_waveguide(ssp, gpu):
     compare("homogeneous", fld, tl, ref)
 
 
-@pytest.mark.parametrize("nz,nsteps", [(2, 50), (3, 50), (127, 200), (511, 400), (1000, 100), (9000, 12)])
+# 8192: the largest grid with one FFT per transform; 8193: the smallest with split transforms
+@pytest.mark.parametrize("nz,nsteps", [(2, 50), (3, 50), (127, 200), (511, 400), (1000, 100), (8192, 10),
+                                      (8193, 10), (9000, 12)])
 def test_munk_small(ssp, gpu, nz, nsteps):
     s = W.munk_deep(nsteps=nsteps, nz=nz)
     # on the coarsest grids the source Gaussian falls between grid points: use a seeded

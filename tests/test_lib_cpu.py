@@ -51,6 +51,7 @@ def test_host_pade_rejects_bad_order(ssp):
     ((64, 100.0, 50.0, 1500.0, 5.0, 4, -1, 1e-10), -1),
     ((64, 100.0, 50.0, 1500.0, 5.0, 4, 8, 0.0), -1),
     ((10 ** 6, 100.0, 50.0, 1500.0, 5.0, 4, 8, 1e-10), -7),
+    ((16385, 5000.0, 50.0, 1500.0, 25.0, 6, 48, 1e-10), -7),   # one above the largest grid
 ])
 def test_plan_create_validates_before_touching_the_device(ssp, args, status):
     with pytest.raises(ssp.SspError) as e:
