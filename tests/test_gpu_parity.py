@@ -184,6 +184,31 @@ def test_munk_small(ssp, gpu, nz, nsteps):
     assert abs(stats["neumann_terms"] - int(ref.iterations.sum())) <= 0.01 * ref.iterations.sum() + 2
 
 
+def test_empty_inputs_and_zero_steps(ssp, gpu):
+    # zero vectors or zero plans are refused before any device work; a march of zero steps
+    # returns no rows and leaves the state as it was: the march that follows it equals a
+    # march from the freshly installed starter, bitwise
+    torch = gpu
+    s = W.munk_deep(nsteps=12, nz=1000)
+    pl = make_plan(ssp, s)
+    try:
+        d = torch.zeros((1, s.nz), dtype=torch.complex64, device="cuda")
+        for call in (lambda: ssp.ssp_dst_device(pl, 0, d.data_ptr(), d.data_ptr()),
+                     lambda: ssp.ssp_march_batch([], [], 4)):
+            with pytest.raises(ssp.SspError) as e:
+                call()
+            assert e.value.status == ssp.SSP_E_INVAL
+        st0, f0, t0, stats0 = ssp.ssp_march(pl, s.nz, s.starter(), 0)
+        assert st0 == OK and f0.shape == (0, s.nz) and t0.shape == (0, s.nz)
+        assert stats0["steps_done"] == 0 and stats0["neumann_terms"] == 0
+        st1, f1, t1, _ = ssp.ssp_march(pl, s.nz, None, s.nsteps)
+        st2, f2, t2, _ = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    assert st1 == OK and st2 == OK and f1.shape[0] > 0
+    assert np.array_equal(f1, f2) and np.array_equal(t1, t2)
+
+
 def test_munk_full_size_start(ssp, gpu):
     # deep Munk waveguide at its full size (Nz = 4096) for the first 24 steps
     s = W.munk_deep(nsteps=24)
