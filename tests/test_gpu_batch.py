@@ -62,6 +62,36 @@ def test_async_batch_equals_host_batch_and_graph_replays(ssp, gpu):
             ssp.ssp_plan_destroy(pl)
 
 
+def test_batch_members_with_zero_steps(ssp, gpu):
+    # a member given zero steps marches nothing (no rows, statistics of zero steps, its state
+    # unchanged) while the other members of the same launches march as they would alone
+    solves = _uneven_solves()
+    steps = [0, 6, 0, 4]
+    nz = [s.nz for s in solves]
+    plans = [make_plan(ssp, s) for s in solves]
+    alone = [make_plan(ssp, s) for s in solves]
+    try:
+        for a, b, s in zip(plans, alone, solves):
+            ssp.ssp_set_field(a, s.starter(), s.nz)
+            ssp.ssp_set_field(b, s.starter(), s.nz)
+        before = [ssp.ssp_get_field(a, s.nz) for a, s in zip(plans, solves)]
+        st, fl, tl, stats = ssp.ssp_march_batch_steps(plans, nz, steps)
+        assert st >= 0  # (a factor's series may stop at the term cap: a warning)
+        for a, b, s, k, f, t, x, f0 in zip(plans, alone, solves, steps, fl, tl, stats, before):
+            _report(f"zero-step batch nz={s.nz}", steps=k, rows=f.shape[0], terms=x["neumann_terms"])
+            if k == 0:
+                assert f.shape[0] == 0 and t.shape[0] == 0
+                assert x["steps_done"] == 0 and x["neumann_terms"] == 0
+                assert np.array_equal(ssp.ssp_get_field(a, s.nz), f0)
+            else:
+                st1, f1, t1, x1 = ssp.ssp_march(b, s.nz, None, k)
+                assert st1 == x["status"] and x["steps_done"] == k and x == x1
+                assert f.shape[0] > 0 and np.array_equal(f, f1) and np.array_equal(t, t1)
+    finally:
+        for pl in plans + alone:
+            ssp.ssp_plan_destroy(pl)
+
+
 def test_async_batch_uneven_steps_vs_oracle(ssp, gpu):
     # a step count per plan, against the oracle
     torch = gpu
