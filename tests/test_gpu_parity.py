@@ -316,13 +316,48 @@ def test_divergence_reported_and_field_kept(ssp, gpu):
     assert np.linalg.norm(back - s.starter()) / np.linalg.norm(s.starter()) < 2e-6
 
 
+@pytest.mark.parametrize("p", [1, 2, 12])
+def test_pade_order_extremes_vs_oracle(ssp, gpu, p):
+    # the smallest approximant ([1/1]) and the largest order a plan accepts ([12/12]), on a
+    # 200 Hz Munk channel (H = 1000 m, Nz = 1000, dr = 20 m) where every factor's series
+    # converges
+    s = W.munk_deep(nsteps=40, nz=1000)
+    s.pade_order, s.freq, s.dr, s.depth, s.zs = p, 200.0, 20.0, 1000.0, 200.0
+    pl = make_plan(ssp, s)
+    try:
+        st, fld, tl, stats = ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert ref.status == OK and st == OK and stats["steps_done"] == s.nsteps
+    compare(f"pade [{p}/{p}]", fld, tl, ref)
+    assert abs(stats["neumann_terms"] - int(ref.iterations.sum())) <= 0.01 * ref.iterations.sum() + 2
+
+
+def test_high_order_divergence_matches_oracle(ssp, gpu):
+    # on the 50 Hz Munk channel at Nz = 1000 the series of a [12/12] factor diverges in the
+    # first step: the device reports it there and keeps the starter, as the oracle stops
+    s = W.munk_deep(nsteps=5, nz=1000)
+    s.pade_order = 12
+    pl = make_plan(ssp, s)
+    try:
+        with pytest.raises(ssp.SspError) as e:
+            ssp.ssp_march(pl, s.nz, s.starter(), s.nsteps)
+        assert e.value.status == ssp.SSP_E_DIVERGED
+        back = ssp.ssp_get_field(pl, s.nz)
+    finally:
+        ssp.ssp_plan_destroy(pl)
+    ref = oracle_march(s)
+    assert ref.status == DIVERGED and ref.steps_done == 0
+    assert np.linalg.norm(back - s.starter()) / np.linalg.norm(s.starter()) < 2e-6
+
+
 @pytest.mark.parametrize("nz", [500, 4096])
 def test_divergence_after_unwritten_steps(ssp, gpu, nz):
-    # layouts that keep the state in registers write it back every 64 steps and at the end
-    # of a launch: a step that diverges after unwritten steps (here step 5, where a slow
-    # layer enters the tabulated profile) reloads the written state and marches those steps
-    # again, so the field is the state after the last good step, bitwise equal to a march
-    # that stops there, and the oracle stops at the same step
+    # the field is written back after every step (the recovery point): a step that diverges
+    # after good steps (here step 5, where a slow layer enters the tabulated profile) leaves
+    # the state after the last good step, bitwise equal to a march that stops there, and the
+    # oracle stops at the same step
     s = W.munk_deep(nsteps=8, nz=nz)
     z = (np.arange(nz) + 1) * s.depth / (nz + 1)
     c = np.repeat(s.profile()[0][None, :], 8, axis=0)
