@@ -419,6 +419,25 @@ def test_resume_is_bitwise(ssp, gpu):
     assert np.array_equal(f_all, np.concatenate([f1, f2]))
 
 
+def test_resume_in_ragged_chunks_is_bitwise(ssp, gpu):
+    # outputs fall on the multiples of out_every after the start: chunks of 3, 4 and 13 steps
+    # with out_every = 5 give 0, 1 and 3 rows, together those of one 20-step march
+    s = W.munk_deep(nsteps=20, nz=700)
+    s.out_every = 5
+    a = make_plan(ssp, s)
+    b = make_plan(ssp, s)
+    try:
+        _, f_all, t_all, _ = ssp.ssp_march(a, s.nz, s.starter(), 20)
+        parts = [ssp.ssp_march(b, s.nz, s.starter() if i == 0 else None, k) for i, k in enumerate((3, 4, 13))]
+    finally:
+        ssp.ssp_plan_destroy(a)
+        ssp.ssp_plan_destroy(b)
+    assert [p[1].shape[0] for p in parts] == [0, 1, 3] and f_all.shape[0] == 4
+    assert [p[3]["step_index"] for p in parts] == [3, 7, 20]
+    assert np.array_equal(f_all, np.concatenate([p[1] for p in parts]))
+    assert np.array_equal(t_all, np.concatenate([p[2] for p in parts]))
+
+
 def test_batch_equals_alone_bitwise(ssp, gpu):
     sizes = [(300, 500.0), (777, 1500.0), (2000, 1000.0), (511, 100.0)]
     solves = [W.munk_deep(nsteps=16, nz=nz, zs=zs) for nz, zs in sizes]
